@@ -1,0 +1,253 @@
+"""Pins for the CPU oracle: values the paper prints, closed forms, invariants, brute force.
+
+Every check here compares the oracle with something other than itself, so a
+plausible slip in it (a dropped term, a wrong sign or index, a transposed
+operand, a reversed product) fails at least one test.
+"""
+import cmath
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fsv, gates as OG, metrics, unitary as UA
+from paper_2305_14398_amd import workloads as W
+from tests import golden_io
+
+TOL = 1e-12
+
+
+# --- Table 1, Eq. 6 and gate identities ---------------------------------------------------
+
+def test_table1_printed_matrices():
+    table = golden_io.load_table1()
+    for name in ("H", "X", "Y", "Z"):
+        np.testing.assert_allclose(OG.one_qubit(name), table[name](), atol=TOL)
+    for phi in (0.0, 0.3, math.pi / 2, math.pi, 5.1):
+        np.testing.assert_allclose(OG.one_qubit("R", phi), table["R"](phi), atol=TOL)
+
+
+def test_eq6_pauli_x_swaps_amplitudes():
+    a, b = 0.6 + 0.1j, -0.2 + 0.77j
+    np.testing.assert_allclose(OG.one_qubit("X") @ np.array([a, b]), [b, a], atol=TOL)
+
+
+def test_gate_identities():
+    H, X, Y, Z, S, T = (OG.one_qubit(g) for g in "HXYZST")
+    np.testing.assert_allclose(S @ S, Z, atol=TOL)
+    np.testing.assert_allclose(T @ T, S, atol=TOL)
+    np.testing.assert_allclose(H @ X @ H, Z, atol=TOL)
+    np.testing.assert_allclose(H @ Z @ H, X, atol=TOL)
+    np.testing.assert_allclose(S, OG.one_qubit("R", math.pi / 2), atol=TOL)
+    np.testing.assert_allclose(T, OG.one_qubit("R", math.pi / 4), atol=TOL)
+    np.testing.assert_allclose(OG.one_qubit("RX", math.pi), -1j * X, atol=TOL)
+    np.testing.assert_allclose(OG.one_qubit("RY", math.pi), -1j * Y, atol=TOL)
+    for th in (0.1, 1.3, 2.9, 4.4):
+        np.testing.assert_allclose(OG.one_qubit("RZ", th), cmath.exp(-0.5j * th) * OG.one_qubit("R", th), atol=TOL)
+        np.testing.assert_allclose(OG.one_qubit("RX", th), H @ OG.one_qubit("RZ", th) @ H, atol=TOL)
+        # RY(a) RY(b) = RY(a + b): rotations compose additively
+        np.testing.assert_allclose(OG.one_qubit("RY", th) @ OG.one_qubit("RY", 0.7), OG.one_qubit("RY", th + 0.7), atol=TOL)
+    for name in ("H", "X", "Y", "Z", "S", "T"):
+        m = OG.one_qubit(name)
+        np.testing.assert_allclose(m.conj().T @ m, np.eye(2), atol=TOL)
+
+
+# --- worked example of Section 2.4 (Eq. 7, 9s1, 10, 11) ------------------------------------
+
+@pytest.mark.parametrize("fixture", ["eq9s1_step1_h_kron_i.txt", "eq10_step2_cnot.txt", "eq7_controlled_u.txt"])
+def test_printed_step_matrices(fixture):
+    fx = golden_io.load(fixture)
+    n, g = fx["qubits"], fx["gates"]
+    np.testing.assert_allclose(UA.step_operator(n, g), fx["matrix"], atol=TOL)
+    np.testing.assert_allclose(fsv.circuit_unitary(n, g), fx["matrix"], atol=TOL)
+
+
+def test_eq11_bell_state():
+    fx = golden_io.load("eq11_bell_state.txt")
+    psi = UA.simulate_full_state(fx["qubits"], fx["gates"])
+    np.testing.assert_allclose(psi, fx["state"], atol=TOL)
+    # the same vector for H(0), CNOT(0 -> 1) in little-endian order (Listing 'belltornado')
+    psi2 = UA.simulate_full_state(2, W.gate_tuples(W.bell()))
+    np.testing.assert_allclose(psi2, fx["state"], atol=TOL)
+    np.testing.assert_allclose(UA.initial_state(2), [1, 0, 0, 0], atol=0)
+
+
+# --- brute force: per-element definition of the tensor product, n <= 3 ----------------------
+
+def _bit(x, q):
+    return (x >> q) & 1
+
+
+def brute_step(n, step):
+    """S[r][s] from the definition of the Kronecker product on basis indices."""
+    N = 1 << n
+    busy = set()
+    for g in step:
+        lo, hi = min(g[1]), max(g[1])
+        busy.update(g[1])
+    S = np.zeros((N, N), dtype=np.complex128)
+    for r in range(N):
+        for s in range(N):
+            v = 1.0 + 0j
+            for q in range(n):
+                if q not in busy and _bit(r, q) != _bit(s, q):
+                    v = 0
+            for name, qs, th in step:
+                if len(qs) == 1:
+                    v *= OG.one_qubit(name, th)[_bit(r, qs[0]), _bit(s, qs[0])]
+                elif name == "SWAP":
+                    a, b = qs
+                    v *= float(_bit(r, a) == _bit(s, b) and _bit(r, b) == _bit(s, a))
+                else:
+                    c, t = qs
+                    if _bit(r, c) != _bit(s, c):
+                        v = 0
+                    elif _bit(s, c) == 0:
+                        v *= float(_bit(r, t) == _bit(s, t))
+                    else:
+                        v *= OG.controlled_target(name, th)[_bit(r, t), _bit(s, t)]
+            S[r, s] = v
+    return S
+
+
+def _all_single_steps(n):
+    one = [(nm, (q,), 0.7 if nm in W.ANGLED else None) for nm in W.ONE_QUBIT for q in range(n)]
+    two = []
+    for nm in ("CNOT", "CY", "CZ", "CR", "SWAP"):
+        for a in range(n):
+            for b in range(n):
+                if a != b:
+                    two.append((nm, (a, b), 1.1 if nm == "CR" else None))
+    return [[g] for g in one + two]
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_brute_force_every_gate_and_placement(n):
+    for step in _all_single_steps(n):
+        ref = brute_step(n, step)
+        np.testing.assert_allclose(UA.step_operator(n, step), ref, atol=TOL, err_msg=str(step))
+        np.testing.assert_allclose(fsv.circuit_unitary(n, step), ref, atol=TOL, err_msg=str(step))
+
+
+def test_brute_force_multi_gate_steps():
+    rng = np.random.default_rng(5)
+    for n in (3, 4):
+        for _ in range(30):
+            c = W.random_layers(n, 2, rng)
+            for st in UA.pack_steps(W.gate_tuples(c)):
+                np.testing.assert_allclose(UA.step_operator(n, st), brute_step(n, st), atol=TOL)
+
+
+def test_permutation_steps_have_one_unit_per_row_and_column():
+    for n in (3, 4):
+        for step in _all_single_steps(n):
+            if step[0][0] in ("X", "CNOT", "SWAP"):
+                S = UA.step_operator(n, step)
+                assert np.all((np.abs(S) < 1e-15) | (np.abs(S - 1) < 1e-15))
+                assert np.all(np.abs(S).sum(0) == 1) and np.all(np.abs(S).sum(1) == 1)
+
+
+# --- closed forms ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", range(1, 9))
+def test_ghz_closed_form(n):
+    N = 1 << n
+    ref = np.zeros(N, dtype=np.complex128)
+    ref[0] = ref[N - 1] = 1 / math.sqrt(2)
+    for c in (W.ghz_chain(n), W.ghz_fanout(n)):
+        g = W.gate_tuples(c)
+        np.testing.assert_allclose(UA.simulate_full_state(n, g), ref, atol=TOL)
+        np.testing.assert_allclose(fsv.final_state(n, g), ref, atol=TOL)
+
+
+@pytest.mark.parametrize("n", range(1, 8))
+def test_qft_is_the_dft(n):
+    N = 1 << n
+    j = np.arange(N)
+    closed = np.exp(2j * np.pi * np.outer(j, j) / N) / math.sqrt(N)
+    U = UA.circuit_unitary(n, W.gate_tuples(W.qft(n)))
+    np.testing.assert_allclose(U, closed, atol=1e-12)
+    # the same matrix from the library inverse FFT
+    np.testing.assert_allclose(U, np.fft.ifft(np.eye(N), axis=0) * math.sqrt(N), atol=1e-12)
+    # QFT |0> = uniform superposition
+    np.testing.assert_allclose(U[:, 0], np.full(N, 1 / math.sqrt(N)), atol=1e-12)
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 7])
+def test_deutsch_jozsa_outcome(n):
+    N = 1 << n
+    half = 1 << (n - 1)
+    for mask in [0] + sorted({1, half - 1, W.dj_mask(n, 0), W.dj_mask(n, 1)}):
+        psi = UA.simulate_full_state(n, W.gate_tuples(W.dj(n, mask)))
+        ref = np.zeros(N, dtype=np.complex128)
+        ref[mask] = 1 / math.sqrt(2)
+        ref[mask + half] = -1 / math.sqrt(2)
+        np.testing.assert_allclose(psi, ref, atol=TOL)
+        p = UA.probabilities(psi)
+        p_inputs_zero = p[0] + p[half]
+        assert p_inputs_zero == pytest.approx(1.0 if mask == 0 else 0.0, abs=1e-12)
+
+
+# --- invariants ---------------------------------------------------------------------------
+
+def test_unitarity_and_mirror_identity():
+    rng = np.random.default_rng(11)
+    for n in (2, 4, 6):
+        c = W.random_layers(n, 6, rng)
+        U = UA.circuit_unitary(n, W.gate_tuples(c))
+        mx, fro = metrics.unitarity_drift(U)
+        assert mx < 1e-12 and fro < 1e-12
+        M = UA.circuit_unitary(n, W.gate_tuples(W.mirror(c)))
+        np.testing.assert_allclose(M, np.eye(1 << n), atol=1e-12)
+        psi = U @ W.random_state(n, 3)
+        assert np.linalg.norm(psi) == pytest.approx(1.0, abs=1e-12)
+
+
+def _families(n, rng):
+    out = [W.ghz_chain(n), W.ghz_fanout(n), W.qft(n), W.random_layers(n, 5, rng)]
+    if n >= 2:
+        out.append(W.dj(n, int(rng.integers(0, 1 << (n - 1)))))
+    return out
+
+
+@pytest.mark.parametrize("n", range(1, 8))
+def test_route_a_equals_route_b(n):
+    rng = np.random.default_rng(100 + n)
+    for c in _families(n, rng):
+        g = W.gate_tuples(c)
+        np.testing.assert_allclose(UA.circuit_unitary(n, g), fsv.circuit_unitary(n, g), atol=1e-12, err_msg=c.family)
+
+
+def test_packing_invariance_and_step_counts():
+    rng = np.random.default_rng(7)
+    for n in (3, 5):
+        for c in _families(n, rng):
+            g = W.gate_tuples(c)
+            packed = UA.circuit_unitary(n, g)
+            one_per_step = UA.circuit_unitary(n, g, steps=[[x] for x in g])
+            np.testing.assert_allclose(packed, one_per_step, atol=1e-12)
+    # every QFT gate overlaps its predecessor's span: k = n + n(n-1)/2 + floor(n/2)
+    for n in (3, 11, 12, 13):
+        assert len(UA.pack_steps(W.gate_tuples(W.qft(n)))) == n + n * (n - 1) // 2 + n // 2
+    assert len(UA.pack_steps(W.gate_tuples(W.ghz_chain(5)))) == 5
+    # one random layer of single-qubit gates fits one step
+    c = W.random_layers(6, 1, np.random.default_rng(0))
+    assert len(UA.pack_steps(W.gate_tuples(c)[:6])) == 1
+
+
+def test_sampled_columns_match_full_unitary():
+    n = 6
+    c = W.random_layers(n, 4, np.random.default_rng(2))
+    g = W.gate_tuples(c)
+    cols = W.random_columns(n, 9, 4)
+    U = UA.circuit_unitary(n, g)
+    np.testing.assert_allclose(fsv.unitary_columns(n, g, cols), U[:, cols], atol=1e-12)
+
+
+def test_metrics():
+    psi = W.random_state(5, 1)
+    assert metrics.fidelity(np.exp(0.7j) * psi, psi) == pytest.approx(1.0, abs=1e-14)
+    assert metrics.max_abs_diff(psi, psi) == 0.0
+    assert metrics.unitarity_drift(np.eye(8)) == (0.0, 0.0)
+    other = W.random_state(5, 2)
+    assert metrics.fidelity(other, psi) == pytest.approx(abs(np.vdot(psi, other)) ** 2, abs=1e-14)
