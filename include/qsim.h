@@ -1,0 +1,202 @@
+/*
+ * qsim.h -- C ABI of libqsim, an MI355X (gfx950) implementation of the
+ * unitary-matrix circuit simulation method of TornadoQSim (arXiv 2305.14398).
+ *
+ * The method (Section 5.3, stages 1-6; Algorithms 1 and 2):
+ *   1-3  split the ordered gate list into steps and fetch each gate's matrix;
+ *   4    expand each step into its dense 2^n x 2^n operator: the Kronecker
+ *        product of the step's gates with identities on idle qubits (Eq. 9s1),
+ *        two-qubit gates on non-adjacent qubits embedded over their span;
+ *   5    multiply the step operators into the circuit unitary,
+ *        result <- A . result from result = I;
+ *   6    multiply the circuit unitary by the initial state vector.
+ *
+ * Conventions used by every call
+ * ------------------------------
+ * Qubit order: little-endian.  Qubit q is bit q of a basis-state index
+ *   (qubit 0 is the least significant bit).
+ * N = 2^n_qubits, 1 <= n_qubits <= QSIM_MAX_QUBITS.
+ * Complex matrices ("planar complex64"): two N x N float32 planes, the real
+ *   plane followed by the imaginary plane, 8*N*N bytes in total.  Row-major:
+ *   entry (r, c) real part at [r*N + c], imaginary part at [N*N + r*N + c].
+ *   Column-major (QSIM_LAYOUT_COL): entry (r, c) at [c*N + r] and
+ *   [N*N + c*N + r].
+ * Split 16-bit operands (QSIM_SPLIT_BF16 / QSIM_SPLIT_FP16): four N x N
+ *   16-bit planes in the order re_hi, re_lo, im_hi, im_lo (8*N*N bytes),
+ *   value = hi + lo * 2^-QSIM_LO_SCALE_LOG2 (lo is stored pre-scaled;
+ *   the scale is 2^0 for bf16).
+ * State vectors: planar complex64, N float32 real parts then N imaginary.
+ * Device pointers are hipMalloc'd (or torch-allocated) memory on the
+ *   context's device, 256-byte aligned, owned by the caller; the library does
+ *   not keep them after a call returns (except qsim_submit, see there).
+ * Streams: `stream` is a hipStream_t passed as void*; NULL is the null stream.
+ *   Device work is enqueued on it asynchronously; calls that return host
+ *   values synchronise that stream first and say so.
+ * Errors: every argument is checked before any device work is enqueued.  A
+ *   call returns a qsim_status; on failure nothing was launched and
+ *   qsim_last_error() describes the problem.  Errors the device reports
+ *   later surface as QSIM_E_DEVICE from the next call on the context.
+ */
+#ifndef LIBQSIM_QSIM_H_
+#define LIBQSIM_QSIM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QSIM_MAX_QUBITS 16
+#define QSIM_MAX_GATES_PER_STEP 16
+#define QSIM_LO_SCALE_LOG2 12
+
+typedef enum qsim_status {
+    QSIM_OK = 0,
+    QSIM_PENDING = 1,        /* qsim_poll: request not finished yet */
+    QSIM_E_INVALID = -1,     /* malformed argument (null, bad gate, overlap, alignment) */
+    QSIM_E_RANGE = -2,       /* size out of range (qubits, workspace too small) */
+    QSIM_E_OOM = -3,         /* arena / workspace cannot hold the request */
+    QSIM_E_DEVICE = -4,      /* a HIP call failed */
+    QSIM_E_FULL = -5,        /* qsim_submit: queue full (back-pressure) */
+    QSIM_E_UNKNOWN_ID = -6   /* qsim_poll: no such request */
+} qsim_status;
+
+/* Arithmetic of the chain product (stage 5). */
+typedef enum qsim_precision {
+    QSIM_FP32_4M = 0,     /* float32 MFMA, four real products per complex product */
+    QSIM_FP32_3M = 1,     /* float32 MFMA, three real products (Gauss) */
+    QSIM_SPLIT_BF16 = 2,  /* operands split into bf16 hi + lo, three bf16 MFMA passes, fp32 accumulate */
+    QSIM_SPLIT_FP16 = 3   /* operands split into fp16 hi + scaled lo, three passes, fp32 accumulate */
+} qsim_precision;
+
+/* Gate kinds.  A gate with control >= 0 is the controlled version of its kind
+ * (Section 2.3, Eq. 7): CNOT = {QSIM_X, control c, target t}, CZ = {QSIM_Z, ..},
+ * CR_phi = {QSIM_R, .., theta = phi}.  Matrices (rows = output bit):
+ *   H, X, Y, Z, R_phi = diag(1, e^{i phi}) as in Section 2.3, Table 1;
+ *   S = diag(1, i), T = diag(1, e^{i pi/4}) (named in Section 5.2.2);
+ *   RX, RY, RZ(theta) = exp(-i theta sigma_{x,y,z} / 2);
+ *   U2 = the caller's 2x2 matrix in u[] (row-major (re, im) pairs);
+ *   SWAP exchanges qubits `target` and `control` (the second qubit; not a
+ *   controlled gate; used by the QFT figure of Section 2.5). */
+typedef enum qsim_kind {
+    QSIM_H = 0, QSIM_X = 1, QSIM_Y = 2, QSIM_Z = 3, QSIM_S = 4, QSIM_T = 5,
+    QSIM_R = 6, QSIM_RX = 7, QSIM_RY = 8, QSIM_RZ = 9, QSIM_U2 = 10, QSIM_SWAP = 11
+} qsim_kind;
+
+typedef struct qsim_gate {
+    int32_t kind;      /* qsim_kind */
+    int32_t target;    /* qubit the 2x2 acts on; first qubit of a SWAP */
+    int32_t control;   /* control qubit, -1 if none; second qubit of a SWAP */
+    int32_t reserved;  /* must be 0 */
+    double theta;      /* angle of R, RX, RY, RZ; ignored otherwise */
+    double u[8];       /* QSIM_U2 only: u00 re, u00 im, u01 re, u01 im, u10 .., u11 .. */
+} qsim_gate;           /* 88 bytes */
+
+typedef enum qsim_layout { QSIM_LAYOUT_ROW = 0, QSIM_LAYOUT_COL = 1 } qsim_layout;
+
+typedef struct qsim_ctx qsim_ctx;
+
+/* Thread-local description of the last failure on this thread; valid until the
+ * next qsim call on the same thread.  Never NULL. */
+const char* qsim_last_error(void);
+
+/* Library version string. */
+const char* qsim_version(void);
+
+/* Create a context on HIP device `device` (0-based).  Allocates a few KiB of
+ * device scratch for reductions.  *out receives the context. */
+qsim_status qsim_ctx_create(int device, qsim_ctx** out);
+/* Destroy a context (stops its serving engine, if started).  NULL is a no-op. */
+qsim_status qsim_ctx_destroy(qsim_ctx* ctx);
+
+/* Stages 1-2 (Section 5.2.1: steps are created as gates are added).  Host only.
+ * A gate joins the most recent step if its qubit span [min q, max q] is
+ * disjoint from the span of every gate already in that step; otherwise it
+ * opens a new step.  Writes n_steps+1 offsets into step_offsets (capacity
+ * n_gates+1 int32): step j holds gates [step_offsets[j], step_offsets[j+1]).
+ * Validates every gate (qubits in range, control != target, kind known).
+ * Also fails if a step would exceed QSIM_MAX_GATES_PER_STEP (cannot happen
+ * for disjoint spans when n_qubits <= 16). */
+qsim_status qsim_pack_steps(int n_qubits, const qsim_gate* gates, int n_gates,
+                            int32_t* step_offsets, int* n_steps_out);
+
+/* Workspace qsim_unitary_chain needs for (n_qubits, prec), in bytes
+ * (scratch step operator + ping-pong chain buffers), or 0 if out of range. */
+size_t qsim_chain_workspace_bytes(int n_qubits, int prec);
+
+/* Stage 4 (Algorithm 2, Eq. 9s1): write the dense operator of ONE step.
+ * gates[0..n_gates) must have pairwise disjoint spans (QSIM_E_INVALID
+ * otherwise).  Each entry is the product over the step's gates of their
+ * matrix entries (identity on idle qubits), computed in float64 and rounded
+ * once to the output format.
+ * prec QSIM_FP32_4M / QSIM_FP32_3M: planar complex64 in `layout`;
+ * prec QSIM_SPLIT_BF16 / QSIM_SPLIT_FP16: split 16-bit planes in `layout`.
+ * d_op: 8*N*N bytes, caller-owned. */
+qsim_status qsim_build_step(qsim_ctx* ctx, int n_qubits, const qsim_gate* gates, int n_gates,
+                            int prec, int layout, void* d_op, void* stream);
+
+/* Stage 5, one product (Algorithm 1, result <- A . result):
+ * d_Uout = d_S . d_Uin for N x N complex matrices.
+ * d_S: the step operator in COLUMN-major layout, in the operand format of
+ *      `prec` (planar complex64 for FP32_*, split planes for SPLIT_*).
+ * d_Uin: row-major, operand format of `prec`.
+ * d_Uout: row-major planar complex64 (float32 result of the accumulation).
+ * d_Uout_split: for SPLIT_* only, optional (may be NULL): the same result
+ *      re-split into row-major split planes, ready to be the next d_Uin.
+ * d_Uout must not alias d_S or d_Uin. */
+qsim_status qsim_step_multiply(qsim_ctx* ctx, int n_qubits, int prec, const void* d_S,
+                               const void* d_Uin, void* d_Uout, void* d_Uout_split, void* stream);
+
+/* Stages 4-5 for a whole circuit: d_U = S_k ... S_1 (row-major planar
+ * complex64).  The first step's operator is the first partial product
+ * (multiplying by the initial identity is exact and is skipped), so a
+ * k-step circuit costs k expansions and k-1 products.
+ * step_offsets: NULL -> packed with the qsim_pack_steps rule; otherwise
+ *      n_steps+1 monotone offsets with offsets[0] = 0 and offsets[n_steps] =
+ *      n_gates, each step of pairwise disjoint spans and 1..16 gates.
+ * d_ws: device workspace of ws_bytes >= qsim_chain_workspace_bytes(n, prec).
+ * n_gates == 0 yields the identity. */
+qsim_status qsim_unitary_chain(qsim_ctx* ctx, int n_qubits, const qsim_gate* gates, int n_gates,
+                               const int32_t* step_offsets, int n_steps, int prec,
+                               void* d_U, void* d_ws, size_t ws_bytes, void* stream);
+
+/* Stage 6: d_psi = d_U . psi0 (complex64 matrix-vector product over the full
+ * row-major U).  d_psi0: planar complex64 initial state, or NULL for |0...0>
+ * (Eq. 9).  Then, in float64: norm2 = sum |psi_i|^2 and, if d_prob is not
+ * NULL, d_prob[i] = |psi_i|^2 / norm2 (N doubles).  If h_norm2 is not NULL the
+ * stream is synchronised and *h_norm2 receives norm2. */
+qsim_status qsim_apply_state(qsim_ctx* ctx, int n_qubits, const void* d_U, const void* d_psi0,
+                             void* d_psi, double* d_prob, double* h_norm2, void* stream);
+
+/* Unitarity drift of a row-major planar complex64 U (Section 2.3: a gate
+ * matrix is unitary iff U^H = U^-1): computes D = U^H U - I in float64 and
+ * returns h_out[0] = max |D_ij| and h_out[1] = ||D||_F / sqrt(N).  No N x N
+ * float64 matrix is stored.  Synchronises the stream. */
+qsim_status qsim_unitarity_drift(qsim_ctx* ctx, int n_qubits, const void* d_U, double* h_out,
+                                 void* stream);
+
+/* Kernel timing with HIP events (instrumentation, not part of the method).
+ * While enabled, every launch the context makes is bracketed by two events
+ * recorded on the launch stream; qsim_profile_read waits for the timed
+ * launches and returns per-class launch counts and summed durations.
+ * Classes: expansion (stage 4), chain product (stage 5), apply incl. the
+ * float64 norm/probabilities (stage 6), unitarity drift.  Enabling resets the
+ * totals; use from one host thread at a time. */
+#define QSIM_PROFILE_EXPAND 0
+#define QSIM_PROFILE_PRODUCT 1
+#define QSIM_PROFILE_APPLY 2
+#define QSIM_PROFILE_DRIFT 3
+#define QSIM_PROFILE_KINDS 4
+typedef struct qsim_kernel_stats {
+    int64_t count[QSIM_PROFILE_KINDS];
+    double total_ms[QSIM_PROFILE_KINDS];
+} qsim_kernel_stats;
+
+qsim_status qsim_profile_enable(qsim_ctx* ctx, int enable);
+qsim_status qsim_profile_read(qsim_ctx* ctx, qsim_kernel_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIBQSIM_QSIM_H_ */

@@ -1,0 +1,261 @@
+"""Thin ctypes binding of libqsim (include/qsim.h): argument marshalling only.
+
+Every function here has the name of the C entry point it forwards to.  Device
+buffers may be given as torch tensors (their ``data_ptr()`` is passed) or as
+raw integer addresses; ``stream`` defaults to torch's current stream on the
+context's device.  Gate lists are ``workloads.Gate`` objects or plain
+``(name, qubits, theta)`` tuples and are packed into ``qsim_gate`` records.
+No computation happens in Python: a missing library raises instead of
+falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, Optional, Sequence
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libqsim.so")
+
+QSIM_OK, QSIM_PENDING = 0, 1
+QSIM_E_INVALID, QSIM_E_RANGE, QSIM_E_OOM, QSIM_E_DEVICE, QSIM_E_FULL, QSIM_E_UNKNOWN_ID = -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "QSIM_OK", 1: "QSIM_PENDING", -1: "QSIM_E_INVALID", -2: "QSIM_E_RANGE", -3: "QSIM_E_OOM",
+                -4: "QSIM_E_DEVICE", -5: "QSIM_E_FULL", -6: "QSIM_E_UNKNOWN_ID"}
+
+QSIM_FP32_4M, QSIM_FP32_3M, QSIM_SPLIT_BF16, QSIM_SPLIT_FP16 = 0, 1, 2, 3
+PRECISIONS = {"fp32_4m": 0, "fp32_3m": 1, "split_bf16": 2, "split_fp16": 3}
+QSIM_LAYOUT_ROW, QSIM_LAYOUT_COL = 0, 1
+
+KIND = {"H": 0, "X": 1, "Y": 2, "Z": 3, "S": 4, "T": 5, "R": 6, "RX": 7, "RY": 8, "RZ": 9, "U2": 10, "SWAP": 11}
+# controlled names -> kind of the gate applied to the target
+CONTROLLED = {"CNOT": "X", "CY": "Y", "CZ": "Z", "CR": "R"}
+
+
+class qsim_gate(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("target", ctypes.c_int32), ("control", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("theta", ctypes.c_double), ("u", ctypes.c_double * 8)]
+
+
+assert ctypes.sizeof(qsim_gate) == 88
+
+PROFILE_KINDS = ("expand", "product", "apply", "drift")
+
+
+class qsim_kernel_stats(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int64 * 4), ("total_ms", ctypes.c_double * 4)]
+
+
+class QsimError(RuntimeError):
+    def __init__(self, status: int, message: str, call: str):
+        super().__init__(f"{call}: {STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libqsim.so (built in-tree by paper_2305_14398_amd.build); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2305_14398_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, sz, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_double
+    gp = ctypes.POINTER(qsim_gate)
+    ip = ctypes.POINTER(ctypes.c_int32)
+    sigs = {
+        "qsim_last_error": (ctypes.c_char_p, []),
+        "qsim_version": (ctypes.c_char_p, []),
+        "qsim_ctx_create": (i32, [i32, ctypes.POINTER(vp)]),
+        "qsim_ctx_destroy": (i32, [vp]),
+        "qsim_pack_steps": (i32, [i32, gp, i32, ip, ctypes.POINTER(i32)]),
+        "qsim_chain_workspace_bytes": (sz, [i32, i32]),
+        "qsim_build_step": (i32, [vp, i32, gp, i32, i32, i32, vp, vp]),
+        "qsim_step_multiply": (i32, [vp, i32, i32, vp, vp, vp, vp, vp]),
+        "qsim_unitary_chain": (i32, [vp, i32, gp, i32, ip, i32, i32, vp, vp, sz, vp]),
+        "qsim_apply_state": (i32, [vp, i32, vp, vp, vp, vp, ctypes.POINTER(dbl), vp]),
+        "qsim_unitarity_drift": (i32, [vp, i32, vp, ctypes.POINTER(dbl), vp]),
+        "qsim_profile_enable": (i32, [vp, i32]),
+        "qsim_profile_read": (i32, [vp, ctypes.POINTER(qsim_kernel_stats)]),
+    }
+    for name, (res, args) in sigs.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status: int, call: str) -> int:
+    if status < 0:
+        raise QsimError(status, lib().qsim_last_error().decode(), call)
+    return status
+
+
+def _ptr(x) -> Optional[int]:
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream, device: int = 0):
+    if stream is not None:
+        return stream if isinstance(stream, int) else stream.cuda_stream
+    import torch
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def gate_record(g) -> qsim_gate:
+    """Marshal one gate (workloads.Gate or (name, qubits, theta[, u])) into a qsim_gate."""
+    name, qubits, theta = (g.name, g.qubits, g.theta) if hasattr(g, "name") else (g[0], g[1], g[2])
+    rec = qsim_gate()
+    rec.reserved = 0
+    rec.theta = 0.0 if theta is None else float(theta)
+    if name in CONTROLLED:
+        rec.kind = KIND[CONTROLLED[name]]
+        rec.control, rec.target = int(qubits[0]), int(qubits[1])
+    elif name == "SWAP":
+        rec.kind = KIND["SWAP"]
+        rec.target, rec.control = int(qubits[0]), int(qubits[1])
+    else:
+        rec.kind = KIND[name]
+        rec.target = int(qubits[0])
+        rec.control = int(qubits[1]) if len(qubits) > 1 else -1
+    if name == "U2":
+        u = g[3] if not hasattr(g, "name") else g.u
+        for i in range(4):
+            rec.u[2 * i] = float(complex(u[i // 2][i % 2]).real)
+            rec.u[2 * i + 1] = float(complex(u[i // 2][i % 2]).imag)
+    return rec
+
+
+def gate_array(gates: Iterable):
+    gl = list(gates)
+    arr = (qsim_gate * max(1, len(gl)))()
+    for i, g in enumerate(gl):
+        arr[i] = g if isinstance(g, qsim_gate) else gate_record(g)
+    return arr, len(gl)
+
+
+class Context:
+    """Owns a qsim_ctx handle (qsim_ctx_create / qsim_ctx_destroy)."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        self.handle = qsim_ctx_create(device)
+
+    def close(self):
+        if self.handle:
+            qsim_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _h(ctx):
+    return ctx.handle if isinstance(ctx, Context) else ctx
+
+
+def _dev(ctx):
+    return ctx.device if isinstance(ctx, Context) else 0
+
+
+# --- entry points (same names as the C ABI) --------------------------------------------------
+
+def qsim_version() -> str:
+    return lib().qsim_version().decode()
+
+
+def qsim_last_error() -> str:
+    return lib().qsim_last_error().decode()
+
+
+def qsim_ctx_create(device: int = 0) -> int:
+    out = ctypes.c_void_p()
+    _check(lib().qsim_ctx_create(device, ctypes.byref(out)), "qsim_ctx_create")
+    return out.value
+
+
+def qsim_ctx_destroy(handle) -> None:
+    _check(lib().qsim_ctx_destroy(handle), "qsim_ctx_destroy")
+
+
+def qsim_pack_steps(n_qubits: int, gates: Sequence) -> list:
+    arr, ng = gate_array(gates)
+    off = (ctypes.c_int32 * (ng + 1))()
+    ns = ctypes.c_int()
+    _check(lib().qsim_pack_steps(n_qubits, arr, ng, off, ctypes.byref(ns)), "qsim_pack_steps")
+    return [int(off[i]) for i in range(ns.value + 1)]
+
+
+def qsim_chain_workspace_bytes(n_qubits: int, prec: int) -> int:
+    return int(lib().qsim_chain_workspace_bytes(n_qubits, prec))
+
+
+def qsim_build_step(ctx, n_qubits: int, gates: Sequence, prec: int, layout: int, d_op, stream=None) -> None:
+    arr, ng = gate_array(gates)
+    st = _stream(stream, _dev(ctx)) if _h(ctx) else None
+    _check(lib().qsim_build_step(_h(ctx), n_qubits, arr, ng, prec, layout, _ptr(d_op), st), "qsim_build_step")
+
+
+def qsim_step_multiply(ctx, n_qubits: int, prec: int, d_S, d_Uin, d_Uout, d_Uout_split=None, stream=None) -> None:
+    st = _stream(stream, _dev(ctx)) if _h(ctx) else None
+    _check(lib().qsim_step_multiply(_h(ctx), n_qubits, prec, _ptr(d_S), _ptr(d_Uin), _ptr(d_Uout),
+                                    _ptr(d_Uout_split), st), "qsim_step_multiply")
+
+
+def qsim_unitary_chain(ctx, n_qubits: int, gates: Sequence, prec: int, d_U, d_ws, ws_bytes: Optional[int] = None,
+                       step_offsets: Optional[Sequence[int]] = None, stream=None) -> None:
+    arr, ng = gate_array(gates)
+    if step_offsets is None:
+        off_p, ns = None, 0
+    else:
+        off_p = (ctypes.c_int32 * len(step_offsets))(*step_offsets)
+        ns = len(step_offsets) - 1
+    if ws_bytes is None:
+        ws_bytes = d_ws.numel() * d_ws.element_size() if hasattr(d_ws, "numel") else 0
+    st = _stream(stream, _dev(ctx)) if _h(ctx) else None
+    _check(lib().qsim_unitary_chain(_h(ctx), n_qubits, arr, ng, off_p, ns, prec, _ptr(d_U), _ptr(d_ws), ws_bytes, st),
+           "qsim_unitary_chain")
+
+
+def qsim_apply_state(ctx, n_qubits: int, d_U, d_psi0, d_psi, d_prob=None, want_norm2: bool = True,
+                     stream=None) -> Optional[float]:
+    norm = ctypes.c_double(float("nan"))
+    st = _stream(stream, _dev(ctx)) if _h(ctx) else None
+    _check(lib().qsim_apply_state(_h(ctx), n_qubits, _ptr(d_U), _ptr(d_psi0), _ptr(d_psi), _ptr(d_prob),
+                                  ctypes.byref(norm) if want_norm2 else None, st), "qsim_apply_state")
+    return norm.value if want_norm2 else None
+
+
+def qsim_unitarity_drift(ctx, n_qubits: int, d_U, stream=None) -> tuple:
+    out = (ctypes.c_double * 2)()
+    st = _stream(stream, _dev(ctx)) if _h(ctx) else None
+    _check(lib().qsim_unitarity_drift(_h(ctx), n_qubits, _ptr(d_U), out, st), "qsim_unitarity_drift")
+    return float(out[0]), float(out[1])
+
+
+def qsim_profile_enable(ctx, enable: bool = True) -> None:
+    _check(lib().qsim_profile_enable(_h(ctx), 1 if enable else 0), "qsim_profile_enable")
+
+
+def qsim_profile_read(ctx) -> dict:
+    """{kind: (launch count, total milliseconds)} for expand / product / apply / drift."""
+    st = qsim_kernel_stats()
+    _check(lib().qsim_profile_read(_h(ctx), ctypes.byref(st)), "qsim_profile_read")
+    return {k: (int(st.count[i]), float(st.total_ms[i])) for i, k in enumerate(PROFILE_KINDS)}

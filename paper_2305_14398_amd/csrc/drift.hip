@@ -1,0 +1,236 @@
+// Unitarity drift of a computed circuit unitary U (Section 2.3: a gate matrix
+// is unitary iff its adjoint is its inverse, so any product of step operators
+// is unitary and U^H U - I measures the rounding accumulated by the chain).
+//
+// G = U^H U is formed on float64 MFMA (v_mfma_f64_16x16x4f64) from the float32
+// planes, and D = G - I is reduced on the fly to max |D_ij| and sum |D_ij|^2:
+// no N x N float64 matrix is written.  G is Hermitian, so only tiles on or
+// above the diagonal are computed; off-diagonal tiles count twice in the sum.
+//   Re G_ij = sum_k Ur_ki Ur_kj + Ui_ki Ui_kj
+//   Im G_ij = sum_k Ur_ki Ui_kj - Ui_ki Ur_kj
+// Both operands are rows k of U, read as contiguous 16-byte vectors.
+#include "common.h"
+
+namespace qsim {
+namespace {
+
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int DT = 64;     // tile edge
+constexpr int DBK = 16;    // k rows per LDS tile
+constexpr int DLD = DT + 16;  // padded row stride (floats): the 4 k-rows of one MFMA land on distinct banks
+
+__device__ __forceinline__ void tile_of(int t, int T, int& tm, int& tn) {
+    // t-th upper-triangular tile in row order: row tm holds T - tm tiles.
+    tm = 0;
+    while (t >= T - tm) {
+        t -= T - tm;
+        ++tm;
+    }
+    tn = tm + t;
+}
+
+__global__ __launch_bounds__(256) void drift_mfma_kernel(int n, const float* __restrict__ U, double* __restrict__ partials) {
+    const int N = 1 << n;
+    const size_t NN = (size_t)N * N;
+    const int T = N / DT;
+    const int ntiles = T * (T + 1) / 2;
+
+    __shared__ float As[2][2][DBK][DLD];
+    __shared__ float Bs[2][2][DBK][DLD];
+    __shared__ double red_max[4], red_sum[4];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int l16 = lane & 15, kq = lane >> 4;
+    // loader: one float4 per plane per operand: row tid/16, columns 4*(tid%16)
+    const int lrow = tid >> 4, lcol = (tid & 15) * 4;
+
+    double tmax = 0.0, tsum = 0.0;
+
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        int tm, tn;
+        tile_of(t, T, tm, tn);
+        const int i0 = tm * DT, j0 = tn * DT;
+        doublex4 acc[2][2][2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+#pragma unroll
+                for (int z = 0; z < 2; ++z) acc[x][y][z] = doublex4{0.0, 0.0, 0.0, 0.0};
+
+        floatx4 ra[2], rb[2];
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            ra[p] = *reinterpret_cast<const floatx4*>(U + p * NN + (size_t)lrow * N + i0 + lcol);
+            rb[p] = *reinterpret_cast<const floatx4*>(U + p * NN + (size_t)lrow * N + j0 + lcol);
+        }
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            *reinterpret_cast<floatx4*>(&As[0][p][lrow][lcol]) = ra[p];
+            *reinterpret_cast<floatx4*>(&Bs[0][p][lrow][lcol]) = rb[p];
+        }
+        __syncthreads();
+
+        const int KT = N / DBK;
+        for (int kt = 0; kt < KT; ++kt) {
+            const int cur = kt & 1;
+            if (kt + 1 < KT) {
+                const size_t r = (size_t)((kt + 1) * DBK + lrow) * N;
+#pragma unroll
+                for (int p = 0; p < 2; ++p) {
+                    ra[p] = *reinterpret_cast<const floatx4*>(U + p * NN + r + i0 + lcol);
+                    rb[p] = *reinterpret_cast<const floatx4*>(U + p * NN + r + j0 + lcol);
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < DBK / 4; ++s) {
+                const int k = 4 * s + kq;
+                double ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+                for (int x = 0; x < 2; ++x) {
+                    ar[x] = (double)As[cur][0][k][wm * 32 + x * 16 + l16];
+                    ai[x] = (double)As[cur][1][k][wm * 32 + x * 16 + l16];
+                    br[x] = (double)Bs[cur][0][k][wn * 32 + x * 16 + l16];
+                    bi[x] = (double)Bs[cur][1][k][wn * 32 + x * 16 + l16];
+                }
+#pragma unroll
+                for (int x = 0; x < 2; ++x) {
+#pragma unroll
+                    for (int y = 0; y < 2; ++y) {
+                        acc[x][y][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[x], br[y], acc[x][y][0], 0, 0, 0);
+                        acc[x][y][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[x], bi[y], acc[x][y][0], 0, 0, 0);
+                        acc[x][y][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[x], bi[y], acc[x][y][1], 0, 0, 0);
+                        acc[x][y][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[x], br[y], acc[x][y][1], 0, 0, 0);
+                    }
+                }
+            }
+            if (kt + 1 < KT) {
+#pragma unroll
+                for (int p = 0; p < 2; ++p) {
+                    *reinterpret_cast<floatx4*>(&As[cur ^ 1][p][lrow][lcol]) = ra[p];
+                    *reinterpret_cast<floatx4*>(&Bs[cur ^ 1][p][lrow][lcol]) = rb[p];
+                }
+            }
+            __syncthreads();
+        }
+
+        // 16x16 float64 accumulator layout: register r of lane l is row l/16 + 4*r, column l%16.
+        const double w = (tm == tn) ? 1.0 : 2.0;
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                const int j = j0 + wn * 32 + y * 16 + l16;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = i0 + wm * 32 + x * 16 + kq + 4 * r;
+                    const double dr = acc[x][y][0][r] - (i == j ? 1.0 : 0.0);
+                    const double di = acc[x][y][1][r];
+                    const double m2 = dr * dr + di * di;
+                    tmax = fmax(tmax, sqrt(m2));
+                    tsum += w * m2;
+                }
+            }
+        }
+    }
+
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        tmax = fmax(tmax, __shfl_xor(tmax, off, 64));
+        tsum += __shfl_xor(tsum, off, 64);
+    }
+    if (lane == 0) {
+        red_max[wave] = tmax;
+        red_sum[wave] = tsum;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        partials[2 * blockIdx.x] = fmax(fmax(red_max[0], red_max[1]), fmax(red_max[2], red_max[3]));
+        partials[2 * blockIdx.x + 1] = (red_sum[0] + red_sum[1]) + (red_sum[2] + red_sum[3]);
+    }
+}
+
+// N < 64: one block, one thread per entry of G, plain float64 arithmetic.
+__global__ __launch_bounds__(256) void drift_small_kernel(int n, const float* __restrict__ U, double* __restrict__ partials) {
+    const int N = 1 << n;
+    const size_t NN = (size_t)N * N;
+    __shared__ double smax[256], ssum[256];
+    double tmax = 0.0, tsum = 0.0;
+    for (int e = threadIdx.x; e < N * N; e += 256) {
+        const int i = e / N, j = e % N;
+        double gr = 0.0, gi = 0.0;
+        for (int k = 0; k < N; ++k) {
+            const double ar = U[(size_t)k * N + i], ai = U[NN + (size_t)k * N + i];
+            const double br = U[(size_t)k * N + j], bi = U[NN + (size_t)k * N + j];
+            gr += ar * br + ai * bi;
+            gi += ar * bi - ai * br;
+        }
+        const double dr = gr - (i == j ? 1.0 : 0.0);
+        const double m2 = dr * dr + gi * gi;
+        tmax = fmax(tmax, sqrt(m2));
+        tsum += m2;
+    }
+    smax[threadIdx.x] = tmax;
+    ssum[threadIdx.x] = tsum;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
+            ssum[threadIdx.x] += ssum[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partials[0] = smax[0];
+        partials[1] = ssum[0];
+    }
+}
+
+__global__ __launch_bounds__(256) void drift_final_kernel(int n, int count, const double* __restrict__ partials,
+                                                          double* __restrict__ out) {
+    __shared__ double smax[256], ssum[256];
+    double tmax = 0.0, tsum = 0.0;
+    for (int i = threadIdx.x; i < count; i += 256) {
+        tmax = fmax(tmax, partials[2 * i]);
+        tsum += partials[2 * i + 1];
+    }
+    smax[threadIdx.x] = tmax;
+    ssum[threadIdx.x] = tsum;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
+            ssum[threadIdx.x] += ssum[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = smax[0];
+        out[1] = sqrt(ssum[0] / (double)(1 << n));
+    }
+}
+
+}  // namespace
+
+hipError_t launch_drift(int n, const float* U_row, double* partials, int max_partials, double* d_out,
+                        hipStream_t stream) {
+    const int N = 1 << n;
+    int count = 1;
+    if (N < DT) {
+        hipLaunchKernelGGL(drift_small_kernel, dim3(1), dim3(256), 0, stream, n, U_row, partials);
+    } else {
+        const int T = N / DT;
+        const int ntiles = T * (T + 1) / 2;
+        count = ntiles < max_partials ? ntiles : max_partials;
+        hipLaunchKernelGGL(drift_mfma_kernel, dim3(count), dim3(256), 0, stream, n, U_row, partials);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(drift_final_kernel, dim3(1), dim3(256), 0, stream, n, count, partials, d_out);
+    return hipGetLastError();
+}
+
+}  // namespace qsim

@@ -1,0 +1,168 @@
+"""Host-side checks of libqsim that need no GPU: loading, exported symbols,
+step formation, workspace sizes and argument validation (every call checks
+its arguments before touching the device)."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import unitary as UA
+from paper_2305_14398_amd import binding as B
+from paper_2305_14398_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE = 256 * 4096  # an aligned address that is never dereferenced: validation fails first
+
+
+def header_functions():
+    with open(os.path.join(ROOT, "include", "qsim.h")) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qsim_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_loads_and_exports_every_declared_function():
+    L = B.lib()
+    names = header_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(L, name), f"{name} declared in qsim.h but not exported"
+    assert "gfx950" in B.qsim_version()
+
+
+def test_header_struct_size_matches_binding():
+    with open(os.path.join(ROOT, "include", "qsim.h")) as f:
+        assert "88 bytes" in f.read()
+    assert B.ctypes.sizeof(B.qsim_gate) == 88
+
+
+def _families(n, rng):
+    out = [W.ghz_chain(n), W.ghz_fanout(n), W.qft(n), W.random_layers(n, 6, rng)]
+    if n >= 2:
+        out.append(W.dj(n, int(rng.integers(0, 1 << (n - 1)))))
+    return out
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 8, 11, 13, 16])
+def test_pack_steps_matches_oracle_rule(n):
+    rng = np.random.default_rng(n)
+    for c in _families(n, rng):
+        off = B.qsim_pack_steps(n, c.gates)
+        steps = UA.pack_steps(W.gate_tuples(c))
+        ref = [0]
+        for st in steps:
+            ref.append(ref[-1] + len(st))
+        assert off == ref, c.family
+
+
+def test_pack_step_counts_of_paper_workloads():
+    assert len(B.qsim_pack_steps(11, W.qft(11).gates)) - 1 == 71
+    assert len(B.qsim_pack_steps(5, W.ghz_chain(5).gates)) - 1 == 5
+    # Deutsch-Jozsa: X + H layer share one step, oracle CNOTs one each, final H layer one step
+    mask = 0b1011
+    k = len(B.qsim_pack_steps(6, W.dj(6, mask).gates)) - 1
+    assert k == len(UA.pack_steps(W.gate_tuples(W.dj(6, mask))))
+
+
+def test_workspace_bytes():
+    for n in (1, 5, 11, 13):
+        mb = 8 << (2 * n)
+        assert B.qsim_chain_workspace_bytes(n, B.QSIM_FP32_4M) == 2 * mb
+        assert B.qsim_chain_workspace_bytes(n, B.QSIM_FP32_3M) == 2 * mb
+        assert B.qsim_chain_workspace_bytes(n, B.QSIM_SPLIT_BF16) == 3 * mb
+    assert B.qsim_chain_workspace_bytes(0, 0) == 0
+    assert B.qsim_chain_workspace_bytes(17, 0) == 0
+    assert B.qsim_chain_workspace_bytes(5, 9) == 0
+
+
+def _expect(status, fn, *args, match=None):
+    with pytest.raises(B.QsimError) as ei:
+        fn(*args)
+    assert ei.value.status == status, str(ei.value)
+    if match:
+        assert re.search(match, ei.value.message), ei.value.message
+
+
+def test_gate_validation_in_pack():
+    _expect(B.QSIM_E_INVALID, B.qsim_pack_steps, 3, [("H", (3,), None)], match="outside")
+    _expect(B.QSIM_E_INVALID, B.qsim_pack_steps, 3, [("H", (-1,), None)], match="outside")
+    bad = B.gate_record(("CNOT", (0, 1), None))
+    bad.control = 0
+    bad.target = 0
+    _expect(B.QSIM_E_INVALID, B.qsim_pack_steps, 3, [bad], match="control equals target")
+    kind = B.gate_record(("H", (0,), None))
+    kind.kind = 42
+    _expect(B.QSIM_E_INVALID, B.qsim_pack_steps, 3, [kind], match="unknown kind")
+    swap = B.gate_record(("SWAP", (0, 1), None))
+    swap.control = -1
+    _expect(B.QSIM_E_INVALID, B.qsim_pack_steps, 3, [swap], match="SWAP")
+    nan = B.gate_record(("RX", (0,), 1.0))
+    nan.theta = math.nan
+    _expect(B.QSIM_E_INVALID, B.qsim_pack_steps, 3, [nan], match="angle")
+    res = B.gate_record(("H", (0,), None))
+    res.reserved = 1
+    _expect(B.QSIM_E_INVALID, B.qsim_pack_steps, 3, [res], match="reserved")
+    _expect(B.QSIM_E_RANGE, B.qsim_pack_steps, 0, [])
+    _expect(B.QSIM_E_RANGE, B.qsim_pack_steps, 17, [])
+
+
+def test_custom_matrix_must_be_unitary():
+    r = 1 / math.sqrt(2)
+    good = ("U2", (0,), None, [[r, 1j * r], [1j * r, r]])
+    assert B.qsim_pack_steps(2, [good]) == [0, 1]
+    bad = ("U2", (0,), None, [[1, 1], [0, 1]])
+    _expect(B.QSIM_E_INVALID, B.qsim_pack_steps, 2, [bad], match="not unitary")
+
+
+def test_build_step_validation_without_device():
+    g = [("H", (0,), None), ("CNOT", (1, 2), None)]
+    # overlapping spans within one step
+    _expect(B.QSIM_E_INVALID, B.qsim_build_step, None, 3, [("CNOT", (0, 2), None), ("H", (1,), None)], 0, 0, FAKE,
+            match="overlaps")
+    _expect(B.QSIM_E_INVALID, B.qsim_build_step, None, 3, g, 0, 0, FAKE + 4, match="aligned")
+    _expect(B.QSIM_E_INVALID, B.qsim_build_step, None, 3, g, 0, 7, FAKE, match="layout")
+    _expect(B.QSIM_E_INVALID, B.qsim_build_step, None, 3, g, 9, 0, FAKE, match="precision")
+    _expect(B.QSIM_E_RANGE, B.qsim_build_step, None, 0, g, 0, 0, FAKE)
+    too_many = [("H", (q,), None) for q in range(16)] + [("X", (0,), None)]
+    _expect(B.QSIM_E_INVALID, B.qsim_build_step, None, 16, too_many, 0, 0, FAKE)
+    # valid arguments and no context: the context check is the last one
+    _expect(B.QSIM_E_INVALID, B.qsim_build_step, None, 3, g, 0, 0, FAKE, match="context is NULL")
+
+
+def test_chain_validation_without_device():
+    g = W.qft(4).gates
+    mb = 8 << 8
+    _expect(B.QSIM_E_RANGE, B.qsim_unitary_chain, None, 4, g, 0, FAKE, FAKE * 4, mb, match="workspace")
+    _expect(B.QSIM_E_INVALID, B.qsim_unitary_chain, None, 4, g, 0, FAKE, FAKE, 2 * mb, match="overlaps")
+    _expect(B.QSIM_E_INVALID, B.qsim_unitary_chain, None, 4, g, 0, FAKE, FAKE * 4, 2 * mb, [0, 3],
+            match="offsets")
+    # a step of the caller's offsets that has overlapping spans
+    _expect(B.QSIM_E_INVALID, B.qsim_unitary_chain, None, 4, g, 0, FAKE, FAKE * 4, 2 * mb,
+            [0, 2] + list(range(3, len(g) + 1)), match="step 0")
+    _expect(B.QSIM_E_INVALID, B.qsim_unitary_chain, None, 4, g, 0, FAKE, FAKE * 4, 2 * mb, match="context is NULL")
+
+
+def test_multiply_apply_drift_validation_without_device():
+    _expect(B.QSIM_E_INVALID, B.qsim_step_multiply, None, 5, 0, FAKE, FAKE * 2, FAKE, None, match="aliases")
+    _expect(B.QSIM_E_INVALID, B.qsim_step_multiply, None, 5, 0, FAKE, FAKE * 2, FAKE * 3, FAKE * 4, match="split")
+    _expect(B.QSIM_E_INVALID, B.qsim_step_multiply, None, 5, 0, FAKE + 8, FAKE * 2, FAKE * 3, None, match="aligned")
+    _expect(B.QSIM_E_INVALID, B.qsim_apply_state, None, 5, FAKE, FAKE * 2, FAKE * 2, None, match="aliases")
+    _expect(B.QSIM_E_INVALID, B.qsim_apply_state, None, 5, FAKE, None, FAKE * 2 + 4, None, match="aligned")
+    _expect(B.QSIM_E_RANGE, B.qsim_unitarity_drift, None, 17, FAKE)
+    _expect(B.QSIM_E_INVALID, B.qsim_unitarity_drift, None, 5, FAKE, match="context is NULL")
+
+
+def test_last_error_is_thread_local_and_resets():
+    _expect(B.QSIM_E_RANGE, B.qsim_pack_steps, 0, [])
+    msg = B.qsim_last_error()
+    assert "n_qubits" in msg
+    import threading
+    seen = []
+    t = threading.Thread(target=lambda: seen.append(B.qsim_last_error()))
+    t.start()
+    t.join()
+    assert seen == ["no error"]
+    B.qsim_pack_steps(2, [("H", (0,), None)])
+    assert B.qsim_last_error() == "no error"
