@@ -50,6 +50,21 @@ def closed_form_error(c, psi):
     return float(np.abs(psi - ref).max())
 
 
+def counted_traffic(profile: str, source: str):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, or None when the kernel source changed
+    since the counters were taken (the summary stores the source's sha256)."""
+    import hashlib
+    try:
+        text = open(os.path.join(ROOT, "profiles", profile)).read()
+        sha = hashlib.sha256(open(os.path.join(ROOT, source), "rb").read()).hexdigest()
+    except OSError:
+        return None
+    fields = dict(line.strip().split(": ", 1) for line in text.splitlines() if line.startswith("    ") and ": " in line)
+    if fields.get("source_sha256") != sha or "hbm_bytes_per_launch" not in fields:
+        return None
+    return int(fields["hbm_bytes_per_launch"])
+
+
 def cpu_baseline(n: int, budget_s: float):
     """The oracle (route A, complex128 numpy/OpenBLAS) on the first steps of qft(n) within a time budget."""
     import numpy as np
@@ -92,6 +107,9 @@ def main() -> int:
     ap.add_argument("--qubits", type=int, default=11)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB (a known-size kernel that "
+                         "scales the HBM byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: --gpus {args.gpus} is not supported (independent circuits would shard "
@@ -117,6 +135,14 @@ def main() -> int:
     records = [B.gate_array(c.gates) for c in circuits]
     ks = [len(B.qsim_pack_steps(n, c.gates)) - 1 for c in circuits]
     flops_per_step = sum(8.0 * N ** 3 * (k - 1) for k in ks)
+
+    if args.copy_calibration_mib:
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     results = {}
 
@@ -192,7 +218,10 @@ def main() -> int:
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4),
-            "traffic": None,
+            "traffic": counted_traffic("cgemm_f32_4m_qft11_dj11.md", "paper_2305_14398_amd/csrc/cgemm_f32.hip")
+            if (args.prec == "fp32_4m" and n == 11) else None,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE, copy-calibrated)",
+            "algorithmic_bytes_per_launch": 3 * 8 * N * N,
         },
         "expand_roofline": {
             "bound": "hbm",
