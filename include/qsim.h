@@ -136,26 +136,33 @@ size_t qsim_chain_workspace_bytes(int n_qubits, int prec);
 qsim_status qsim_build_step(qsim_ctx* ctx, int n_qubits, const qsim_gate* gates, int n_gates,
                             int prec, int layout, void* d_op, void* stream);
 
-/* Stage 5, one product (Algorithm 1, result <- A . result):
- * d_Uout = d_S . d_Uin for N x N complex matrices.
- * d_S: the step operator in COLUMN-major layout, in the operand format of
- *      `prec` (planar complex64 for FP32_*, split planes for SPLIT_*).
- * d_Uin: row-major, operand format of `prec`.
- * d_Uout: row-major planar complex64 (float32 result of the accumulation).
- * d_Uout_split: for SPLIT_* only, optional (may be NULL): the same result
- *      re-split into row-major split planes, ready to be the next d_Uin.
- * d_Uout must not alias d_S or d_Uin. */
+/* Stage 5, one product (Algorithm 1, result <- A . result): C = S . U for
+ * N x N complex matrices.  Operand layouts follow what each MFMA shape reads
+ * contiguously along the contraction index:
+ *   QSIM_FP32_4M / QSIM_FP32_3M: d_S planar complex64 COLUMN-major, d_Uin
+ *      planar complex64 row-major, d_Uout (required) planar complex64
+ *      row-major; d_Uout_split must be NULL.
+ *   QSIM_SPLIT_BF16 / QSIM_SPLIT_FP16: d_S split planes ROW-major, d_Uin split
+ *      planes COLUMN-major.  d_Uout (optional): C as planar complex64
+ *      row-major; d_Uout_split (optional): C as split planes column-major, i.e.
+ *      the d_Uin of the next product.  At least one output; each requested
+ *      output costs one kernel launch.
+ * Outputs must not alias inputs or each other. */
 qsim_status qsim_step_multiply(qsim_ctx* ctx, int n_qubits, int prec, const void* d_S,
                                const void* d_Uin, void* d_Uout, void* d_Uout_split, void* stream);
 
 /* Stages 4-5 for a whole circuit: d_U = S_k ... S_1 (row-major planar
  * complex64).  The first step's operator is the first partial product
  * (multiplying by the initial identity is exact and is skipped), so a
- * k-step circuit costs k expansions and k-1 products.
+ * k-step circuit costs k expansions and k-1 products.  With a split
+ * precision the partial products are carried in split form (re-split from the
+ * float32 accumulators after every product) and only the last is written as
+ * float32.
  * step_offsets: NULL -> packed with the qsim_pack_steps rule; otherwise
  *      n_steps+1 monotone offsets with offsets[0] = 0 and offsets[n_steps] =
  *      n_gates, each step of pairwise disjoint spans and 1..16 gates.
- * d_ws: device workspace of ws_bytes >= qsim_chain_workspace_bytes(n, prec).
+ * d_ws: device workspace of ws_bytes >= qsim_chain_workspace_bytes(n, prec)
+ *      (2 matrices for float32, 3 for split precisions), not overlapping d_U.
  * n_gates == 0 yields the identity. */
 qsim_status qsim_unitary_chain(qsim_ctx* ctx, int n_qubits, const qsim_gate* gates, int n_gates,
                                const int32_t* step_offsets, int n_steps, int prec,

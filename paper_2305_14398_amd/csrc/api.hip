@@ -56,7 +56,7 @@ bool valid_n(int n) { return n >= 1 && n <= QSIM_MAX_QUBITS; }
 bool valid_prec(int p) { return p >= QSIM_FP32_4M && p <= QSIM_SPLIT_FP16; }
 
 // Precisions with a kernel in this build.
-bool built_prec(int p) { return p == QSIM_FP32_4M || p == QSIM_FP32_3M; }
+bool built_prec(int p) { return valid_prec(p); }
 
 qsim_status check_gate(int n, const qsim_gate& g, int idx) {
     if (g.kind < QSIM_H || g.kind > QSIM_SWAP) return fail(QSIM_E_INVALID, "gate %d: unknown kind %d", idx, g.kind);
@@ -345,7 +345,39 @@ qsim_status chain_impl(int n, const qsim_gate* gates, int n_gates, const int32_t
         }
         return QSIM_OK;
     }
-    return fail(QSIM_E_INVALID, "split precisions are not available in this build");
+    // Split 16-bit operands: the running product is kept column-major in split
+    // form (two ping-pong buffers), each step operator row-major in split form;
+    // the last product is taken in the direct orientation and written as
+    // float32 row-major into d_U.
+    void* S = ws;
+    void* P[2] = {ws + mb, ws + 2 * mb};
+    const int k = n_steps;
+    s = make_step(n, gates + off[0], off[1] - off[0], st);
+    if (s != QSIM_OK) return s;
+    if (k == 1) {
+        e = timed(prof, QSIM_PROFILE_EXPAND, stream, [&] { return launch_expand_step(st, n, 0, FMT_F32, d_U, stream); });
+        return e == hipSuccess ? QSIM_OK : device_fail("expand", e);
+    }
+    e = timed(prof, QSIM_PROFILE_EXPAND, stream, [&] { return launch_expand_step(st, n, 1, fmt, P[0], stream); });
+    if (e != hipSuccess) return device_fail("expand", e);
+    int cur = 0;
+    for (int j = 1; j < k; ++j) {
+        s = make_step(n, gates + off[j], off[j + 1] - off[j], st);
+        if (s != QSIM_OK) return s;
+        e = timed(prof, QSIM_PROFILE_EXPAND, stream, [&] { return launch_expand_step(st, n, 0, fmt, S, stream); });
+        if (e != hipSuccess) return device_fail("expand", e);
+        if (j < k - 1) {
+            e = timed(prof, QSIM_PROFILE_PRODUCT, stream,
+                      [&] { return launch_cgemm_split(n, fmt, P[cur], S, P[cur ^ 1], nullptr, stream); });
+            cur ^= 1;
+        } else {
+            e = timed(prof, QSIM_PROFILE_PRODUCT, stream, [&] {
+                return launch_cgemm_split(n, fmt, S, P[cur], nullptr, static_cast<float*>(d_U), stream);
+            });
+        }
+        if (e != hipSuccess) return device_fail("cgemm_split", e);
+    }
+    return QSIM_OK;
 }
 
 }  // namespace qsim
@@ -432,22 +464,39 @@ qsim_status qsim_step_multiply(qsim_ctx* ctx, int n_qubits, int prec, const void
     if (!valid_n(n_qubits)) return fail(QSIM_E_RANGE, "n_qubits %d outside 1..%d", n_qubits, QSIM_MAX_QUBITS);
     if (!valid_prec(prec)) return fail(QSIM_E_INVALID, "unknown precision %d", prec);
     if (!built_prec(prec)) return fail(QSIM_E_INVALID, "precision %d is not available in this build", prec);
-    if (!d_S || !d_Uin || !d_Uout || !aligned(d_S) || !aligned(d_Uin) || !aligned(d_Uout))
-        return fail(QSIM_E_INVALID, "matrix pointer is NULL or not 256-byte aligned");
-    if (d_Uout == d_S || d_Uout == d_Uin) return fail(QSIM_E_INVALID, "d_Uout aliases an input");
     const OpFormat fmt = format_of(prec);
-    if (d_Uout_split && (fmt == FMT_F32 || !aligned(d_Uout_split) || d_Uout_split == d_S || d_Uout_split == d_Uin ||
-                         d_Uout_split == d_Uout))
-        return fail(QSIM_E_INVALID, "d_Uout_split must be NULL for float32 precisions, aligned and not aliased");
+    if (!d_S || !d_Uin || !aligned(d_S) || !aligned(d_Uin))
+        return fail(QSIM_E_INVALID, "d_S / d_Uin is NULL or not 256-byte aligned");
+    if (fmt == FMT_F32 && (d_Uout == nullptr || d_Uout_split != nullptr))
+        return fail(QSIM_E_INVALID, "float32 precisions write d_Uout only (d_Uout_split must be NULL)");
+    if (fmt != FMT_F32 && d_Uout == nullptr && d_Uout_split == nullptr)
+        return fail(QSIM_E_INVALID, "split precisions need d_Uout and/or d_Uout_split");
+    for (const void* o : {static_cast<const void*>(d_Uout), static_cast<const void*>(d_Uout_split)}) {
+        if (o == nullptr) continue;
+        if (!aligned(o)) return fail(QSIM_E_INVALID, "output not 256-byte aligned");
+        if (o == d_S || o == d_Uin) return fail(QSIM_E_INVALID, "an output aliases an input");
+    }
+    if (d_Uout && d_Uout == d_Uout_split) return fail(QSIM_E_INVALID, "the two outputs alias");
     s = check_ctx(ctx);
     if (s != QSIM_OK) return s;
     DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return device_fail("hipSetDevice", g.err);
     hipStream_t hs = static_cast<hipStream_t>(stream);
-    hipError_t e = timed(ctx->prof, QSIM_PROFILE_PRODUCT, hs, [&] {
-        return launch_cgemm_f32(n_qubits, prec == QSIM_FP32_3M, static_cast<const float*>(d_S),
-                                static_cast<const float*>(d_Uin), static_cast<float*>(d_Uout), hs);
-    });
+    hipError_t e = hipSuccess;
+    if (fmt == FMT_F32) {
+        e = timed(ctx->prof, QSIM_PROFILE_PRODUCT, hs, [&] {
+            return launch_cgemm_f32(n_qubits, prec == QSIM_FP32_3M, static_cast<const float*>(d_S),
+                                    static_cast<const float*>(d_Uin), static_cast<float*>(d_Uout), hs);
+        });
+    } else {
+        if (d_Uout_split)
+            e = timed(ctx->prof, QSIM_PROFILE_PRODUCT, hs,
+                      [&] { return launch_cgemm_split(n_qubits, fmt, d_Uin, d_S, d_Uout_split, nullptr, hs); });
+        if (e == hipSuccess && d_Uout)
+            e = timed(ctx->prof, QSIM_PROFILE_PRODUCT, hs, [&] {
+                return launch_cgemm_split(n_qubits, fmt, d_S, d_Uin, nullptr, static_cast<float*>(d_Uout), hs);
+            });
+    }
     return e == hipSuccess ? ok() : device_fail("cgemm launch", e);
 }
 

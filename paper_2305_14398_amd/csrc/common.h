@@ -40,6 +40,9 @@ hipError_t launch_expand_step(const DevStep& st, int n, int layout_col, OpFormat
                               hipStream_t stream);
 hipError_t launch_cgemm_f32(int n, bool gauss, const float* S_col, const float* U_row, float* C_row,
                             hipStream_t stream);
+// D = X Y^T over split operands (see cgemm_split.hip); D_split and/or D_f32 row-major.
+hipError_t launch_cgemm_split(int n, OpFormat fmt, const void* X, const void* Y, void* D_split, float* D_f32,
+                              hipStream_t stream);
 hipError_t launch_apply_state(int n, const float* U_row, const float* psi0, float* psi, double* prob,
                               double* d_norm2, hipStream_t stream);
 hipError_t launch_drift(int n, const float* U_row, double* partials, int max_partials, double* d_out,
