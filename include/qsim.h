@@ -183,6 +183,58 @@ qsim_status qsim_apply_state(qsim_ctx* ctx, int n_qubits, const void* d_U, const
 qsim_status qsim_unitarity_drift(qsim_ctx* ctx, int n_qubits, const void* d_U, double* h_out,
                                  void* stream);
 
+/* ---- Batches of circuits of mixed size (stages 4-5 for many circuits) ----
+ * One iteration of a batch expands the current step of every circuit that has
+ * one in a single grouped launch, then takes every such circuit's current
+ * chain product in a single grouped launch (persistent grid over a device job
+ * table; each circuit keeps its own size and tile configuration).  Results
+ * are the same products as qsim_unitary_chain with the same precision and
+ * tile configuration, circuit by circuit. */
+typedef struct qsim_circuit_desc {
+    int32_t n_qubits;
+    int32_t n_gates;
+    const qsim_gate* gates;       /* copied at plan creation */
+    const int32_t* step_offsets;  /* NULL: the qsim_pack_steps rule; else n_steps+1 offsets */
+    int32_t n_steps;
+    int32_t reserved;             /* must be 0 */
+    void* d_U;                    /* out: row-major planar complex64 U (8*N*N bytes, 256-byte aligned) */
+} qsim_circuit_desc;
+
+#define QSIM_BATCH_GRAPH 1  /* capture the plan's launches in a hipGraph at first launch and replay it */
+
+typedef struct qsim_batch_plan qsim_batch_plan;
+
+/* Workspace a batch needs (2 matrices per circuit for float32, 3 for split precisions, each rounded up to 256 bytes). */
+qsim_status qsim_batch_workspace_bytes(const qsim_circuit_desc* circuits, int count, int prec, size_t* out);
+/* Validate the batch, build and upload the job tables of every iteration (this
+ * allocates the tables on the device; launching allocates nothing).  The
+ * workspace and every d_U must stay valid and untouched by others for the
+ * plan's lifetime; d_U ranges must not overlap each other or the workspace. */
+qsim_status qsim_batch_plan_create(qsim_ctx* ctx, const qsim_circuit_desc* circuits, int count, int prec, void* d_ws,
+                                   size_t ws_bytes, int flags, qsim_batch_plan** out);
+/* Enqueue the whole batch on `stream` (2 grouped kernels per iteration, or one graph launch with QSIM_BATCH_GRAPH). */
+qsim_status qsim_batch_plan_launch(qsim_batch_plan* plan, void* stream);
+/* Iterations, number of chain products and their flop count (8 N^3 each). */
+qsim_status qsim_batch_plan_info(const qsim_batch_plan* plan, int* iterations, int* products, double* flops);
+/* Wait for the device and free the plan's tables and graph.  NULL is a no-op. */
+qsim_status qsim_batch_plan_destroy(qsim_batch_plan* plan);
+/* One-shot batch: create, launch, synchronise the stream, destroy. */
+qsim_status qsim_unitary_chain_batched(qsim_ctx* ctx, const qsim_circuit_desc* circuits, int count, int prec,
+                                       void* d_ws, size_t ws_bytes, void* stream);
+
+/* ---- Tile autotuner ----
+ * For n in [max(n_lo, 6), n_hi] (n_hi <= 13) times grouped launches of
+ * identical products with 64x64 and 128x128 tiles and records the faster tile
+ * edge per n in the context (used by every later product of that precision
+ * family: float32, split bf16 or split fp16; split fp16 always uses 64).  ms_out (nullable, 2 doubles per n from 6):
+ * milliseconds per product for tile 64 and tile 128 (-1 if not applicable).
+ * Synchronises; allocates scratch for the timing runs. */
+qsim_status qsim_autotune(qsim_ctx* ctx, int prec, int n_lo, int n_hi, double* ms_out);
+/* Current tile edge per qubit count (17 ints, index n; 0 = whole-product path). */
+qsim_status qsim_tune_get(qsim_ctx* ctx, int prec, int* tiles_out);
+/* Override the tile edge (64 or 128; split fp16: 64 only) for n in 7..16. */
+qsim_status qsim_tune_set(qsim_ctx* ctx, int prec, int n_qubits, int tile);
+
 /* Kernel timing with HIP events (instrumentation, not part of the method).
  * While enabled, every launch the context makes is bracketed by two events
  * recorded on the launch stream; qsim_profile_read waits for the timed

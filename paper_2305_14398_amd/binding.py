@@ -45,6 +45,15 @@ class qsim_kernel_stats(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int64 * 4), ("total_ms", ctypes.c_double * 4)]
 
 
+class qsim_circuit_desc(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_int32), ("n_gates", ctypes.c_int32), ("gates", ctypes.POINTER(qsim_gate)),
+                ("step_offsets", ctypes.POINTER(ctypes.c_int32)), ("n_steps", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("d_U", ctypes.c_void_p)]
+
+
+QSIM_BATCH_GRAPH = 1
+
+
 class QsimError(RuntimeError):
     def __init__(self, status: int, message: str, call: str):
         super().__init__(f"{call}: {STATUS_NAMES.get(status, status)}: {message}")
@@ -79,6 +88,16 @@ def lib() -> ctypes.CDLL:
         "qsim_apply_state": (i32, [vp, i32, vp, vp, vp, vp, ctypes.POINTER(dbl), vp]),
         "qsim_unitarity_drift": (i32, [vp, i32, vp, ctypes.POINTER(dbl), vp]),
         "qsim_profile_enable": (i32, [vp, i32]),
+        "qsim_batch_workspace_bytes": (i32, [ctypes.POINTER(qsim_circuit_desc), i32, i32, ctypes.POINTER(sz)]),
+        "qsim_batch_plan_create": (i32, [vp, ctypes.POINTER(qsim_circuit_desc), i32, i32, vp, sz, i32,
+                                         ctypes.POINTER(vp)]),
+        "qsim_batch_plan_launch": (i32, [vp, vp]),
+        "qsim_batch_plan_info": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(dbl)]),
+        "qsim_batch_plan_destroy": (i32, [vp]),
+        "qsim_unitary_chain_batched": (i32, [vp, ctypes.POINTER(qsim_circuit_desc), i32, i32, vp, sz, vp]),
+        "qsim_autotune": (i32, [vp, i32, i32, i32, ctypes.POINTER(dbl)]),
+        "qsim_tune_get": (i32, [vp, i32, ctypes.POINTER(i32)]),
+        "qsim_tune_set": (i32, [vp, i32, i32, i32]),
         "qsim_profile_read": (i32, [vp, ctypes.POINTER(qsim_kernel_stats)]),
     }
     for name, (res, args) in sigs.items():
@@ -259,3 +278,94 @@ def qsim_profile_read(ctx) -> dict:
     st = qsim_kernel_stats()
     _check(lib().qsim_profile_read(_h(ctx), ctypes.byref(st)), "qsim_profile_read")
     return {k: (int(st.count[i]), float(st.total_ms[i])) for i, k in enumerate(PROFILE_KINDS)}
+
+
+# --- batches -------------------------------------------------------------------------------
+
+def circuit_descs(circuits: Sequence, outputs: Sequence):
+    """Marshal (n_qubits, gates) pairs and their output buffers into a qsim_circuit_desc array.
+    Returns the array and the gate arrays it points into (keep both alive across the call)."""
+    arr = (qsim_circuit_desc * len(circuits))()
+    keep = []
+    for i, (c, U) in enumerate(zip(circuits, outputs)):
+        n, gates = (c.n, c.gates) if hasattr(c, "n") else c
+        g, ng = gate_array(gates)
+        keep.append(g)
+        arr[i].n_qubits = n
+        arr[i].n_gates = ng
+        arr[i].gates = ctypes.cast(g, ctypes.POINTER(qsim_gate))
+        arr[i].step_offsets = None
+        arr[i].n_steps = 0
+        arr[i].reserved = 0
+        arr[i].d_U = _ptr(U)
+    return arr, keep
+
+
+def qsim_batch_workspace_bytes(circuits: Sequence, prec: int) -> int:
+    arr, _keep = circuit_descs(circuits, [0] * len(circuits))
+    out = ctypes.c_size_t()
+    _check(lib().qsim_batch_workspace_bytes(arr, len(circuits), prec, ctypes.byref(out)), "qsim_batch_workspace_bytes")
+    return int(out.value)
+
+
+class BatchPlan:
+    """qsim_batch_plan_create / _launch / _info / _destroy."""
+
+    def __init__(self, ctx, circuits: Sequence, outputs: Sequence, prec: int, d_ws, ws_bytes: Optional[int] = None,
+                 graph: bool = False):
+        arr, _keep = circuit_descs(circuits, outputs)
+        if ws_bytes is None:
+            ws_bytes = d_ws.numel() * d_ws.element_size() if hasattr(d_ws, "numel") else 0
+        out = ctypes.c_void_p()
+        _check(lib().qsim_batch_plan_create(_h(ctx), arr, len(circuits), prec, _ptr(d_ws), ws_bytes,
+                                            QSIM_BATCH_GRAPH if graph else 0, ctypes.byref(out)),
+               "qsim_batch_plan_create")
+        self.handle = out.value
+        self.device = _dev(ctx)
+
+    def launch(self, stream=None):
+        _check(lib().qsim_batch_plan_launch(self.handle, _stream(stream, self.device)), "qsim_batch_plan_launch")
+
+    def info(self):
+        it, pr, fl = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        _check(lib().qsim_batch_plan_info(self.handle, ctypes.byref(it), ctypes.byref(pr), ctypes.byref(fl)),
+               "qsim_batch_plan_info")
+        return {"iterations": it.value, "products": pr.value, "flops": fl.value}
+
+    def close(self):
+        if self.handle:
+            _check(lib().qsim_batch_plan_destroy(self.handle), "qsim_batch_plan_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def qsim_unitary_chain_batched(ctx, circuits: Sequence, outputs: Sequence, prec: int, d_ws,
+                               ws_bytes: Optional[int] = None, stream=None) -> None:
+    arr, _keep = circuit_descs(circuits, outputs)
+    if ws_bytes is None:
+        ws_bytes = d_ws.numel() * d_ws.element_size() if hasattr(d_ws, "numel") else 0
+    st = _stream(stream, _dev(ctx)) if _h(ctx) else None
+    _check(lib().qsim_unitary_chain_batched(_h(ctx), arr, len(circuits), prec, _ptr(d_ws), ws_bytes, st),
+           "qsim_unitary_chain_batched")
+
+
+def qsim_autotune(ctx, prec: int, n_lo: int = 6, n_hi: int = 11) -> dict:
+    """Returns {n: (ms per product with 64-tiles, with 128-tiles)} and stores the choice in the context."""
+    out = (ctypes.c_double * (2 * (n_hi - 5)))()
+    _check(lib().qsim_autotune(_h(ctx), prec, n_lo, n_hi, out), "qsim_autotune")
+    return {n: (out[2 * (n - 6)], out[2 * (n - 6) + 1]) for n in range(max(6, n_lo), n_hi + 1)}
+
+
+def qsim_tune_get(ctx, prec: int) -> list:
+    out = (ctypes.c_int * 17)()
+    _check(lib().qsim_tune_get(_h(ctx), prec, out), "qsim_tune_get")
+    return list(out)
+
+
+def qsim_tune_set(ctx, prec: int, n_qubits: int, tile: int) -> None:
+    _check(lib().qsim_tune_set(_h(ctx), prec, n_qubits, tile), "qsim_tune_set")

@@ -8,13 +8,17 @@
 #include <string>
 #include <vector>
 
-#include "common.h"
+#include "host.h"
 
 using namespace qsim;
 
-namespace {
+namespace qsim {
 
+namespace {
 thread_local std::string g_last_error = "no error";
+}  // namespace
+
+const std::string& last_error_text() { return g_last_error; }
 
 qsim_status fail(qsim_status st, const char* fmt, ...) {
     char buf[512];
@@ -37,28 +41,14 @@ qsim_status device_fail(const char* what, hipError_t e) {
 
 bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
 
-// Makes `dev` current for the lifetime of the guard and restores the caller's device.
-struct DeviceGuard {
-    int prev = -1;
-    hipError_t err = hipSuccess;
-    explicit DeviceGuard(int dev) {
-        err = hipGetDevice(&prev);
-        if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
-    }
-    ~DeviceGuard() {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
-
 bool valid_n(int n) { return n >= 1 && n <= QSIM_MAX_QUBITS; }
 
 bool valid_prec(int p) { return p >= QSIM_FP32_4M && p <= QSIM_SPLIT_FP16; }
 
 // Precisions with a kernel in this build.
-bool built_prec(int p) { return valid_prec(p); }
+static bool built_prec(int p) { return valid_prec(p); }
 
-qsim_status check_gate(int n, const qsim_gate& g, int idx) {
+static qsim_status check_gate(int n, const qsim_gate& g, int idx) {
     if (g.kind < QSIM_H || g.kind > QSIM_SWAP) return fail(QSIM_E_INVALID, "gate %d: unknown kind %d", idx, g.kind);
     if (g.reserved != 0) return fail(QSIM_E_INVALID, "gate %d: reserved field must be 0", idx);
     if (g.target < 0 || g.target >= n)
@@ -95,7 +85,7 @@ qsim_status check_gates(int n, const qsim_gate* gates, int n_gates) {
     return QSIM_OK;
 }
 
-void span_of(const qsim_gate& g, int& lo, int& hi) {
+static void span_of(const qsim_gate& g, int& lo, int& hi) {
     lo = g.target;
     hi = g.target;
     if (g.control >= 0) {
@@ -104,14 +94,14 @@ void span_of(const qsim_gate& g, int& lo, int& hi) {
     }
 }
 
-uint32_t span_mask(const qsim_gate& g) {
+static uint32_t span_mask(const qsim_gate& g) {
     int lo, hi;
     span_of(g, lo, hi);
     return (uint32_t)(((1ull << (hi + 1)) - 1) & ~((1ull << lo) - 1));
 }
 
 // 2x2 float64 matrix of a gate kind, rows = output bit, (re, im) pairs.
-void gate_matrix(const qsim_gate& g, double m[8]) {
+static void gate_matrix(const qsim_gate& g, double m[8]) {
     const double r2 = 0.70710678118654752440;
     for (int i = 0; i < 8; ++i) m[i] = 0.0;
     auto set = [&](int idx, double re, double im) {
@@ -216,82 +206,8 @@ qsim_status check_offsets(const int32_t* off, int n_steps, int n_gates) {
     return QSIM_OK;
 }
 
-size_t mat_bytes(int n) { return (size_t)8 << (2 * n); }
 
-}  // namespace
 
-namespace qsim {
-
-// Optional per-launch timing with HIP events recorded on the launch stream
-// around each kernel (qsim_profile_enable / qsim_profile_read).  Used from one
-// host thread at a time.
-struct Profiler {
-    struct Pending {
-        int kind;
-        hipEvent_t a, b;
-    };
-    std::vector<hipEvent_t> pool;
-    std::vector<Pending> pending;
-    double total_ms[QSIM_PROFILE_KINDS] = {};
-    int64_t count[QSIM_PROFILE_KINDS] = {};
-
-    hipEvent_t get() {
-        if (!pool.empty()) {
-            hipEvent_t e = pool.back();
-            pool.pop_back();
-            return e;
-        }
-        hipEvent_t e = nullptr;
-        (void)hipEventCreate(&e);
-        return e;
-    }
-    hipError_t collect() {
-        hipError_t err = hipSuccess;
-        for (auto& p : pending) {
-            float ms = 0.f;
-            hipError_t e = hipEventSynchronize(p.b);
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, p.a, p.b);
-            if (e == hipSuccess) {
-                total_ms[p.kind] += ms;
-                count[p.kind] += 1;
-            } else {
-                err = e;
-            }
-            pool.push_back(p.a);
-            pool.push_back(p.b);
-        }
-        pending.clear();
-        return err;
-    }
-    ~Profiler() {
-        (void)collect();
-        for (auto e : pool) (void)hipEventDestroy(e);
-    }
-};
-
-// Runs `launch` (returning hipError_t) bracketed by events when profiling.
-template <class F>
-hipError_t timed(Profiler* prof, int kind, hipStream_t s, F&& launch) {
-    if (prof == nullptr) return launch();
-    hipEvent_t a = prof->get(), b = prof->get();
-    (void)hipEventRecord(a, s);
-    hipError_t e = launch();
-    (void)hipEventRecord(b, s);
-    prof->pending.push_back({kind, a, b});
-    return e;
-}
-
-}  // namespace qsim
-
-struct qsim_ctx {
-    int device = 0;
-    double* d_scratch = nullptr;  // [0] norm2, [2..3] drift result, [8..] drift partials
-    qsim::Profiler* prof = nullptr;
-};
-
-namespace {
-
-constexpr size_t kScratchDoubles = 8 + 2 * kDriftMaxPartials;
 
 qsim_status check_ctx(qsim_ctx* ctx) {
     if (ctx == nullptr) return fail(QSIM_E_INVALID, "context is NULL");
@@ -300,13 +216,14 @@ qsim_status check_ctx(qsim_ctx* ctx) {
     return QSIM_OK;
 }
 
-}  // namespace
+}  // namespace qsim
 
 namespace qsim {
 
 // Shared by the synchronous entry points and the serving engine.
 qsim_status chain_impl(int n, const qsim_gate* gates, int n_gates, const int32_t* off, int n_steps, int prec, void* d_U,
-                       void* d_ws, hipStream_t stream, Profiler* prof) {
+                       void* d_ws, hipStream_t stream, Profiler* prof, const TuneTable& tune) {
+    const int tile = tune.get(prec, n);
     const size_t mb = mat_bytes(n);
     const OpFormat fmt = format_of(prec);
     DevStep st;
@@ -337,7 +254,7 @@ qsim_status chain_impl(int n, const qsim_gate* gates, int n_gates, const int32_t
             if (e != hipSuccess) return device_fail("expand", e);
             void* nxt = X[(k - 1 - j) & 1];
             e = timed(prof, QSIM_PROFILE_PRODUCT, stream, [&] {
-                return launch_cgemm_f32(n, prec == QSIM_FP32_3M, static_cast<const float*>(S),
+                return launch_cgemm_f32(n, prec == QSIM_FP32_3M, tile, static_cast<const float*>(S),
                                         static_cast<const float*>(cur), static_cast<float*>(nxt), stream);
             });
             if (e != hipSuccess) return device_fail("cgemm", e);
@@ -368,11 +285,11 @@ qsim_status chain_impl(int n, const qsim_gate* gates, int n_gates, const int32_t
         if (e != hipSuccess) return device_fail("expand", e);
         if (j < k - 1) {
             e = timed(prof, QSIM_PROFILE_PRODUCT, stream,
-                      [&] { return launch_cgemm_split(n, fmt, P[cur], S, P[cur ^ 1], nullptr, stream); });
+                      [&] { return launch_cgemm_split(n, fmt, tile, P[cur], S, P[cur ^ 1], nullptr, stream); });
             cur ^= 1;
         } else {
             e = timed(prof, QSIM_PROFILE_PRODUCT, stream, [&] {
-                return launch_cgemm_split(n, fmt, S, P[cur], nullptr, static_cast<float*>(d_U), stream);
+                return launch_cgemm_split(n, fmt, tile, S, P[cur], nullptr, static_cast<float*>(d_U), stream);
             });
         }
         if (e != hipSuccess) return device_fail("cgemm_split", e);
@@ -384,7 +301,7 @@ qsim_status chain_impl(int n, const qsim_gate* gates, int n_gates, const int32_t
 
 extern "C" {
 
-const char* qsim_last_error(void) { return g_last_error.c_str(); }
+const char* qsim_last_error(void) { return last_error_text().c_str(); }
 
 const char* qsim_version(void) { return "libqsim 0.1 (gfx950)"; }
 
@@ -482,19 +399,20 @@ qsim_status qsim_step_multiply(qsim_ctx* ctx, int n_qubits, int prec, const void
     DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return device_fail("hipSetDevice", g.err);
     hipStream_t hs = static_cast<hipStream_t>(stream);
+    const int tile = ctx->tune.get(prec, n_qubits);
     hipError_t e = hipSuccess;
     if (fmt == FMT_F32) {
         e = timed(ctx->prof, QSIM_PROFILE_PRODUCT, hs, [&] {
-            return launch_cgemm_f32(n_qubits, prec == QSIM_FP32_3M, static_cast<const float*>(d_S),
+            return launch_cgemm_f32(n_qubits, prec == QSIM_FP32_3M, tile, static_cast<const float*>(d_S),
                                     static_cast<const float*>(d_Uin), static_cast<float*>(d_Uout), hs);
         });
     } else {
         if (d_Uout_split)
             e = timed(ctx->prof, QSIM_PROFILE_PRODUCT, hs,
-                      [&] { return launch_cgemm_split(n_qubits, fmt, d_Uin, d_S, d_Uout_split, nullptr, hs); });
+                      [&] { return launch_cgemm_split(n_qubits, fmt, tile, d_Uin, d_S, d_Uout_split, nullptr, hs); });
         if (e == hipSuccess && d_Uout)
             e = timed(ctx->prof, QSIM_PROFILE_PRODUCT, hs, [&] {
-                return launch_cgemm_split(n_qubits, fmt, d_S, d_Uin, nullptr, static_cast<float*>(d_Uout), hs);
+                return launch_cgemm_split(n_qubits, fmt, tile, d_S, d_Uin, nullptr, static_cast<float*>(d_Uout), hs);
             });
     }
     return e == hipSuccess ? ok() : device_fail("cgemm launch", e);
@@ -532,13 +450,14 @@ qsim_status qsim_unitary_chain(qsim_ctx* ctx, int n_qubits, const qsim_gate* gat
     DevStep st;
     for (int j = 0; j < k; ++j) {
         s = make_step(n_qubits, gates + off[j], off[j + 1] - off[j], st);
-        if (s != QSIM_OK) return fail(s, "step %d: %s", j, g_last_error.c_str());
+        if (s != QSIM_OK) return fail(s, "step %d: %s", j, last_error_text().c_str());
     }
     s = check_ctx(ctx);
     if (s != QSIM_OK) return s;
     DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return device_fail("hipSetDevice", g.err);
-    s = chain_impl(n_qubits, gates, n_gates, off.data(), k, prec, d_U, d_ws, static_cast<hipStream_t>(stream), ctx->prof);
+    s = chain_impl(n_qubits, gates, n_gates, off.data(), k, prec, d_U, d_ws, static_cast<hipStream_t>(stream), ctx->prof,
+                   ctx->tune);
     return s == QSIM_OK ? ok() : s;
 }
 

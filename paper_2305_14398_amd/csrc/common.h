@@ -28,6 +28,35 @@ struct DevStep {
     DevGate g[QSIM_MAX_GATES_PER_STEP];
 };
 
+// One step operator to expand inside a grouped launch.  Job j owns the
+// workgroup-iterations [block_begin, block_begin + blocks) of the launch.
+struct ExpandJob {
+    DevStep st;
+    void* out;
+    int32_t n;
+    int32_t layout_col;
+    int32_t fmt;  // OpFormat
+    int32_t block_begin;
+    int32_t blocks;
+    int32_t pad[3];
+};
+
+// One chain product inside a grouped launch (all jobs of a launch share the
+// arithmetic family).  float32: X = S column-major, Y = U row-major, D0 = C
+// row-major.  Split: D = X Y^T with D0 = split output, D1 = float32 output
+// (either may be null).  cfg: 0 = whole product by one workgroup (n <= 5),
+// 64 or 128 = MFMA tile edge.  Job j owns tiles [tile_begin, tile_begin + tiles).
+struct GemmJob {
+    const void* X;
+    const void* Y;
+    void* D0;
+    void* D1;
+    int32_t n;
+    int32_t cfg;
+    int32_t tile_begin;
+    int32_t tiles;
+};
+
 // Output formats of the expansion kernel and operand formats of the GEMMs.
 enum OpFormat : int { FMT_F32 = 0, FMT_BF16 = 1, FMT_F16 = 2 };
 
@@ -35,14 +64,26 @@ inline OpFormat format_of(int prec) {
     return prec == QSIM_SPLIT_BF16 ? FMT_BF16 : prec == QSIM_SPLIT_FP16 ? FMT_F16 : FMT_F32;
 }
 
+// float32 -> bfloat16, round to nearest even (inputs are finite).
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
 // ---- kernel launchers (each returns the launch status) ----
 hipError_t launch_expand_step(const DevStep& st, int n, int layout_col, OpFormat fmt, void* out,
                               hipStream_t stream);
-hipError_t launch_cgemm_f32(int n, bool gauss, const float* S_col, const float* U_row, float* C_row,
+hipError_t launch_cgemm_f32(int n, bool gauss, int tile, const float* S_col, const float* U_row, float* C_row,
                             hipStream_t stream);
 // D = X Y^T over split operands (see cgemm_split.hip); D_split and/or D_f32 row-major.
-hipError_t launch_cgemm_split(int n, OpFormat fmt, const void* X, const void* Y, void* D_split, float* D_f32,
-                              hipStream_t stream);
+hipError_t launch_cgemm_split(int n, OpFormat fmt, int tile, const void* X, const void* Y, void* D_split,
+                              float* D_f32, hipStream_t stream);
+// Grouped launches over device job tables (grouped.hip).  `grid` workgroups
+// loop over the `total` tiles / expansion blocks.
+hipError_t launch_grouped_expand(const ExpandJob* jobs, int njobs, int total_blocks, int grid, hipStream_t stream);
+hipError_t launch_grouped_gemm(int prec, const GemmJob* jobs, int njobs, int total_tiles, int grid,
+                               hipStream_t stream);
 hipError_t launch_apply_state(int n, const float* U_row, const float* psi0, float* psi, double* prob,
                               double* d_norm2, hipStream_t stream);
 hipError_t launch_drift(int n, const float* U_row, double* partials, int max_partials, double* d_out,

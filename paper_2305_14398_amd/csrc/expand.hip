@@ -1,130 +1,19 @@
 // Stage 4 of the unitary method (Section 5.3; Algorithm 2; Eq. 9s1): write the
-// dense 2^n x 2^n operator of one circuit step.
-//
-// The Kronecker product of the step's gates with identities on idle qubits has
-// the per-entry form (little-endian, r_q = bit q of the row index r, s_q of
-// the column index s):
-//   idle qubit q            : [r_q == s_q]
-//   one-qubit gate G on q   : G[r_q][s_q]
-//   controlled-U (c -> t)   : [r_c == s_c] * (s_c == 0 ? [r_t == s_t] : U[r_t][s_t])   (Eq. 7)
-//   SWAP(a, b)              : [r_a == s_b] * [r_b == s_a]
-// and the entry is the product of these factors.  Every entry is computed in
-// float64 and rounded once to the output format, so the kernel is a pure
-// streaming writer: 8 bytes of HBM traffic per entry and no reads.
-#include "common.h"
+// dense 2^n x 2^n operator of one circuit step.  The per-entry rule is in
+// expand_entry.h; the kernel is a pure streaming writer (8 bytes of HBM
+// traffic per entry, no reads).
+#include "expand_entry.h"
 
 namespace qsim {
 namespace {
 
-__device__ __forceinline__ double sel4(int idx, double a, double b, double c, double d) {
-    return idx == 0 ? a : idx == 1 ? b : idx == 2 ? c : d;
-}
-
-// Entry (r, s) of the step operator in float64.  All reads of `st` use a
-// wave-uniform gate index, so they stay scalar loads from the kernel argument
-// segment; the per-lane choice of matrix entry is a select.
-__device__ __forceinline__ void step_entry(const DevStep& st, uint32_t r, uint32_t s, double& out_re,
-                                           double& out_im) {
-    double pr = 1.0, pi = 0.0;
-    bool zero = ((r ^ s) & st.idle_mask) != 0;
-    for (int g = 0; g < st.n_gates; ++g) {
-        const int type = st.g[g].type;
-        const int q0 = st.g[g].q0, q1 = st.g[g].q1;
-        int idx = 0;
-        bool use = true;
-        if (type == GATE_ONE) {
-            idx = (((r >> q0) & 1u) << 1) | ((s >> q0) & 1u);
-        } else if (type == GATE_CTRL) {
-            const uint32_t rc = (r >> q0) & 1u, sc = (s >> q0) & 1u;
-            const uint32_t rt = (r >> q1) & 1u, stt = (s >> q1) & 1u;
-            zero |= rc != sc;
-            if (sc == 0) {
-                zero |= rt != stt;
-                use = false;
-            }
-            idx = (int)((rt << 1) | stt);
-        } else {  // GATE_SWAP
-            zero |= ((r >> q0) & 1u) != ((s >> q1) & 1u);
-            zero |= ((r >> q1) & 1u) != ((s >> q0) & 1u);
-            use = false;
-        }
-        if (use) {
-            const double* m = st.g[g].m;
-            const double ar = sel4(idx, m[0], m[2], m[4], m[6]);
-            const double ai = sel4(idx, m[1], m[3], m[5], m[7]);
-            const double t = pr * ar - pi * ai;
-            pi = pr * ai + pi * ar;
-            pr = t;
-        }
-    }
-    out_re = zero ? 0.0 : pr;
-    out_im = zero ? 0.0 : pi;
-}
-
-__device__ __forceinline__ uint16_t bf16_rne(float f) {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-
-__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
-
-// Split a float64 value into 16-bit hi + lo with value ~= hi + lo * 2^-shift.
-template <int FMT>
-__device__ __forceinline__ void split16(double v, uint16_t& hi, uint16_t& lo) {
-    if (FMT == FMT_BF16) {
-        hi = bf16_rne((float)v);
-        lo = bf16_rne((float)(v - (double)bf16_to_f32(hi)));
-    } else {
-        _Float16 h = (_Float16)(float)v;
-        _Float16 l = (_Float16)(float)((v - (double)(float)h) * (double)(1 << QSIM_LO_SCALE_LOG2));
-        hi = __builtin_bit_cast(uint16_t, h);
-        lo = __builtin_bit_cast(uint16_t, l);
-    }
-}
-
 // Each work item writes 4 consecutive storage entries (one row holds fewer
-// than 4 only when N = 2); the grid strides over all N*N/4 items.  Storage
-// (a, b) holds logical entry (r, s) = (a, b) for row-major output and (b, a)
-// for column-major.
+// than 4 only when N = 2); the grid strides over all N*N/4 items.
 template <int FMT>
 __global__ __launch_bounds__(256) void expand_step_kernel(DevStep st, int n, int layout_col, void* out) {
-    const uint64_t N = 1ull << n;
-    const uint64_t NN = N * N;
-    const uint64_t items = NN >> 2;
-    for (uint64_t it = (uint64_t)blockIdx.x * 256u + threadIdx.x; it < items; it += (uint64_t)gridDim.x * 256u) {
-        const uint64_t e0 = it << 2;
-        double vr[4], vi[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const uint32_t a = (uint32_t)((e0 + c) >> n);
-            const uint32_t b = (uint32_t)((e0 + c) & (N - 1));
-            const uint32_t r = layout_col ? b : a;
-            const uint32_t s = layout_col ? a : b;
-            step_entry(st, r, s, vr[c], vi[c]);
-        }
-        if (FMT == FMT_F32) {
-            float* o = reinterpret_cast<float*>(out);
-            *reinterpret_cast<float4*>(o + e0) = make_float4((float)vr[0], (float)vr[1], (float)vr[2], (float)vr[3]);
-            *reinterpret_cast<float4*>(o + NN + e0) =
-                make_float4((float)vi[0], (float)vi[1], (float)vi[2], (float)vi[3]);
-        } else {
-            uint16_t rh[4], rl[4], ih[4], il[4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                split16<FMT>(vr[c], rh[c], rl[c]);
-                split16<FMT>(vi[c], ih[c], il[c]);
-            }
-            uint16_t* o = reinterpret_cast<uint16_t*>(out);
-            auto pack = [](const uint16_t* h) {
-                return make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16));
-            };
-            *reinterpret_cast<uint2*>(o + e0) = pack(rh);
-            *reinterpret_cast<uint2*>(o + NN + e0) = pack(rl);
-            *reinterpret_cast<uint2*>(o + 2 * NN + e0) = pack(ih);
-            *reinterpret_cast<uint2*>(o + 3 * NN + e0) = pack(il);
-        }
-    }
+    const uint64_t items = (1ull << (2 * n)) >> 2;
+    for (uint64_t it = (uint64_t)blockIdx.x * 256u + threadIdx.x; it < items; it += (uint64_t)gridDim.x * 256u)
+        expand_four<FMT>(st, n, layout_col, out, it << 2);
 }
 
 }  // namespace

@@ -1,0 +1,137 @@
+// Host-side internals of libqsim shared by the C ABI (api.hip), the batch
+// planner (batch.hip) and the serving engine (engine.hip).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace qsim {
+
+
+// --- status and validation (api.hip) ---
+qsim_status fail(qsim_status st, const char* fmt, ...);
+qsim_status ok();
+qsim_status device_fail(const char* what, hipError_t e);
+const std::string& last_error_text();
+bool aligned(const void* p);
+bool valid_n(int n);
+bool valid_prec(int p);
+qsim_status check_gates(int n, const qsim_gate* gates, int n_gates);
+qsim_status check_offsets(const int32_t* off, int n_steps, int n_gates);
+// Descriptor of one step (gates validated and pairwise span-disjoint).
+qsim_status make_step(int n, const qsim_gate* gates, int count, DevStep& st);
+// Step formation rule (see qsim_pack_steps).
+void pack(const qsim_gate* gates, int n_gates, std::vector<int32_t>& off);
+inline size_t mat_bytes(int n) { return (size_t)8 << (2 * n); }
+
+// Makes `dev` current for the lifetime of the guard and restores the caller's device.
+struct DeviceGuard {
+    int prev = -1;
+    hipError_t err = hipSuccess;
+    explicit DeviceGuard(int dev) {
+        err = hipGetDevice(&prev);
+        if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+// Optional per-launch timing with HIP events recorded on the launch stream
+// around each kernel (qsim_profile_enable / qsim_profile_read).  Used from one
+// host thread at a time.
+struct Profiler {
+    struct Pending {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<hipEvent_t> pool;
+    std::vector<Pending> pending;
+    double total_ms[QSIM_PROFILE_KINDS] = {};
+    int64_t count[QSIM_PROFILE_KINDS] = {};
+
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        (void)hipEventCreate(&e);
+        return e;
+    }
+    hipError_t collect() {
+        hipError_t err = hipSuccess;
+        for (auto& p : pending) {
+            float ms = 0.f;
+            hipError_t e = hipEventSynchronize(p.b);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, p.a, p.b);
+            if (e == hipSuccess) {
+                total_ms[p.kind] += ms;
+                count[p.kind] += 1;
+            } else {
+                err = e;
+            }
+            pool.push_back(p.a);
+            pool.push_back(p.b);
+        }
+        pending.clear();
+        return err;
+    }
+    ~Profiler() {
+        (void)collect();
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+// Runs `launch` (returning hipError_t) bracketed by events when profiling.
+template <class F>
+hipError_t timed(Profiler* prof, int kind, hipStream_t s, F&& launch) {
+    if (prof == nullptr) return launch();
+    hipEvent_t a = prof->get(), b = prof->get();
+    (void)hipEventRecord(a, s);
+    hipError_t e = launch();
+    (void)hipEventRecord(b, s);
+    prof->pending.push_back({kind, a, b});
+    return e;
+}
+
+
+// MFMA tile edge per qubit count, per arithmetic family (0 float32, 1 split
+// bf16, 2 split fp16); filled by the autotuner or by the default rule (128
+// for n >= 7, 64 for n = 6).  Split fp16 always uses 64: its 128-wide tile
+// needs every register and would spill inside the grouped kernel.
+struct TuneTable {
+    static int family(int prec) { return prec == QSIM_SPLIT_FP16 ? 2 : prec == QSIM_SPLIT_BF16 ? 1 : 0; }
+    int tile[3][QSIM_MAX_QUBITS + 1];
+    bool tuned[3];
+    TuneTable() {
+        for (int f = 0; f < 3; ++f) {
+            tuned[f] = false;
+            for (int n = 0; n <= QSIM_MAX_QUBITS; ++n) tile[f][n] = n >= 7 && f != 2 ? 128 : (n >= 6 ? 64 : 0);
+        }
+    }
+    int get(int prec, int n) const { return tile[family(prec)][n]; }
+};
+
+// Shared by the synchronous entry points and the serving engine.
+qsim_status chain_impl(int n, const qsim_gate* gates, int n_gates, const int32_t* off, int n_steps, int prec, void* d_U,
+                       void* d_ws, hipStream_t stream, Profiler* prof, const TuneTable& tune);
+
+constexpr size_t kScratchDoubles = 8 + 2 * kDriftMaxPartials;
+
+}  // namespace qsim
+
+struct qsim_ctx {
+    int device = 0;
+    double* d_scratch = nullptr;  // [0] norm2, [2..3] drift result, [8..] drift partials
+    qsim::Profiler* prof = nullptr;
+    qsim::TuneTable tune;
+};
+
+namespace qsim {
+qsim_status check_ctx(qsim_ctx* ctx);
+}  // namespace qsim

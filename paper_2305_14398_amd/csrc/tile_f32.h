@@ -1,0 +1,226 @@
+// One output tile of the float32 complex product of stage 5 (Section 5.3;
+// Algorithm 1, result <- A . result), shared by the single-problem kernel
+// (cgemm_f32.hip) and the grouped kernel (grouped.hip).
+//
+// C = A . B for N x N complex matrices held as float32 planes:
+//   A (the step operator) column-major: A[i][k] at A[k*N + i]
+//   B (the running product) row-major:  B[k][j] at B[k*N + j]
+//   C row-major.
+// Both operands are read as rows of length N indexed by k, so every global
+// load is a contiguous 16-byte vector and a K-tile lands in LDS as [k][m]
+// without a transpose.
+//
+// MFMA mapping (v_mfma_f32_32x32x2f32, 64 cycles, 4096 flops): lane l holds
+// A[m0 + l%32][k] and B[k][n0 + l%32] with k = kbase + 8*(l/32) (the two
+// k-slots of the instruction are taken 8 rows apart in the LDS tile, which
+// puts the two half-waves on disjoint LDS banks with a 4-float row pad).
+//   4M:  Cre += Ar.Br + (-Ai).Bi ;  Cim += Ar.Bi + Ai.Br        (4 MFMAs per k-pair)
+//   3M:  T1 += Ar.Br ; T2 += Ai.Bi ; T3 += (Ar+Ai).(Br+Bi)       (3 MFMAs per k-pair)
+//        Cre = T1 - T2 ;  Cim = T3 - T1 - T2
+// A workgroup of WM x WN waves computes a (32*WM*BMB) x (32*WN*BNB) tile of C;
+// each wave owns BMB x BNB blocks of 32x32.  K-tiles of 16 are double
+// buffered in LDS; the next tile's global loads are issued before the MFMAs
+// of the current one.  The tile ends with a barrier, so a persistent
+// workgroup may start its next tile in the same LDS right away.
+#pragma once
+
+#include "common.h"
+
+namespace qsim {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Tile (tm, tn) of local tile id t: ids run in groups of 4 tile-rows so that
+// consecutive ids share A and B panels.
+__device__ __forceinline__ void grouped_tile_order(int t, int tiles_m, int tiles_n, int& tm, int& tn) {
+    constexpr int GROUP_M = 4;
+    const int per_group = GROUP_M * tiles_n;
+    const int first_m = (t / per_group) * GROUP_M;
+    const int gsize = min(tiles_m - first_m, GROUP_M);
+    tm = first_m + (t % per_group) % gsize;
+    tn = (t % per_group) / gsize;
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs: renumber so that each
+// XCD receives a contiguous range of tile ids (whose panels then share that
+// XCD's L2).
+__device__ __forceinline__ int xcd_contiguous_id(int bid, int nblk) {
+    return ((nblk & 7) == 0) ? (bid & 7) * (nblk >> 3) + (bid >> 3) : bid;
+}
+
+template <int WM, int WN, int BMB, int BNB, bool GAUSS>
+struct F32Tile {
+    static constexpr int NT = 64 * WM * WN;
+    static constexpr int TM = 32 * WM * BMB;
+    static constexpr int TN = 32 * WN * BNB;
+    static constexpr int BK = 16;
+    static constexpr int LDA = TM + 4;
+    static constexpr int LDB = TN + 4;
+    static constexpr int A_V4 = BK * TM / 4 / NT;  // float4 loads per thread per plane
+    static constexpr int B_V4 = BK * TN / 4 / NT;
+    static_assert(A_V4 * NT * 4 == BK * TM && B_V4 * NT * 4 == BK * TN, "tile/thread mismatch");
+    static constexpr int NACC = GAUSS ? 3 : 2;
+    static constexpr int SMEM_FLOATS = 2 * 2 * BK * (LDA + LDB);
+
+    __device__ static void run(int n, const float* __restrict__ A, const float* __restrict__ B, float* __restrict__ C,
+                               int tm, int tn, float* smem) {
+        auto As = reinterpret_cast<float(*)[2][BK][LDA]>(smem);
+        auto Bs = reinterpret_cast<float(*)[2][BK][LDB]>(smem + 2 * 2 * BK * LDA);
+        const int N = 1 << n;
+        const size_t NN = (size_t)N * N;
+        const int i0 = tm * TM, j0 = tn * TN;
+        const int tid = threadIdx.x;
+        const int lane = tid & 63;
+        const int wave = tid >> 6;
+        const int wm = wave % WM, wn = wave / WM;
+        const int lrow = lane & 31;
+        const int khalf = (lane >> 5) * (BK / 2);
+
+        floatx16 acc[BMB][BNB][NACC];
+#pragma unroll
+        for (int x = 0; x < BMB; ++x)
+#pragma unroll
+            for (int y = 0; y < BNB; ++y)
+#pragma unroll
+                for (int z = 0; z < NACC; ++z)
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) acc[x][y][z][e] = 0.f;
+
+        // Per-thread slice of a K-tile: float4 number f = tid + NT*u of a plane
+        // covers row f / (T/4) and columns 4*(f % (T/4)) .. +3 of that tile.
+        floatx4 ra[2][A_V4], rb[2][B_V4];
+#define QSIM_GLOAD(k0)                                                                                   \
+    _Pragma("unroll") for (int p = 0; p < 2; ++p) {                                                      \
+        _Pragma("unroll") for (int u = 0; u < A_V4; ++u) {                                               \
+            const int f = tid + NT * u;                                                                   \
+            ra[p][u] = *reinterpret_cast<const floatx4*>(A + p * NN + (size_t)((k0) + f / (TM / 4)) * N + \
+                                                         i0 + (f % (TM / 4)) * 4);                        \
+        }                                                                                                 \
+        _Pragma("unroll") for (int u = 0; u < B_V4; ++u) {                                               \
+            const int f = tid + NT * u;                                                                   \
+            rb[p][u] = *reinterpret_cast<const floatx4*>(B + p * NN + (size_t)((k0) + f / (TN / 4)) * N + \
+                                                         j0 + (f % (TN / 4)) * 4);                        \
+        }                                                                                                 \
+    }
+#define QSIM_LSTORE(s)                                                                          \
+    _Pragma("unroll") for (int p = 0; p < 2; ++p) {                                             \
+        _Pragma("unroll") for (int u = 0; u < A_V4; ++u) {                                      \
+            const int f = tid + NT * u;                                                          \
+            *reinterpret_cast<floatx4*>(&As[s][p][f / (TM / 4)][(f % (TM / 4)) * 4]) = ra[p][u]; \
+        }                                                                                        \
+        _Pragma("unroll") for (int u = 0; u < B_V4; ++u) {                                      \
+            const int f = tid + NT * u;                                                          \
+            *reinterpret_cast<floatx4*>(&Bs[s][p][f / (TN / 4)][(f % (TN / 4)) * 4]) = rb[p][u]; \
+        }                                                                                        \
+    }
+
+        const int KT = N / BK;
+        QSIM_GLOAD(0);
+        QSIM_LSTORE(0);
+        __syncthreads();
+
+        for (int kt = 0; kt < KT; ++kt) {
+            const int cur = kt & 1;
+            if (kt + 1 < KT) { QSIM_GLOAD((kt + 1) * BK); }
+#pragma unroll
+            for (int t = 0; t < BK / 2; ++t) {
+                const int kk = t + khalf;
+                float ar[BMB], ai[BMB], br[BNB], bi[BNB];
+#pragma unroll
+                for (int x = 0; x < BMB; ++x) {
+                    const int m = wm * (32 * BMB) + x * 32 + lrow;
+                    ar[x] = As[cur][0][kk][m];
+                    ai[x] = As[cur][1][kk][m];
+                }
+#pragma unroll
+                for (int y = 0; y < BNB; ++y) {
+                    const int c = wn * (32 * BNB) + y * 32 + lrow;
+                    br[y] = Bs[cur][0][kk][c];
+                    bi[y] = Bs[cur][1][kk][c];
+                }
+#pragma unroll
+                for (int x = 0; x < BMB; ++x) {
+#pragma unroll
+                    for (int y = 0; y < BNB; ++y) {
+                        if constexpr (!GAUSS) {
+                            acc[x][y][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[x], br[y], acc[x][y][0], 0, 0, 0);
+                            acc[x][y][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai[x], bi[y], acc[x][y][0], 0, 0, 0);
+                            acc[x][y][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[x], bi[y], acc[x][y][1], 0, 0, 0);
+                            acc[x][y][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[x], br[y], acc[x][y][1], 0, 0, 0);
+                        } else {
+                            acc[x][y][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[x], br[y], acc[x][y][0], 0, 0, 0);
+                            acc[x][y][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[x], bi[y], acc[x][y][1], 0, 0, 0);
+                            acc[x][y][2] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[x] + ai[x], br[y] + bi[y],
+                                                                                acc[x][y][2], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+            if (kt + 1 < KT) { QSIM_LSTORE(cur ^ 1); }
+            __syncthreads();
+        }
+#undef QSIM_GLOAD
+#undef QSIM_LSTORE
+
+        // Accumulator layout of a 32x32 block: register e of lane l is
+        // row 8*(e/4) + 4*(l/32) + e%4, column l%32.
+#pragma unroll
+        for (int x = 0; x < BMB; ++x) {
+#pragma unroll
+            for (int y = 0; y < BNB; ++y) {
+                const int col = j0 + wn * (32 * BNB) + y * 32 + lrow;
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int row = i0 + wm * (32 * BMB) + x * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+                    float re, im;
+                    if constexpr (!GAUSS) {
+                        re = acc[x][y][0][e];
+                        im = acc[x][y][1][e];
+                    } else {
+                        re = acc[x][y][0][e] - acc[x][y][1][e];
+                        im = acc[x][y][2][e] - acc[x][y][0][e] - acc[x][y][1][e];
+                    }
+                    C[(size_t)row * N + col] = re;
+                    C[NN + (size_t)row * N + col] = im;
+                }
+            }
+        }
+    }
+};
+
+// Whole product for N <= 32 by a workgroup of `nthreads` threads, one output
+// entry per thread and pass, plain float32 FMAs (same 4M / 3M arithmetic).
+template <bool GAUSS>
+__device__ __forceinline__ void f32_small_product(int n, const float* __restrict__ A, const float* __restrict__ B,
+                                                  float* __restrict__ C, int first, int stride) {
+    const int N = 1 << n;
+    const int NN = N * N;
+    for (int idx = first; idx < NN; idx += stride) {
+        const int i = idx / N, j = idx % N;
+        float t1 = 0.f, t2 = 0.f, t3 = 0.f;
+        for (int k = 0; k < N; ++k) {
+            const float ar = A[k * N + i], ai = A[NN + k * N + i];
+            const float br = B[k * N + j], bi = B[NN + k * N + j];
+            if constexpr (!GAUSS) {
+                t1 = fmaf(ar, br, t1);
+                t1 = fmaf(-ai, bi, t1);
+                t2 = fmaf(ar, bi, t2);
+                t2 = fmaf(ai, br, t2);
+            } else {
+                t1 = fmaf(ar, br, t1);
+                t2 = fmaf(ai, bi, t2);
+                t3 = fmaf(ar + ai, br + bi, t3);
+            }
+        }
+        if constexpr (!GAUSS) {
+            C[idx] = t1;
+            C[NN + idx] = t2;
+        } else {
+            C[idx] = t1 - t2;
+            C[NN + idx] = t3 - t1 - t2;
+        }
+    }
+}
+
+}  // namespace qsim

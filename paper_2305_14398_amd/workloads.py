@@ -230,6 +230,8 @@ def mixed(rng: np.random.Generator, n_lo: int, n_hi: int, d_lo: int, d_hi: int) 
     if fam == "ghz_chain":
         return ghz_chain(n)
     if fam == "dj":
+        if n < 2:  # Deutsch-Jozsa needs an input qubit besides the ancilla
+            return ghz_chain(n)
         return dj(n, int(rng.integers(1, 1 << (n - 1))))
     if fam == "qft":
         return qft(n)

@@ -1,0 +1,120 @@
+"""Grouped batches of mixed-size circuits: per-circuit results equal the single-circuit
+chain (bit for bit where both use the same tile code), match the oracle, are the same alone
+and in the mix, and survive repeated hipGraph replays with eager work in between."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import unitary as UA  # noqa: E402
+from paper_2305_14398_amd import binding as B  # noqa: E402
+from paper_2305_14398_amd import workloads as W  # noqa: E402
+from tests import gpu_util as G  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = B.Context(0)
+    yield c
+    c.close()
+
+
+def run_batch(ctx, circuits, prec, graph=False, launches=1, between=None):
+    outs = [G.planar(c.n) for c in circuits]
+    ws = G.workspace(B.qsim_batch_workspace_bytes(circuits, prec))
+    plan = B.BatchPlan(ctx, circuits, outs, prec, ws, graph=graph)
+    results = []
+    for r in range(launches):
+        for o in outs:
+            o.fill_(float("nan"))
+        plan.launch()
+        G.sync()
+        results.append([G.to_complex(o) for o in outs])
+        if between:
+            between(r)
+    info = plan.info()
+    plan.close()
+    return results, info
+
+
+def single(ctx, c, prec):
+    U = G.planar(c.n)
+    ws = G.workspace(B.qsim_chain_workspace_bytes(c.n, prec))
+    B.qsim_unitary_chain(ctx, c.n, c.gates, prec, U, ws)
+    G.sync()
+    return G.to_complex(U)
+
+
+PRECS = [B.QSIM_FP32_4M, B.QSIM_FP32_3M, B.QSIM_SPLIT_BF16, B.QSIM_SPLIT_FP16]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_batch_matches_single_and_oracle(ctx, prec):
+    circuits = W.batch_mixed(40, seed=7, n_lo=1, n_hi=9, d_lo=1, d_hi=8)
+    circuits.append(W.Circuit(3, [], "empty"))
+    (res,), info = run_batch(ctx, circuits, prec)
+    assert info["iterations"] >= 1
+    for c, U in zip(circuits, res):
+        ref = UA.circuit_unitary(c.n, W.gate_tuples(c))
+        tol = 2e-3 if prec == B.QSIM_SPLIT_BF16 else 1e-5
+        assert np.abs(U - ref).max() <= tol, (c.family, c.n)
+        S = single(ctx, c, prec)
+        if c.n != 5:  # n = 5 runs 32x32 MFMA tiles alone and the whole-product path in a batch
+            np.testing.assert_array_equal(U, S, err_msg=f"{c.family} n={c.n}")
+        else:
+            assert np.abs(U - S).max() <= tol
+
+
+def test_alone_and_in_the_mix_are_identical(ctx):
+    mix = W.batch_mixed(24, seed=3, n_lo=4, n_hi=10, d_lo=2, d_hi=10)
+    probe = W.qft(10)
+    for prec in (B.QSIM_FP32_4M, B.QSIM_SPLIT_BF16):
+        (alone,), _ = run_batch(ctx, [probe], prec)
+        (mixed,), _ = run_batch(ctx, mix[:12] + [probe] + mix[12:], prec)
+        np.testing.assert_array_equal(alone[0], mixed[12])
+
+
+def test_graph_replays_match_eager(ctx):
+    circuits = W.batch_mixed(30, seed=11, n_lo=2, n_hi=9, d_lo=2, d_hi=6)
+    for prec in (B.QSIM_FP32_4M, B.QSIM_SPLIT_BF16):
+        (eager,), _ = run_batch(ctx, circuits, prec)
+        scratch = torch.empty(1 << 20, device=G.DEV)
+
+        def eager_work(r):
+            scratch.normal_()
+            float(scratch.sum().item())
+            G.sync()
+
+        replays, _ = run_batch(ctx, circuits, prec, graph=True, launches=4, between=eager_work)
+        for rep in replays:
+            for a, b in zip(rep, eager):
+                np.testing.assert_array_equal(a, b)
+
+
+def test_autotune_records_choices_and_stays_correct(ctx):
+    timings = B.qsim_autotune(ctx, B.QSIM_FP32_4M, 7, 10)
+    tiles = B.qsim_tune_get(ctx, B.QSIM_FP32_4M)
+    for n in range(7, 11):
+        t64, t128 = timings[n]
+        assert t64 > 0 and t128 > 0
+        assert tiles[n] == (64 if t64 < t128 else 128)
+    c = W.random_layers(9, 4, np.random.default_rng(1))
+    ref = UA.circuit_unitary(9, W.gate_tuples(c))
+    for tile in (64, 128):
+        B.qsim_tune_set(ctx, B.QSIM_FP32_4M, 9, tile)
+        assert np.abs(single(ctx, c, B.QSIM_FP32_4M) - ref).max() <= 1e-5
+        (res,), _ = run_batch(ctx, [c], B.QSIM_FP32_4M)
+        assert np.abs(res[0] - ref).max() <= 1e-5
+    B.qsim_tune_set(ctx, B.QSIM_FP32_4M, 9, tiles[9])
+
+
+def test_one_shot_batched_call(ctx):
+    circuits = [W.ghz_chain(5), W.dj(7, 5), W.qft(8)]
+    outs = [G.planar(c.n) for c in circuits]
+    ws = G.workspace(B.qsim_batch_workspace_bytes(circuits, B.QSIM_FP32_4M))
+    B.qsim_unitary_chain_batched(ctx, circuits, outs, B.QSIM_FP32_4M, ws)
+    for c, o in zip(circuits, outs):
+        ref = UA.circuit_unitary(c.n, W.gate_tuples(c))
+        assert np.abs(G.to_complex(o) - ref).max() <= 1e-5

@@ -166,3 +166,21 @@ def test_last_error_is_thread_local_and_resets():
     assert seen == ["no error"]
     B.qsim_pack_steps(2, [("H", (0,), None)])
     assert B.qsim_last_error() == "no error"
+
+
+def test_batch_validation_without_device():
+    circuits = [W.qft(5), W.ghz_chain(6)]
+    need = B.qsim_batch_workspace_bytes(circuits, B.QSIM_FP32_4M)
+    assert need == 2 * (8 << 10) + 2 * (8 << 12)
+    assert B.qsim_batch_workspace_bytes(circuits, B.QSIM_SPLIT_BF16) == 3 * (8 << 10) + 3 * (8 << 12)
+    outs = [FAKE * 64, FAKE * 65]
+    with pytest.raises(B.QsimError, match="workspace"):
+        B.BatchPlan(None, circuits, outs, B.QSIM_FP32_4M, FAKE * 4, need - 256)
+    with pytest.raises(B.QsimError, match="overlap"):
+        B.BatchPlan(None, circuits, [FAKE * 64, FAKE * 64], B.QSIM_FP32_4M, FAKE * 4, need)
+    with pytest.raises(B.QsimError, match="overlaps the workspace"):
+        B.BatchPlan(None, circuits, [FAKE * 4, FAKE * 65], B.QSIM_FP32_4M, FAKE * 4, need)
+    with pytest.raises(B.QsimError, match="context is NULL"):
+        B.BatchPlan(None, circuits, outs, B.QSIM_FP32_4M, FAKE * 4, need)
+    with pytest.raises(B.QsimError, match="n_qubits"):
+        B.qsim_batch_workspace_bytes([(17, [])], 0)
