@@ -59,7 +59,8 @@ typedef enum qsim_status {
     QSIM_E_OOM = -3,         /* arena / workspace cannot hold the request */
     QSIM_E_DEVICE = -4,      /* a HIP call failed */
     QSIM_E_FULL = -5,        /* qsim_submit: queue full (back-pressure) */
-    QSIM_E_UNKNOWN_ID = -6   /* qsim_poll: no such request */
+    QSIM_E_UNKNOWN_ID = -6,  /* qsim_poll: no such request */
+    QSIM_E_CANCELLED = -7    /* request dropped because the engine stopped before admitting it */
 } qsim_status;
 
 /* Arithmetic of the chain product (stage 5). */
@@ -104,7 +105,7 @@ const char* qsim_last_error(void);
 /* Library version string. */
 const char* qsim_version(void);
 
-/* Create a context on HIP device `device` (0-based).  Allocates a few KiB of
+/* Create a context on HIP device `device` (0-based).  Allocates about 9 MB of
  * device scratch for reductions.  *out receives the context. */
 qsim_status qsim_ctx_create(int device, qsim_ctx** out);
 /* Destroy a context (stops its serving engine, if started).  NULL is a no-op. */
@@ -183,6 +184,12 @@ qsim_status qsim_apply_state(qsim_ctx* ctx, int n_qubits, const void* d_U, const
 qsim_status qsim_unitarity_drift(qsim_ctx* ctx, int n_qubits, const void* d_U, double* h_out,
                                  void* stream);
 
+/* Probe form of the drift check for serving: with the fixed unit vector
+ * x_j = exp(2 pi i frac(j g)) / sqrt(N) (g = (sqrt 5 - 1) / 2), computes
+ * d = U^H (U x) - x in float64 (two passes over U) and returns
+ * h_out[0] = max |d_j|, h_out[1] = |d|_2.  Synchronises the stream. */
+qsim_status qsim_unitarity_drift_probe(qsim_ctx* ctx, int n_qubits, const void* d_U, double* h_out, void* stream);
+
 /* ---- Batches of circuits of mixed size (stages 4-5 for many circuits) ----
  * One iteration of a batch expands the current step of every circuit that has
  * one in a single grouped launch, then takes every such circuit's current
@@ -234,6 +241,83 @@ qsim_status qsim_autotune(qsim_ctx* ctx, int prec, int n_lo, int n_hi, double* m
 qsim_status qsim_tune_get(qsim_ctx* ctx, int prec, int* tiles_out);
 /* Override the tile edge (64 or 128; split fp16: 64 only) for n in 7..16. */
 qsim_status qsim_tune_set(qsim_ctx* ctx, int prec, int n_qubits, int tile);
+
+/* ---- Serving: continuous batching of submitted circuits ----
+ * qsim_serve_start runs an engine thread for the context with its own HIP
+ * stream.  A request is admitted in arrival order once the caller's device
+ * arena has room for its footprint (chain workspace: 2 matrices for float32,
+ * 3 for split precisions, plus U when d_U is NULL; 8*N*N bytes per matrix,
+ * each rounded up to 256) and fewer than max_active requests are admitted.
+ * QSIM_SERVE_CONTINUOUS: every engine iteration advances every admitted
+ *   request by one step (stages 4-5) in one grouped expansion launch and one
+ *   grouped product launch; a request whose chain is complete gets stage 6
+ *   (psi = U psi0, float64 norm) and, if asked, the float64 probe drift.
+ *   Requests that arrive while others are on the GPU join at the next
+ *   iteration.  Each request's arithmetic does not depend on what else is in
+ *   flight (same tiles, same order), so results are identical alone and in
+ *   the mix.
+ * QSIM_SERVE_FIFO: the plain baseline; one request at a time through the
+ *   qsim_unitary_chain kernels.
+ * The engine allocates its job tables and result slots at start; serving
+ * allocates nothing.  Calls may come from any thread. */
+#define QSIM_SERVE_CONTINUOUS 0
+#define QSIM_SERVE_FIFO 1
+
+typedef struct qsim_serve_config {
+    int32_t prec;            /* qsim_precision of every served chain */
+    int32_t mode;            /* QSIM_SERVE_CONTINUOUS or QSIM_SERVE_FIFO */
+    int32_t max_active;      /* 1..4096 requests advanced together (forced to 1 in FIFO mode) */
+    int32_t queue_capacity;  /* queued (not yet admitted) requests before qsim_submit returns QSIM_E_FULL */
+    void* d_arena;           /* caller-owned device memory, 256-byte aligned, untouched by others while serving */
+    size_t arena_bytes;
+} qsim_serve_config;
+
+#define QSIM_REQ_DRIFT_PROBE 1u  /* also compute the probe drift (qsim_unitarity_drift_probe) */
+
+typedef struct qsim_request {
+    int32_t n_qubits;
+    int32_t n_gates;
+    const qsim_gate* gates;  /* copied by qsim_submit */
+    void* d_psi;             /* out: final state, planar complex64 (2N floats); required */
+    const void* d_psi0;      /* initial state (planar complex64) or NULL for |0...0> */
+    void* d_U;               /* out: circuit unitary, row-major planar complex64, or NULL (kept in the arena) */
+    uint32_t flags;          /* QSIM_REQ_DRIFT_PROBE */
+    uint32_t reserved;       /* must be 0 */
+} qsim_request;              /* d_psi, d_psi0 and d_U must stay valid until the request is polled done */
+
+typedef struct qsim_result {
+    int32_t status;          /* QSIM_PENDING, QSIM_OK, QSIM_E_DEVICE or QSIM_E_CANCELLED */
+    int32_t n_steps;
+    double norm2;            /* float64 sum |psi_i|^2 */
+    double drift_max;        /* probe drift max |d_j| (-1 if not requested) */
+    double drift_l2;         /* probe drift |d|_2 (-1 if not requested) */
+    uint64_t t_submit_ns;    /* steady clock: submitted, admitted, results observed by the engine */
+    uint64_t t_start_ns;
+    uint64_t t_done_ns;
+} qsim_result;
+
+typedef struct qsim_serve_stats {
+    int64_t iterations;        /* engine iterations (FIFO: requests served) */
+    int64_t grouped_launches;  /* grouped expansion + product launches */
+    int64_t admitted;
+    int64_t completed;
+    int64_t peak_active;
+    uint64_t arena_high_water; /* bytes */
+} qsim_serve_stats;
+
+qsim_status qsim_serve_start(qsim_ctx* ctx, const qsim_serve_config* cfg);
+/* Serve every admitted request to completion, cancel queued ones and stop the
+ * thread.  Results not yet polled are dropped with the engine. */
+qsim_status qsim_serve_stop(qsim_ctx* ctx);
+/* Validate and copy the request, queue it; *id_out identifies it.
+ * QSIM_E_FULL: queue at capacity (retry later); QSIM_E_OOM: the request can
+ * never fit the arena. */
+qsim_status qsim_submit(qsim_ctx* ctx, const qsim_request* req, uint64_t* id_out);
+/* Non-blocking.  QSIM_PENDING while queued or running; QSIM_OK once finished,
+ * with *out filled (out->status tells the request's own outcome) and the id
+ * released; QSIM_E_UNKNOWN_ID for ids never issued or already collected. */
+qsim_status qsim_poll(qsim_ctx* ctx, uint64_t id, qsim_result* out);
+qsim_status qsim_serve_get_stats(qsim_ctx* ctx, qsim_serve_stats* out);
 
 /* Kernel timing with HIP events (instrumentation, not part of the method).
  * While enabled, every launch the context makes is bracketed by two events

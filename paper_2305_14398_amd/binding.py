@@ -52,6 +52,32 @@ class qsim_circuit_desc(ctypes.Structure):
 
 
 QSIM_BATCH_GRAPH = 1
+QSIM_SERVE_CONTINUOUS, QSIM_SERVE_FIFO = 0, 1
+QSIM_REQ_DRIFT_PROBE = 1
+QSIM_E_CANCELLED = -7
+STATUS_NAMES[-7] = "QSIM_E_CANCELLED"
+
+
+class qsim_serve_config(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int32), ("mode", ctypes.c_int32), ("max_active", ctypes.c_int32),
+                ("queue_capacity", ctypes.c_int32), ("d_arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t)]
+
+
+class qsim_request(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_int32), ("n_gates", ctypes.c_int32), ("gates", ctypes.POINTER(qsim_gate)),
+                ("d_psi", ctypes.c_void_p), ("d_psi0", ctypes.c_void_p), ("d_U", ctypes.c_void_p),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class qsim_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n_steps", ctypes.c_int32), ("norm2", ctypes.c_double),
+                ("drift_max", ctypes.c_double), ("drift_l2", ctypes.c_double), ("t_submit_ns", ctypes.c_uint64),
+                ("t_start_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64)]
+
+
+class qsim_serve_stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("grouped_launches", ctypes.c_int64), ("admitted", ctypes.c_int64),
+                ("completed", ctypes.c_int64), ("peak_active", ctypes.c_int64), ("arena_high_water", ctypes.c_uint64)]
 
 
 class QsimError(RuntimeError):
@@ -96,6 +122,12 @@ def lib() -> ctypes.CDLL:
         "qsim_batch_plan_destroy": (i32, [vp]),
         "qsim_unitary_chain_batched": (i32, [vp, ctypes.POINTER(qsim_circuit_desc), i32, i32, vp, sz, vp]),
         "qsim_autotune": (i32, [vp, i32, i32, i32, ctypes.POINTER(dbl)]),
+        "qsim_unitarity_drift_probe": (i32, [vp, i32, vp, ctypes.POINTER(dbl), vp]),
+        "qsim_serve_start": (i32, [vp, ctypes.POINTER(qsim_serve_config)]),
+        "qsim_serve_stop": (i32, [vp]),
+        "qsim_submit": (i32, [vp, ctypes.POINTER(qsim_request), ctypes.POINTER(ctypes.c_uint64)]),
+        "qsim_poll": (i32, [vp, ctypes.c_uint64, ctypes.POINTER(qsim_result)]),
+        "qsim_serve_get_stats": (i32, [vp, ctypes.POINTER(qsim_serve_stats)]),
         "qsim_tune_get": (i32, [vp, i32, ctypes.POINTER(i32)]),
         "qsim_tune_set": (i32, [vp, i32, i32, i32]),
         "qsim_profile_read": (i32, [vp, ctypes.POINTER(qsim_kernel_stats)]),
@@ -369,3 +401,49 @@ def qsim_tune_get(ctx, prec: int) -> list:
 
 def qsim_tune_set(ctx, prec: int, n_qubits: int, tile: int) -> None:
     _check(lib().qsim_tune_set(_h(ctx), prec, n_qubits, tile), "qsim_tune_set")
+
+
+def qsim_unitarity_drift_probe(ctx, n_qubits: int, d_U, stream=None) -> tuple:
+    out = (ctypes.c_double * 2)()
+    st = _stream(stream, _dev(ctx)) if _h(ctx) else None
+    _check(lib().qsim_unitarity_drift_probe(_h(ctx), n_qubits, _ptr(d_U), out, st), "qsim_unitarity_drift_probe")
+    return float(out[0]), float(out[1])
+
+
+# --- serving -------------------------------------------------------------------------------
+
+def qsim_serve_start(ctx, prec: int, d_arena, arena_bytes: Optional[int] = None, mode: int = QSIM_SERVE_CONTINUOUS,
+                     max_active: int = 64, queue_capacity: int = 4096) -> None:
+    if arena_bytes is None:
+        arena_bytes = d_arena.numel() * d_arena.element_size() if hasattr(d_arena, "numel") else 0
+    cfg = qsim_serve_config(prec, mode, max_active, queue_capacity, _ptr(d_arena), arena_bytes)
+    _check(lib().qsim_serve_start(_h(ctx), ctypes.byref(cfg)), "qsim_serve_start")
+
+
+def qsim_serve_stop(ctx) -> None:
+    _check(lib().qsim_serve_stop(_h(ctx)), "qsim_serve_stop")
+
+
+def qsim_submit(ctx, n_qubits: int, gates: Sequence, d_psi, d_psi0=None, d_U=None, probe: bool = True) -> int:
+    arr, ng = gate_array(gates)
+    req = qsim_request(n_qubits, ng, ctypes.cast(arr, ctypes.POINTER(qsim_gate)), _ptr(d_psi), _ptr(d_psi0),
+                       _ptr(d_U), QSIM_REQ_DRIFT_PROBE if probe else 0, 0)
+    rid = ctypes.c_uint64()
+    _check(lib().qsim_submit(_h(ctx), ctypes.byref(req), ctypes.byref(rid)), "qsim_submit")
+    return int(rid.value)
+
+
+def qsim_poll(ctx, rid: int) -> Optional[dict]:
+    """None while pending; else the result as a dict (its 'status' is the request's own outcome)."""
+    res = qsim_result()
+    st = lib().qsim_poll(_h(ctx), rid, ctypes.byref(res))
+    if st == QSIM_PENDING:
+        return None
+    _check(st, "qsim_poll")
+    return {f: getattr(res, f) for f, _ in qsim_result._fields_}
+
+
+def qsim_serve_get_stats(ctx) -> dict:
+    out = qsim_serve_stats()
+    _check(lib().qsim_serve_get_stats(_h(ctx), ctypes.byref(out)), "qsim_serve_get_stats")
+    return {f: getattr(out, f) for f, _ in qsim_serve_stats._fields_}

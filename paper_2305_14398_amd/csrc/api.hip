@@ -8,6 +8,7 @@
 #include <string>
 #include <vector>
 
+#include "engine.h"
 #include "host.h"
 
 using namespace qsim;
@@ -327,6 +328,8 @@ qsim_status qsim_ctx_create(int device, qsim_ctx** out) {
 
 qsim_status qsim_ctx_destroy(qsim_ctx* ctx) {
     if (ctx == nullptr) return ok();
+    delete ctx->engine;  // serves admitted requests to completion first
+    ctx->engine = nullptr;
     DeviceGuard g(ctx->device);
     (void)hipDeviceSynchronize();
     delete ctx->prof;
@@ -528,6 +531,26 @@ qsim_status qsim_profile_read(qsim_ctx* ctx, qsim_kernel_stats* out) {
         out->count[k] = ctx->prof->count[k];
         out->total_ms[k] = ctx->prof->total_ms[k];
     }
+    return ok();
+}
+
+qsim_status qsim_unitarity_drift_probe(qsim_ctx* ctx, int n_qubits, const void* d_U, double* h_out, void* stream) {
+    qsim_status s = QSIM_OK;
+    if (!valid_n(n_qubits)) return fail(QSIM_E_RANGE, "n_qubits %d outside 1..%d", n_qubits, QSIM_MAX_QUBITS);
+    if (!d_U || !aligned(d_U) || !h_out) return fail(QSIM_E_INVALID, "d_U is NULL/unaligned or h_out is NULL");
+    s = check_ctx(ctx);
+    if (s != QSIM_OK) return s;
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return device_fail("hipSetDevice", g.err);
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    hipError_t e = timed(ctx->prof, QSIM_PROFILE_DRIFT, hs, [&] {
+        return launch_drift_probe(n_qubits, static_cast<const float*>(d_U), ctx->d_scratch + kProbeScratchOffset,
+                                  ctx->d_scratch + 4, hs);
+    });
+    if (e != hipSuccess) return device_fail("probe drift launch", e);
+    e = hipMemcpyAsync(h_out, ctx->d_scratch + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, hs);
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    if (e != hipSuccess) return device_fail("probe drift readback", e);
     return ok();
 }
 

@@ -12,7 +12,7 @@
 #include <cstring>
 #include <numeric>
 
-#include "host.h"
+#include "chain_jobs.h"
 
 using namespace qsim;
 
@@ -65,17 +65,7 @@ int device_cus(int device) {
     return cus;
 }
 
-int tiles_of(int n, int cfg) {
-    if (cfg == 0) return 1;
-    const int t = (1 << n) / cfg;
-    return t * t;
-}
-
-int expand_blocks(int n) {
-    const long long items = (1ll << (2 * n)) >> 2;
-    const long long b = (items + 255) / 256;
-    return (int)std::min<long long>(std::max<long long>(b, 1), 1024);
-}
+int tiles_of(int n, int cfg) { return ChainCursor::tiles_of(n, cfg); }
 
 hipError_t enqueue(qsim_batch_plan* p, hipStream_t s) {
     for (const auto& it : p->iters) {
@@ -146,7 +136,6 @@ qsim_status qsim_batch_plan_create(qsim_ctx* ctx, const qsim_circuit_desc* circu
     for (int i = 0; i < count; ++i) maxk = std::max<int>(maxk, (int)offs[i].size() - 1);
     std::vector<std::vector<ExpandJob>> ej(maxk);
     std::vector<std::vector<GemmJob>> gj(maxk);
-    std::vector<int> cur(count, 0);
     char* ws = static_cast<char*>(d_ws);
     size_t base = 0;
     double flops = 0.0;
@@ -160,63 +149,28 @@ qsim_status qsim_batch_plan_create(qsim_ctx* ctx, const qsim_circuit_desc* circu
         char* W1 = ws + base + mb;
         char* W2 = ws + base + 2 * mb;
         base += per_circuit_ws(n, prec);
-        const int cfg = n <= 5 ? 0 : ctx->tune.get(prec, n);
-        auto add_expand = [&](int j, int first, int cnt, void* dst, int layout_col, int f) -> qsim_status {
-            ExpandJob J;
-            std::memset(&J, 0, sizeof J);
-            qsim_status st = make_step(n, c.gates + first, cnt, J.st);
-            if (st != QSIM_OK) return fail(st, "circuit %d step %d: %s", i, j, last_error_text().c_str());
-            J.out = dst;
-            J.n = n;
-            J.layout_col = layout_col;
-            J.fmt = f;
-            J.blocks = expand_blocks(n);
-            ej[j].push_back(J);
-            return QSIM_OK;
-        };
-        auto add_gemm = [&](int j, const void* X, const void* Y, void* D0, void* D1) {
-            GemmJob G;
-            G.X = X;
-            G.Y = Y;
-            G.D0 = D0;
-            G.D1 = D1;
-            G.n = n;
-            G.cfg = cfg;
-            G.tiles = tiles_of(n, cfg);
-            gj[j].push_back(G);
-            flops += 8.0 * (double)(1ll << (3 * n));
-            ++products;
-        };
-        if (k == 0) {
-            if ((s = add_expand(0, 0, 0, c.d_U, 0, FMT_F32)) != QSIM_OK) return s;
-            continue;
-        }
-        if (!split) {
-            void* X[2] = {c.d_U, W1};
-            void* u = X[(k - 1) & 1];
-            if ((s = add_expand(0, offs[i][0], offs[i][1] - offs[i][0], u, 0, FMT_F32)) != QSIM_OK) return s;
-            for (int j = 1; j < k; ++j) {
-                if ((s = add_expand(j, offs[i][j], offs[i][j + 1] - offs[i][j], S, 1, FMT_F32)) != QSIM_OK) return s;
-                void* nxt = X[(k - 1 - j) & 1];
-                add_gemm(j, S, u, nxt, nullptr);
-                u = nxt;
-            }
-        } else {
-            void* P[2] = {W1, W2};
-            if (k == 1) {
-                if ((s = add_expand(0, offs[i][0], offs[i][1] - offs[i][0], c.d_U, 0, FMT_F32)) != QSIM_OK) return s;
-                continue;
-            }
-            if ((s = add_expand(0, offs[i][0], offs[i][1] - offs[i][0], P[0], 1, fmt)) != QSIM_OK) return s;
-            int cu = 0;
-            for (int j = 1; j < k; ++j) {
-                if ((s = add_expand(j, offs[i][j], offs[i][j + 1] - offs[i][j], S, 0, fmt)) != QSIM_OK) return s;
-                if (j < k - 1) {
-                    add_gemm(j, P[cu], S, P[cu ^ 1], nullptr);
-                    cu ^= 1;
-                } else {
-                    add_gemm(j, S, P[cu], nullptr, c.d_U);
-                }
+        ChainCursor cc;
+        cc.n = n;
+        cc.k = k;
+        cc.prec = prec;
+        cc.cfg = n <= 5 ? 0 : ctx->tune.get(prec, n);
+        cc.gates = c.gates;
+        cc.off = offs[i];
+        cc.U = c.d_U;
+        cc.S = S;
+        cc.W1 = W1;
+        cc.W2 = W2;
+        for (int j = 0; j < std::max(k, 1); ++j) {
+            ExpandJob E;
+            GemmJob Gj;
+            bool has_gemm = false;
+            s = cc.emit(j, E, Gj, has_gemm);
+            if (s != QSIM_OK) return fail(s, "circuit %d step %d: %s", i, j, last_error_text().c_str());
+            ej[j].push_back(E);
+            if (has_gemm) {
+                gj[j].push_back(Gj);
+                flops += 8.0 * (double)(1ll << (3 * n));
+                ++products;
             }
         }
     }

@@ -90,5 +90,10 @@ hipError_t launch_drift(int n, const float* U_row, double* partials, int max_par
                         hipStream_t stream);
 
 constexpr int kDriftMaxPartials = 2048;
+// Probe drift: partial sums of at most this many complex entries (chunks * N).
+constexpr int kProbeChunkEntries = 1 << 19;
+// Doubles of scratch the probe needs: y (2 N) + partials (2 * kProbeChunkEntries).
+constexpr size_t kProbeScratchDoubles = 2 * ((size_t)1 << QSIM_MAX_QUBITS) + 2 * (size_t)kProbeChunkEntries;
+hipError_t launch_drift_probe(int n, const float* U_row, double* scratch, double* d_out, hipStream_t stream);
 
 }  // namespace qsim

@@ -213,7 +213,125 @@ __global__ __launch_bounds__(256) void drift_final_kernel(int n, int count, cons
     }
 }
 
+
+// ---- probe variant: | U^H (U x) - x | for one fixed unit vector x ----
+// x_j = exp(2 pi i frac(j * g)) / sqrt(N) with g the golden-ratio conjugate
+// (unit-modulus entries, so |x| = 1).  y = U x and z = U^H y are accumulated in
+// float64 (products of float32 entries are exact in float64); the cost is two
+// passes over U instead of the 8 N^3 flops of the full check.
+constexpr double kGolden = 0.61803398874989484820;
+
+__device__ __forceinline__ void probe_x(uint32_t j, double inv_sqrt_n, double& xr, double& xi) {
+    double t = (double)j * kGolden;
+    t -= floor(t);
+    double sn, cs;
+    sincospi(2.0 * t, &sn, &cs);
+    xr = cs * inv_sqrt_n;
+    xi = sn * inv_sqrt_n;
+}
+
+// y = U x, one wave per row.
+__global__ __launch_bounds__(256) void probe_y_kernel(int n, const float* __restrict__ U, double* __restrict__ y) {
+    const int N = 1 << n;
+    const size_t NN = (size_t)N * N;
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= N) return;
+    const double inv = rsqrt((double)N);
+    double sr = 0.0, si = 0.0;
+    for (int k = lane; k < N; k += 64) {
+        const double ar = U[(size_t)row * N + k], ai = U[NN + (size_t)row * N + k];
+        double xr, xi;
+        probe_x((uint32_t)k, inv, xr, xi);
+        sr += ar * xr - ai * xi;
+        si += ar * xi + ai * xr;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        sr += __shfl_xor(sr, off, 64);
+        si += __shfl_xor(si, off, 64);
+    }
+    if (lane == 0) {
+        y[2 * row] = sr;
+        y[2 * row + 1] = si;
+    }
+}
+
+// Partial z_j over one chunk of rows: zpart[chunk][j] = sum_{i in chunk} conj(U_ij) y_i.
+__global__ __launch_bounds__(256) void probe_z_kernel(int n, int rows_per_chunk, const float* __restrict__ U,
+                                                      const double* __restrict__ y, double* __restrict__ zpart) {
+    const int N = 1 << n;
+    const size_t NN = (size_t)N * N;
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= N) return;
+    const int i0 = blockIdx.y * rows_per_chunk;
+    double zr = 0.0, zi = 0.0;
+    for (int i = i0; i < i0 + rows_per_chunk; ++i) {
+        const double ur = U[(size_t)i * N + j], ui = U[NN + (size_t)i * N + j];
+        const double yr = y[2 * i], yi = y[2 * i + 1];
+        zr += ur * yr + ui * yi;
+        zi += ur * yi - ui * yr;
+    }
+    zpart[2 * ((size_t)blockIdx.y * N + j)] = zr;
+    zpart[2 * ((size_t)blockIdx.y * N + j) + 1] = zi;
+}
+
+// Sum the chunks in a fixed order, subtract x, reduce to max |d| and |d|_2.
+__global__ __launch_bounds__(1024) void probe_final_kernel(int n, int chunks, const double* __restrict__ zpart,
+                                                          double* __restrict__ out) {
+    const int N = 1 << n;
+    const double inv = rsqrt((double)N);
+    __shared__ double smax[1024], ssum[1024];
+    double tmax = 0.0, tsum = 0.0;
+    for (int j = threadIdx.x; j < N; j += 1024) {
+        double zr = 0.0, zi = 0.0;
+        for (int c = 0; c < chunks; ++c) {
+            zr += zpart[2 * ((size_t)c * N + j)];
+            zi += zpart[2 * ((size_t)c * N + j) + 1];
+        }
+        double xr, xi;
+        probe_x((uint32_t)j, inv, xr, xi);
+        const double dr = zr - xr, di = zi - xi;
+        const double m2 = dr * dr + di * di;
+        tmax = fmax(tmax, sqrt(m2));
+        tsum += m2;
+    }
+    smax[threadIdx.x] = tmax;
+    ssum[threadIdx.x] = tsum;
+    __syncthreads();
+    for (int w = 512; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
+            ssum[threadIdx.x] += ssum[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = smax[0];
+        out[1] = sqrt(ssum[0]);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_drift_probe(int n, const float* U_row, double* scratch, double* d_out, hipStream_t stream) {
+    const int N = 1 << n;
+    double* y = scratch;
+    double* zpart = scratch + 2 * (size_t)N;
+    // chunks * N <= kProbeChunkEntries keeps the partials inside the scratch.
+    int chunks = kProbeChunkEntries / N;
+    if (chunks > N) chunks = N;
+    if (chunks < 1) chunks = 1;
+    const int rows = N / chunks;
+    hipLaunchKernelGGL(probe_y_kernel, dim3((N + 3) / 4), dim3(256), 0, stream, n, U_row, y);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(probe_z_kernel, dim3((N + 255) / 256, chunks), dim3(256), 0, stream, n, rows, U_row, y, zpart);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(probe_final_kernel, dim3(1), dim3(1024), 0, stream, n, chunks, zpart, d_out);
+    return hipGetLastError();
+}
 
 hipError_t launch_drift(int n, const float* U_row, double* partials, int max_partials, double* d_out,
                         hipStream_t stream) {

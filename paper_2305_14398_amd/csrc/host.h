@@ -9,6 +9,8 @@
 
 namespace qsim {
 
+class Engine;
+
 
 // --- status and validation (api.hip) ---
 qsim_status fail(qsim_status st, const char* fmt, ...);
@@ -121,7 +123,10 @@ struct TuneTable {
 qsim_status chain_impl(int n, const qsim_gate* gates, int n_gates, const int32_t* off, int n_steps, int prec, void* d_U,
                        void* d_ws, hipStream_t stream, Profiler* prof, const TuneTable& tune);
 
-constexpr size_t kScratchDoubles = 8 + 2 * kDriftMaxPartials;
+// Context scratch layout (doubles): [0] norm2, [2..3] drift, [4..5] probe
+// drift, [8, 8 + 2*kDriftMaxPartials) drift partials, then the probe scratch.
+constexpr size_t kProbeScratchOffset = 8 + 2 * kDriftMaxPartials;
+constexpr size_t kScratchDoubles = kProbeScratchOffset + kProbeScratchDoubles;
 
 }  // namespace qsim
 
@@ -130,6 +135,7 @@ struct qsim_ctx {
     double* d_scratch = nullptr;  // [0] norm2, [2..3] drift result, [8..] drift partials
     qsim::Profiler* prof = nullptr;
     qsim::TuneTable tune;
+    qsim::Engine* engine = nullptr;
 };
 
 namespace qsim {

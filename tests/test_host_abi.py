@@ -184,3 +184,18 @@ def test_batch_validation_without_device():
         B.BatchPlan(None, circuits, outs, B.QSIM_FP32_4M, FAKE * 4, need)
     with pytest.raises(B.QsimError, match="n_qubits"):
         B.qsim_batch_workspace_bytes([(17, [])], 0)
+
+
+def test_serving_validation_without_device():
+    with pytest.raises(B.QsimError, match="context is NULL"):
+        B.qsim_serve_start(None, B.QSIM_FP32_4M, FAKE, arena_bytes=1 << 20)
+    with pytest.raises(B.QsimError, match="max_active"):
+        B.qsim_serve_start(None, B.QSIM_FP32_4M, FAKE, arena_bytes=1 << 20, max_active=0)
+    with pytest.raises(B.QsimError, match="arena"):
+        B.qsim_serve_start(None, B.QSIM_FP32_4M, FAKE + 8, arena_bytes=1 << 20)
+    with pytest.raises(B.QsimError, match="precision"):
+        B.qsim_serve_start(None, 7, FAKE, arena_bytes=1 << 20)
+    with pytest.raises(B.QsimError, match="NULL"):
+        B.qsim_submit(None, 3, [("H", (0,), None)], FAKE)
+    with pytest.raises(B.QsimError, match="NULL"):
+        B.qsim_poll(None, 1)
