@@ -50,6 +50,137 @@ def closed_form_error(c, psi):
     return float(np.abs(psi - ref).max())
 
 
+def progress(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def flops_of(B, c):
+    k = len(B.qsim_pack_steps(c.n, c.gates)) - 1
+    return 8.0 * (1 << c.n) ** 3 * max(k - 1, 0)
+
+
+def bench_batched(B, ctx, torch, count: int, seed: int, prec_name: str, reps: int):
+    """512 seeded mixed circuits (n 4..11, depth 5..30): one autotuned, graph-captured batch plan vs the same
+    circuits one at a time through qsim_unitary_chain."""
+    from paper_2305_14398_amd import workloads as W
+    prec = B.PRECISIONS[prec_name]
+    circuits = W.batch_mixed(count, seed=seed, n_lo=4, n_hi=11, d_lo=5, d_hi=30)
+    tuning = B.qsim_autotune(ctx, prec, 7, 11)
+    dev = torch.device("cuda:0")
+    outs = [torch.empty((2, 1 << c.n, 1 << c.n), dtype=torch.float32, device=dev) for c in circuits]
+    ws = torch.empty(B.qsim_batch_workspace_bytes(circuits, prec), dtype=torch.uint8, device=dev)
+    plan = B.BatchPlan(ctx, circuits, outs, prec, ws, graph=True)
+    info = plan.info()
+    plan.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.launch()
+    torch.cuda.synchronize()
+    grouped = (time.perf_counter() - t0) / reps
+    plan.close()
+    # one at a time (same kernels and precision, no grouping, no graph)
+    wss = torch.empty(B.qsim_chain_workspace_bytes(11, prec), dtype=torch.uint8, device=dev)
+    for c, o in zip(circuits[:8], outs[:8]):
+        B.qsim_unitary_chain(ctx, c.n, c.gates, prec, o, wss)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c, o in zip(circuits, outs):
+        B.qsim_unitary_chain(ctx, c.n, c.gates, prec, o, wss)
+    torch.cuda.synchronize()
+    single = time.perf_counter() - t0
+    hist = {}
+    for c in circuits:
+        hist[c.n] = hist.get(c.n, 0) + 1
+    return {
+        "workload": f"{count} seeded circuits (seed {seed}), n ~ U{{4..11}}, families ghz_chain/dj/qft/random, "
+                    f"depth ~ U{{5..30}} for random layers; {prec_name}; grouped persistent launches, autotuned "
+                    f"tiles, hipGraph replay",
+        "qubit_histogram": {str(k): v for k, v in sorted(hist.items())},
+        "iterations": info["iterations"],
+        "products": info["products"],
+        "tflop": round(info["flops"] / 1e12, 2),
+        "grouped_s": round(grouped, 4),
+        "grouped_circuits_per_s": round(count / grouped, 1),
+        "grouped_tflops": round(info["flops"] / grouped / 1e12, 2),
+        "one_at_a_time_s": round(single, 4),
+        "one_at_a_time_circuits_per_s": round(count / single, 1),
+        "one_at_a_time_tflops": round(info["flops"] / single / 1e12, 2),
+        "speedup_vs_one_at_a_time": round(single / grouped, 3),
+        "autotune_ms_per_product_64_128": {str(k): [round(a, 4), round(b, 4)] for k, (a, b) in tuning.items()},
+        "tiles_chosen": {str(n): B.qsim_tune_get(ctx, prec)[n] for n in range(6, 12)},
+    }
+
+
+def replay_trace(B, ctx, torch, trace, prec: int, mode: int, arena, max_active: int):
+    import threading
+    dev = torch.device("cuda:0")
+    psis = [torch.empty(2 << c.n, dtype=torch.float32, device=dev) for _, c in trace]
+    torch.cuda.synchronize()
+    B.qsim_serve_start(ctx, prec, arena, mode=mode, max_active=max_active, queue_capacity=len(trace) + 1)
+    ids = [None] * len(trace)
+    t0 = time.monotonic_ns()
+
+    def submitter():
+        for i, (t, c) in enumerate(trace):
+            target = t0 + int(t * 1e9)
+            while True:
+                now = time.monotonic_ns()
+                if now >= target:
+                    break
+                time.sleep(min(0.002, (target - now) / 1e9))
+            ids[i] = B.qsim_submit(ctx, c.n, c.gates, psis[i], probe=True)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    results = {}
+    while len(results) < len(trace):
+        for i in range(len(trace)):
+            if ids[i] is not None and i not in results:
+                r = B.qsim_poll(ctx, ids[i])
+                if r is not None:
+                    results[i] = r
+        time.sleep(0.0005)
+    th.join()
+    stats = B.qsim_serve_get_stats(ctx)
+    B.qsim_serve_stop(ctx)
+    lat = sorted((results[i]["t_done_ns"] - (t0 + int(t * 1e9))) / 1e6 for i, (t, _) in enumerate(trace))
+    end = max(r["t_done_ns"] for r in results.values())
+    span = (end - t0) / 1e9
+    flops = sum(flops_of(B, c) for _, c in trace)
+    bad = sum(1 for r in results.values() if r["status"] != 0)
+    drift = max(r["drift_max"] for r in results.values())
+    q = lambda p: lat[min(len(lat) - 1, int(round(p * (len(lat) - 1))))]
+    return {"p50_ms": round(q(0.50), 2), "p99_ms": round(q(0.99), 2), "max_ms": round(lat[-1], 2),
+            "throughput_req_per_s": round(len(trace) / span, 2), "achieved_tflops": round(flops / span / 1e12, 2),
+            "makespan_s": round(span, 3), "failed": bad, "max_probe_drift": drift,
+            "peak_active": stats["peak_active"], "arena_high_water_gib": round(stats["arena_high_water"] / 2**30, 2)}
+
+
+def bench_served(B, ctx, torch, count: int, rate: float, seed: int, prec_name: str, arena_gib: int):
+    from paper_2305_14398_amd import workloads as W
+    prec = B.PRECISIONS[prec_name]
+    trace = W.poisson_trace(count, rate, seed, n_lo=6, n_hi=13, d_lo=10, d_hi=40)
+    arena = torch.empty(arena_gib << 30, dtype=torch.uint8, device=torch.device("cuda:0"))
+    B.qsim_autotune(ctx, prec, 7, 13)
+    offered = sum(flops_of(B, c) for _, c in trace) / trace[-1][0]
+    cont = replay_trace(B, ctx, torch, trace, prec, B.QSIM_SERVE_CONTINUOUS, arena, 64)
+    progress(f"served continuous: p50 {cont['p50_ms']} ms p99 {cont['p99_ms']} ms")
+    plain = replay_trace(B, ctx, torch, trace, prec, B.QSIM_SERVE_FIFO, arena, 1)
+    del arena
+    torch.cuda.empty_cache()
+    return {
+        "workload": f"{count} Poisson arrivals at {rate:g} req/s (seed {seed}), n ~ U{{6..13}}, depth ~ U{{10..40}}, "
+                    f"families ghz_chain/dj/qft/random; {prec_name} chains, float64 probe drift and norm per "
+                    f"request; arena {arena_gib} GiB",
+        "offered_tflops": round(offered / 1e12, 1),
+        "continuous": cont,
+        "plain_fifo": plain,
+        "p99_speedup_vs_plain": round(plain["p99_ms"] / cont["p99_ms"], 3),
+        "throughput_gain_vs_plain": round(cont["throughput_req_per_s"] / plain["throughput_req_per_s"], 3),
+    }
+
+
 def counted_traffic(profile: str, source: str):
     """HBM bytes per launch from a committed rocprofv3 counter summary, or None when the kernel source changed
     since the counters were taken (the summary stores the source's sha256)."""
@@ -107,6 +238,10 @@ def main() -> int:
     ap.add_argument("--qubits", type=int, default=11)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched", type=int, default=512, help="circuits in the batched workload (0: skip)")
+    ap.add_argument("--served", type=int, default=200, help="requests in the served trace (0: skip)")
+    ap.add_argument("--served-rate", type=float, default=200.0)
+    ap.add_argument("--served-prec", default="split_bf16", choices=sorted(PEAK_TFLOPS))
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a known-size kernel that "
                          "scales the HBM byte counters of a profiler run)")
@@ -234,8 +369,17 @@ def main() -> int:
                          "entangled), 493.10x (Deutsch-Jozsa) and 518.12x (QFT) at 11 qubits on a Quadro GP100; "
                          "different hardware, precision and baseline",
     }
+    progress(f"headline done: {tflops:.1f} TFLOP/s")
+    if args.batched:
+        out["batched"] = bench_batched(B, ctx, torch, args.batched, 0, "fp32_4m" if args.prec == "fp32_4m"
+                                       else args.prec, reps=2)
+        progress("batched done")
+    if args.served:
+        out["served"] = bench_served(B, ctx, torch, args.served, args.served_rate, 0, args.served_prec, 96)
+        progress("served done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_seconds)
+        progress("cpu baseline done")
         out["speedup_vs_cpu_oracle"] = round(tflops / out["cpu_baseline"]["value"], 1)
     ctx.close()
     print(json.dumps(out))

@@ -230,11 +230,13 @@ qsim_status qsim_unitary_chain_batched(qsim_ctx* ctx, const qsim_circuit_desc* c
                                        void* d_ws, size_t ws_bytes, void* stream);
 
 /* ---- Tile autotuner ----
- * For n in [max(n_lo, 6), n_hi] (n_hi <= 13) times grouped launches of
- * identical products with 64x64 and 128x128 tiles and records the faster tile
- * edge per n in the context (used by every later product of that precision
- * family: float32, split bf16 or split fp16; split fp16 always uses 64).  ms_out (nullable, 2 doubles per n from 6):
- * milliseconds per product for tile 64 and tile 128 (-1 if not applicable).
+ * For n in [max(n_lo, 7), n_hi] (n_hi <= 13; below 7 qubits a 128-wide tile
+ * does not fit, so n = 6 always uses 64) times grouped launches of identical
+ * products with 64x64 and 128x128 tiles and records the faster tile edge per
+ * n in the context (used by every later product of that precision family:
+ * float32, split bf16 or split fp16; split fp16 always uses 64).  ms_out
+ * (nullable, 2 doubles per n from 7): milliseconds per product for tile 64 and
+ * tile 128 (-1 if not applicable).
  * Synchronises; allocates scratch for the timing runs. */
 qsim_status qsim_autotune(qsim_ctx* ctx, int prec, int n_lo, int n_hi, double* ms_out);
 /* Current tile edge per qubit count (17 ints, index n; 0 = whole-product path). */

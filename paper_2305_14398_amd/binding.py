@@ -386,11 +386,11 @@ def qsim_unitary_chain_batched(ctx, circuits: Sequence, outputs: Sequence, prec:
            "qsim_unitary_chain_batched")
 
 
-def qsim_autotune(ctx, prec: int, n_lo: int = 6, n_hi: int = 11) -> dict:
-    """Returns {n: (ms per product with 64-tiles, with 128-tiles)} and stores the choice in the context."""
-    out = (ctypes.c_double * (2 * (n_hi - 5)))()
+def qsim_autotune(ctx, prec: int, n_lo: int = 7, n_hi: int = 11) -> dict:
+    """Returns {n: (ms per product with 64-tiles, with 128-tiles)} for n >= 7 and stores the choice in the context."""
+    out = (ctypes.c_double * (2 * max(1, n_hi - 6)))()
     _check(lib().qsim_autotune(_h(ctx), prec, n_lo, n_hi, out), "qsim_autotune")
-    return {n: (out[2 * (n - 6)], out[2 * (n - 6) + 1]) for n in range(max(6, n_lo), n_hi + 1)}
+    return {n: (out[2 * (n - 7)], out[2 * (n - 7) + 1]) for n in range(max(7, n_lo), n_hi + 1)}
 
 
 def qsim_tune_get(ctx, prec: int) -> list:

@@ -300,7 +300,7 @@ qsim_status qsim_unitary_chain_batched(qsim_ctx* ctx, const qsim_circuit_desc* c
 // work) and keep the faster per unit of work.
 qsim_status qsim_autotune(qsim_ctx* ctx, int prec, int n_lo, int n_hi, double* ms_out) {
     if (!valid_prec(prec)) return fail(QSIM_E_INVALID, "unknown precision %d", prec);
-    if (n_lo < 6) n_lo = 6;
+    if (n_lo < 7) n_lo = 7;  // below 7 qubits a 128-wide tile does not fit: nothing to choose
     if (n_hi > 13) return fail(QSIM_E_RANGE, "autotuning goes up to 13 qubits");
     if (n_lo > n_hi) return fail(QSIM_E_RANGE, "empty qubit range");
     qsim_status s = check_ctx(ctx);
@@ -329,7 +329,7 @@ qsim_status qsim_autotune(qsim_ctx* ctx, int prec, int n_lo, int n_hi, double* m
         for (int ci = 0; ci < 2 && e == hipSuccess; ++ci) {
             const int cfg = cfgs[ci];
             if (split && prec == QSIM_SPLIT_FP16 && cfg == 128) {
-                if (ms_out) ms_out[(n - 6) * 2 + ci] = -1.0;  // fp16 grouped tiles are always 64 x 64
+                if (ms_out) ms_out[(n - 7) * 2 + ci] = -1.0;  // fp16 grouped tiles are always 64 x 64
                 continue;
             }
             std::vector<GemmJob> jobs(copies);
@@ -357,7 +357,7 @@ qsim_status qsim_autotune(qsim_ctx* ctx, int prec, int n_lo, int n_hi, double* m
             float ms = 0.f;
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
             const double per = ms / reps / copies;  // per product
-            if (ms_out) ms_out[(n - 6) * 2 + ci] = per;
+            if (ms_out) ms_out[(n - 7) * 2 + ci] = per;
             if (e == hipSuccess && per < best) {
                 best = per;
                 best_cfg = cfg;

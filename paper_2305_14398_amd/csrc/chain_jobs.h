@@ -77,6 +77,7 @@ struct ChainCursor {
         Gj.n = n;
         Gj.cfg = cfg;
         Gj.tiles = tiles_of(n, cfg);
+        if (Gj.tiles < 1) return fail(QSIM_E_INVALID, "tile edge %d does not fit n = %d", cfg, n);
         Gj.tile_begin = 0;
         if (!split) {
             Gj.X = S;

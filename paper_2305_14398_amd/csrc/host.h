@@ -116,7 +116,12 @@ struct TuneTable {
             for (int n = 0; n <= QSIM_MAX_QUBITS; ++n) tile[f][n] = n >= 7 && f != 2 ? 128 : (n >= 6 ? 64 : 0);
         }
     }
-    int get(int prec, int n) const { return tile[family(prec)][n]; }
+    // Never wider than the matrix: n = 6 always uses 64, n <= 5 the whole-product path.
+    int get(int prec, int n) const {
+        if (n <= 5) return 0;
+        if (n == 6) return 64;
+        return tile[family(prec)][n];
+    }
 };
 
 // Shared by the synchronous entry points and the serving engine.

@@ -94,7 +94,13 @@ def test_graph_replays_match_eager(ctx):
 
 
 def test_autotune_records_choices_and_stays_correct(ctx):
-    timings = B.qsim_autotune(ctx, B.QSIM_FP32_4M, 7, 10)
+    # a range starting below 7 qubits must not give a 6-qubit product a 128-wide tile (that is zero tiles)
+    timings = B.qsim_autotune(ctx, B.QSIM_FP32_4M, 4, 10)
+    assert min(timings) == 7
+    assert B.qsim_tune_get(ctx, B.QSIM_FP32_4M)[6] == 64
+    c6 = W.qft(6)
+    (res6,), _ = run_batch(ctx, [c6, W.random_layers(8, 3, np.random.default_rng(0))], B.QSIM_FP32_4M)
+    assert np.abs(res6[0] - UA.circuit_unitary(6, W.gate_tuples(c6))).max() <= 1e-5
     tiles = B.qsim_tune_get(ctx, B.QSIM_FP32_4M)
     for n in range(7, 11):
         t64, t128 = timings[n]
@@ -118,3 +124,27 @@ def test_one_shot_batched_call(ctx):
     for c, o in zip(circuits, outs):
         ref = UA.circuit_unitary(c.n, W.gate_tuples(c))
         assert np.abs(G.to_complex(o) - ref).max() <= 1e-5
+
+
+@pytest.mark.parametrize("prec", [B.QSIM_FP32_4M, B.QSIM_SPLIT_BF16, B.QSIM_SPLIT_FP16])
+def test_large_circuits_batch_equals_single(ctx, prec):
+    rng = np.random.default_rng(2)
+    circuits = [W.random_layers(13, 3, rng), W.qft(12), W.random_layers(12, 4, rng), W.dj(11, 333),
+                W.random_layers(11, 5, rng), W.ghz_chain(13)]
+    outs = [G.planar(c.n) for c in circuits]
+    ws = G.workspace(B.qsim_batch_workspace_bytes(circuits, prec))
+    plan = B.BatchPlan(ctx, circuits, outs, prec, ws)
+    plan.launch()
+    G.sync()
+    plan.close()
+    del ws
+    for c, o in zip(circuits, outs):
+        U = G.planar(c.n)
+        wss = G.workspace(B.qsim_chain_workspace_bytes(c.n, prec))
+        B.qsim_unitary_chain(ctx, c.n, c.gates, prec, U, wss)
+        G.sync()
+        assert torch.equal(o, U), (c.family, c.n)
+        mx, _ = B.qsim_unitarity_drift_probe(ctx, c.n, o)
+        assert mx < (1e-3 if prec == B.QSIM_SPLIT_BF16 else 1e-5), (c.family, c.n, mx)
+        del U, wss
+    torch.cuda.empty_cache()

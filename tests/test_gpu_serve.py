@@ -145,3 +145,14 @@ def test_probe_drift_matches_full_check(ctx):
         assert mx == pytest.approx(np.abs(d).max(), rel=1e-6, abs=1e-15)
         assert l2 == pytest.approx(np.linalg.norm(d), rel=1e-6, abs=1e-15)
         assert mx < 1e-5
+
+
+def test_large_requests_continuous_equals_fifo(ctx):
+    rng = np.random.default_rng(8)
+    circuits = [W.random_layers(13, 4, rng), W.qft(12), W.random_layers(12, 6, rng), W.dj(11, 99),
+                W.random_layers(7, 12, rng), W.random_layers(11, 8, rng), W.ghz_chain(13), W.qft(9)]
+    cont, _ = serve(ctx, circuits, B.QSIM_SPLIT_BF16, arena_mib=24 << 10)
+    fifo, _ = serve(ctx, circuits, B.QSIM_SPLIT_BF16, mode=B.QSIM_SERVE_FIFO, arena_mib=24 << 10)
+    for c, (a, ra, _), (b, rb, _) in zip(circuits, cont, fifo):
+        assert ra["drift_max"] < 1e-3 and rb["drift_max"] < 1e-3, (c.family, c.n, ra["drift_max"], rb["drift_max"])
+        np.testing.assert_array_equal(a, b, err_msg=f"{c.family} n={c.n}")
