@@ -112,12 +112,14 @@ def bench_batched(B, ctx, torch, count: int, seed: int, prec_name: str, reps: in
     }
 
 
-def replay_trace(B, ctx, torch, trace, prec: int, mode: int, arena, max_active: int):
+def replay_trace(B, ctx, torch, trace, prec: int, mode: int, arena, max_active: int, policy: int = 0,
+                 budget: float = 2.0):
     import threading
     dev = torch.device("cuda:0")
     psis = [torch.empty(2 << c.n, dtype=torch.float32, device=dev) for _, c in trace]
     torch.cuda.synchronize()
-    B.qsim_serve_start(ctx, prec, arena, mode=mode, max_active=max_active, queue_capacity=len(trace) + 1)
+    B.qsim_serve_start(ctx, prec, arena, mode=mode, max_active=max_active, queue_capacity=len(trace) + 1,
+                       policy=policy, iter_budget_tflop=budget)
     ids = [None] * len(trace)
     t0 = time.monotonic_ns()
 
@@ -165,7 +167,9 @@ def bench_served(B, ctx, torch, count: int, rate: float, seed: int, prec_name: s
     B.qsim_autotune(ctx, prec, 7, 13)
     offered = sum(flops_of(B, c) for _, c in trace) / trace[-1][0]
     cont = replay_trace(B, ctx, torch, trace, prec, B.QSIM_SERVE_CONTINUOUS, arena, 64)
-    progress(f"served continuous: p50 {cont['p50_ms']} ms p99 {cont['p99_ms']} ms")
+    progress(f"served continuous (arrival order): p50 {cont['p50_ms']} ms p99 {cont['p99_ms']} ms")
+    srpt = replay_trace(B, ctx, torch, trace, prec, B.QSIM_SERVE_CONTINUOUS, arena, 64, B.QSIM_POLICY_SHORTEST, 2.0)
+    progress(f"served continuous (least work first): p50 {srpt['p50_ms']} ms p99 {srpt['p99_ms']} ms")
     plain = replay_trace(B, ctx, torch, trace, prec, B.QSIM_SERVE_FIFO, arena, 1)
     del arena
     torch.cuda.empty_cache()
@@ -174,10 +178,15 @@ def bench_served(B, ctx, torch, count: int, rate: float, seed: int, prec_name: s
                     f"families ghz_chain/dj/qft/random; {prec_name} chains, float64 probe drift and norm per "
                     f"request; arena {arena_gib} GiB",
         "offered_tflops": round(offered / 1e12, 1),
-        "continuous": cont,
+        "continuous_arrival_order": cont,
+        "continuous_least_work_first": srpt,
         "plain_fifo": plain,
-        "p99_speedup_vs_plain": round(plain["p99_ms"] / cont["p99_ms"], 3),
-        "throughput_gain_vs_plain": round(cont["throughput_req_per_s"] / plain["throughput_req_per_s"], 3),
+        "p50_speedup_vs_plain": {"arrival_order": round(plain["p50_ms"] / cont["p50_ms"], 3),
+                                 "least_work_first": round(plain["p50_ms"] / srpt["p50_ms"], 3)},
+        "p99_speedup_vs_plain": {"arrival_order": round(plain["p99_ms"] / cont["p99_ms"], 3),
+                                 "least_work_first": round(plain["p99_ms"] / srpt["p99_ms"], 3)},
+        "throughput_gain_vs_plain": {"arrival_order": round(cont["throughput_req_per_s"] / plain["throughput_req_per_s"], 3),
+                                     "least_work_first": round(srpt["throughput_req_per_s"] / plain["throughput_req_per_s"], 3)},
     }
 
 

@@ -265,6 +265,17 @@ qsim_status qsim_tune_set(qsim_ctx* ctx, int prec, int n_qubits, int tile);
 #define QSIM_SERVE_CONTINUOUS 0
 #define QSIM_SERVE_FIFO 1
 
+/* Continuous-mode policies.
+ * QSIM_POLICY_ARRIVAL: admit in arrival order; every iteration advances every
+ *   admitted request by one step.
+ * QSIM_POLICY_SHORTEST: admit the queued request with the least estimated work
+ *   (8 N^3 per chain product) that fits the arena; every iteration advances the
+ *   admitted requests in order of least remaining work until the iteration's
+ *   work reaches iter_budget_tflop (at least one request per iteration), so
+ *   short circuits are not held to the pace of large ones. */
+#define QSIM_POLICY_ARRIVAL 0
+#define QSIM_POLICY_SHORTEST 1
+
 typedef struct qsim_serve_config {
     int32_t prec;            /* qsim_precision of every served chain */
     int32_t mode;            /* QSIM_SERVE_CONTINUOUS or QSIM_SERVE_FIFO */
@@ -272,6 +283,9 @@ typedef struct qsim_serve_config {
     int32_t queue_capacity;  /* queued (not yet admitted) requests before qsim_submit returns QSIM_E_FULL */
     void* d_arena;           /* caller-owned device memory, 256-byte aligned, untouched by others while serving */
     size_t arena_bytes;
+    int32_t policy;          /* QSIM_POLICY_ARRIVAL or QSIM_POLICY_SHORTEST (continuous mode) */
+    int32_t reserved;        /* must be 0 */
+    double iter_budget_tflop;/* QSIM_POLICY_SHORTEST: product work per iteration (e.g. 2.0) */
 } qsim_serve_config;
 
 #define QSIM_REQ_DRIFT_PROBE 1u  /* also compute the probe drift (qsim_unitarity_drift_probe) */

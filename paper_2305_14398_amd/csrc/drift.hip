@@ -31,7 +31,7 @@ __device__ __forceinline__ void tile_of(int t, int T, int& tm, int& tn) {
     tn = tm + t;
 }
 
-__global__ __launch_bounds__(256) void drift_mfma_kernel(int n, const float* __restrict__ U, double* __restrict__ partials) {
+__global__ __launch_bounds__(256, 3) void drift_mfma_kernel(int n, const float* __restrict__ U, double* __restrict__ partials) {
     const int N = 1 << n;
     const size_t NN = (size_t)N * N;
     const int T = N / DT;

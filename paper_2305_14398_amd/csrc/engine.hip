@@ -97,7 +97,9 @@ struct Engine::Req {
     size_t foot = 0, arena_off = 0;
     int slot = -1;
     int next_j = 0;
+    double step_work = 0.0;  // 8 N^3: one chain product
     ChainCursor cc;
+    double remaining() const { return step_work * (double)(std::max<int>((int)off.size() - 1, 1) - next_j); }
     qsim_result res{};
 };
 
@@ -187,6 +189,7 @@ qsim_status Engine::submit(const qsim_request& r, uint64_t* id_out) {
     q->d_U = r.d_U;
     q->flags = r.flags;
     q->foot = footprint(q->n, r);
+    q->step_work = 8.0 * (double)(1ll << (3 * q->n));
     if (q->foot > cfg_.arena_bytes)
         return fail(QSIM_E_OOM, "request needs %zu arena bytes, the arena has %zu", q->foot, cfg_.arena_bytes);
     q->res.status = QSIM_PENDING;
@@ -236,13 +239,38 @@ hipEvent_t Engine::event() {
     return e;
 }
 
-// Caller holds mu_.  Moves queue heads to the active set while they fit.
+// Caller holds mu_.  Moves queued requests to the active set while they fit:
+// queue heads in arrival order, or the least estimated work first.
 void Engine::admit_locked() {
+    const bool shortest = cfg_.policy == QSIM_POLICY_SHORTEST && cfg_.mode == QSIM_SERVE_CONTINUOUS;
     while (!queue_.empty() && (int)active_.size() < cfg_.max_active && !free_slots_.empty()) {
-        Req* q = queue_.front();
+        auto pick = queue_.begin();
         size_t off = 0;
-        if (!arena_->alloc(q->foot, off)) break;  // strict arrival order: wait for room
-        queue_.pop_front();
+        if (shortest) {
+            // the smallest request that fits; ties keep arrival order
+            auto best = queue_.end();
+            for (auto it = queue_.begin(); it != queue_.end(); ++it)
+                if (best == queue_.end() || (*it)->remaining() < (*best)->remaining()) best = it;
+            pick = best;
+            if (!arena_->alloc((*pick)->foot, off)) {
+                // try others in increasing work order until one fits
+                std::vector<std::deque<Req*>::iterator> order;
+                for (auto it = queue_.begin(); it != queue_.end(); ++it) order.push_back(it);
+                std::stable_sort(order.begin(), order.end(),
+                                 [](auto a, auto b) { return (*a)->remaining() < (*b)->remaining(); });
+                pick = queue_.end();
+                for (auto it : order)
+                    if (arena_->alloc((*it)->foot, off)) {
+                        pick = it;
+                        break;
+                    }
+                if (pick == queue_.end()) break;
+            }
+        } else if (!arena_->alloc((*pick)->foot, off)) {
+            break;  // strict arrival order: wait for room
+        }
+        Req* q = *pick;
+        queue_.erase(pick);
         q->arena_off = off;
         q->slot = free_slots_.back();
         free_slots_.pop_back();
@@ -330,6 +358,16 @@ hipError_t Engine::iterate(std::deque<Inflight>& inflight) {
     {
         std::lock_guard<std::mutex> lk(mu_);
         work = active_;
+    }
+    if (cfg_.policy == QSIM_POLICY_SHORTEST) {
+        // least remaining work first, up to the iteration budget (at least one request)
+        std::stable_sort(work.begin(), work.end(),
+                         [](const Req* a, const Req* b) { return a->remaining() < b->remaining(); });
+        const double budget = cfg_.iter_budget_tflop * 1e12;
+        double used = 0.0;
+        size_t keep = 0;
+        while (keep < work.size() && (keep == 0 || used + work[keep]->step_work <= budget)) used += work[keep++]->step_work;
+        work.resize(keep);
     }
     // largest circuits first: the persistent grid then ends on small tiles
     std::stable_sort(work.begin(), work.end(), [](const Req* a, const Req* b) { return a->n > b->n; });
@@ -455,6 +493,11 @@ qsim_status qsim_serve_start(qsim_ctx* ctx, const qsim_serve_config* cfg) {
     if (cfg->queue_capacity < 1) return fail(QSIM_E_RANGE, "queue_capacity must be >= 1");
     if (cfg->d_arena == nullptr || !aligned(cfg->d_arena) || cfg->arena_bytes < 256)
         return fail(QSIM_E_INVALID, "arena is NULL, unaligned or empty");
+    if (cfg->policy != QSIM_POLICY_ARRIVAL && cfg->policy != QSIM_POLICY_SHORTEST)
+        return fail(QSIM_E_INVALID, "unknown policy %d", cfg->policy);
+    if (cfg->reserved != 0) return fail(QSIM_E_INVALID, "reserved field must be 0");
+    if (cfg->policy == QSIM_POLICY_SHORTEST && !(cfg->iter_budget_tflop > 0.0))
+        return fail(QSIM_E_INVALID, "iter_budget_tflop must be positive");
     qsim_status s = check_ctx(ctx);
     if (s != QSIM_OK) return s;
     if (ctx->engine) return fail(QSIM_E_INVALID, "a serving engine is already running on this context");

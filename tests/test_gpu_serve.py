@@ -22,12 +22,12 @@ def ctx():
 
 
 def serve(ctx, circuits, prec, mode=B.QSIM_SERVE_CONTINUOUS, max_active=64, arena_mib=2048, want_U=False,
-          stagger=0.0):
+          stagger=0.0, policy=B.QSIM_POLICY_ARRIVAL, budget=2.0):
     arena = torch.empty(arena_mib << 20, dtype=torch.uint8, device=G.DEV)
     psis = [torch.empty(2 << c.n, dtype=torch.float32, device=G.DEV) for c in circuits]
     Us = [G.planar(c.n) if want_U else None for c in circuits]
     G.sync()
-    B.qsim_serve_start(ctx, prec, arena, mode=mode, max_active=max_active)
+    B.qsim_serve_start(ctx, prec, arena, mode=mode, max_active=max_active, policy=policy, iter_budget_tflop=budget)
     try:
         ids = []
         for c, p, U in zip(circuits, psis, Us):
@@ -156,3 +156,26 @@ def test_large_requests_continuous_equals_fifo(ctx):
     for c, (a, ra, _), (b, rb, _) in zip(circuits, cont, fifo):
         assert ra["drift_max"] < 1e-3 and rb["drift_max"] < 1e-3, (c.family, c.n, ra["drift_max"], rb["drift_max"])
         np.testing.assert_array_equal(a, b, err_msg=f"{c.family} n={c.n}")
+
+
+def test_shortest_policy_gives_identical_results_and_finishes_small_first(ctx):
+    big = [W.random_layers(12, 6, np.random.default_rng(s)) for s in range(2)]
+    small = W.batch_mixed(20, seed=13, n_lo=4, n_hi=8, d_lo=2, d_hi=10)
+    circuits = big + small  # the large ones arrive first
+    arrival, _ = serve(ctx, circuits, B.QSIM_SPLIT_BF16)
+    shortest, stats = serve(ctx, circuits, B.QSIM_SPLIT_BF16, policy=B.QSIM_POLICY_SHORTEST, budget=0.05)
+    for (a, ra, _), (b, rb, _) in zip(arrival, shortest):
+        np.testing.assert_array_equal(a, b)
+        assert rb["status"] == B.QSIM_OK
+    # with least-work-first, every small request is done before either large one
+    last_small = max(r["t_done_ns"] for _, r, _ in shortest[2:])
+    first_big = min(r["t_done_ns"] for _, r, _ in shortest[:2])
+    assert last_small <= first_big
+
+
+def test_policy_validation(ctx):
+    arena = torch.empty(1 << 20, dtype=torch.uint8, device=G.DEV)
+    with pytest.raises(B.QsimError, match="policy"):
+        B.qsim_serve_start(ctx, B.QSIM_FP32_4M, arena, policy=5)
+    with pytest.raises(B.QsimError, match="budget"):
+        B.qsim_serve_start(ctx, B.QSIM_FP32_4M, arena, policy=B.QSIM_POLICY_SHORTEST, iter_budget_tflop=0.0)
