@@ -13,6 +13,15 @@
 namespace qsim {
 namespace {
 
+// Tile visited by workgroup `bid` in round `r` of a persistent grid of `grid`
+// workgroups (a multiple of 8): blocks are dispatched round-robin over the 8
+// XCDs, so within each round the XCD of block b takes a contiguous slice of the
+// round's tile ids, which keeps its tiles' A and B panels together in its L2.
+__device__ __forceinline__ int persistent_tile(int r, int bid, int grid) {
+    if (grid & 7) return r * grid + bid;
+    return r * grid + (bid & 7) * (grid >> 3) + (bid >> 3);
+}
+
 template <class Job>
 __device__ __forceinline__ int find_job(const Job* __restrict__ jobs, int njobs, int t, int Job::*begin) {
     int lo = 0, hi = njobs - 1;
@@ -49,7 +58,10 @@ __global__ __launch_bounds__(256) void grouped_f32_kernel(const GemmJob* __restr
     using T128 = F32Tile<2, 2, 2, 2, GAUSS>;
     using T64 = F32Tile<2, 2, 1, 1, GAUSS>;
     __shared__ __attribute__((aligned(16))) float smem[T128::SMEM_FLOATS];
-    for (int t = blockIdx.x; t < total_tiles; t += gridDim.x) {
+    const int rounds = (total_tiles + gridDim.x - 1) / gridDim.x;
+    for (int r = 0; r < rounds; ++r) {
+        const int t = persistent_tile(r, blockIdx.x, gridDim.x);
+        if (t >= total_tiles) continue;
         const int j = find_job(jobs, njobs, t, &GemmJob::tile_begin);
         const GemmJob& J = jobs[j];
         const int local = t - J.tile_begin;
@@ -79,7 +91,10 @@ __global__ __launch_bounds__(256) void grouped_split_kernel(const GemmJob* __res
     using T128 = SplitTile<2, 2, 2, 2, FMT>;
     using T64 = SplitTile<2, 2, 1, 1, FMT>;
     __shared__ u32x4 smem[BIG ? T128::SMEM_CHUNKS : T64::SMEM_CHUNKS];
-    for (int t = blockIdx.x; t < total_tiles; t += gridDim.x) {
+    const int rounds = (total_tiles + gridDim.x - 1) / gridDim.x;
+    for (int r = 0; r < rounds; ++r) {
+        const int t = persistent_tile(r, blockIdx.x, gridDim.x);
+        if (t >= total_tiles) continue;
         const int j = find_job(jobs, njobs, t, &GemmJob::tile_begin);
         const GemmJob& J = jobs[j];
         const int local = t - J.tile_begin;
