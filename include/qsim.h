@@ -177,6 +177,18 @@ qsim_status qsim_unitary_chain(qsim_ctx* ctx, int n_qubits, const qsim_gate* gat
 qsim_status qsim_apply_state(qsim_ctx* ctx, int n_qubits, const void* d_U, const void* d_psi0,
                              void* d_psi, double* d_prob, double* h_norm2, void* stream);
 
+/* Measurement (the paper's simulateAndCollapse, Section 5.2.3): draws `shots`
+ * basis-state indices with probabilities d_prob (N float64 values, e.g. from
+ * qsim_apply_state; they need not sum exactly to 1).  The caller supplies the
+ * random numbers: d_uniform holds `shots` float64 values in [0, 1), and shot k
+ * is the smallest index i with u_k * C[N-1] < C[i], where C is the cumulative
+ * sum of d_prob in float64 (each of 1024 threads sums a contiguous chunk, chunk
+ * totals are scanned in a fixed order).  d_out: `shots` int64.  Uses the
+ * context's scratch, like the drift calls: calls on one context must not
+ * overlap on different streams. */
+qsim_status qsim_sample(qsim_ctx* ctx, int n_qubits, const double* d_prob, const double* d_uniform, int shots,
+                        int64_t* d_out, void* stream);
+
 /* Unitarity drift of a row-major planar complex64 U (Section 2.3: a gate
  * matrix is unitary iff U^H = U^-1): computes D = U^H U - I in float64 and
  * returns h_out[0] = max |D_ij| and h_out[1] = ||D||_F / sqrt(N).  No N x N

@@ -16,9 +16,14 @@ Two independent routes:
   identity or to a state vector, with the per-amplitude update of the
   full-state-vector method (Appendix A, Eq. 12).
 
+:mod:`oracle.measure` draws measurement outcomes from a state's
+probabilities by inverse-CDF sampling with caller-supplied uniforms (the
+collapsing method of the Simulator interface, Section 5.2.3).
+
 Parity status: every function here is pinned by the tests in
 ``tests/test_oracle_pins.py`` (printed matrices of Table 1 and Eq. 8-11,
 closed forms for GHZ, QFT and Deutsch-Jozsa, unitarity, brute-force 1-2 qubit
-matrices, and route A == route B).  No function is parity unpinned.
+matrices, route A == route B, and for the sampler one-hot, uniform-grid and
+Deutsch-Jozsa outcomes).  No function is parity unpinned.
 """
-from . import gates, unitary, fsv, metrics  # noqa: F401
+from . import gates, unitary, fsv, metrics, measure  # noqa: F401

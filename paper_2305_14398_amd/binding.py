@@ -127,6 +127,7 @@ def lib() -> ctypes.CDLL:
         "qsim_unitary_chain_batched": (i32, [vp, ctypes.POINTER(qsim_circuit_desc), i32, i32, vp, sz, vp]),
         "qsim_autotune": (i32, [vp, i32, i32, i32, ctypes.POINTER(dbl)]),
         "qsim_unitarity_drift_probe": (i32, [vp, i32, vp, ctypes.POINTER(dbl), vp]),
+        "qsim_sample": (i32, [vp, i32, vp, vp, i32, vp, vp]),
         "qsim_serve_start": (i32, [vp, ctypes.POINTER(qsim_serve_config)]),
         "qsim_serve_stop": (i32, [vp]),
         "qsim_submit": (i32, [vp, ctypes.POINTER(qsim_request), ctypes.POINTER(ctypes.c_uint64)]),
@@ -453,3 +454,8 @@ def qsim_serve_get_stats(ctx) -> dict:
     out = qsim_serve_stats()
     _check(lib().qsim_serve_get_stats(_h(ctx), ctypes.byref(out)), "qsim_serve_get_stats")
     return {f: getattr(out, f) for f, _ in qsim_serve_stats._fields_}
+
+
+def qsim_sample(ctx, n_qubits: int, d_prob, d_uniform, shots: int, d_out, stream=None) -> None:
+    st = _stream(stream, _dev(ctx)) if _h(ctx) else None
+    _check(lib().qsim_sample(_h(ctx), n_qubits, _ptr(d_prob), _ptr(d_uniform), shots, _ptr(d_out), st), "qsim_sample")

@@ -554,4 +554,21 @@ qsim_status qsim_unitarity_drift_probe(qsim_ctx* ctx, int n_qubits, const void* 
     return ok();
 }
 
+qsim_status qsim_sample(qsim_ctx* ctx, int n_qubits, const double* d_prob, const double* d_uniform, int shots,
+                        int64_t* d_out, void* stream) {
+    qsim_status s = QSIM_OK;
+    if (!valid_n(n_qubits)) return fail(QSIM_E_RANGE, "n_qubits %d outside 1..%d", n_qubits, QSIM_MAX_QUBITS);
+    if (shots < 0) return fail(QSIM_E_INVALID, "negative shot count");
+    if (!d_prob || !aligned(d_prob)) return fail(QSIM_E_INVALID, "d_prob is NULL or not 256-byte aligned");
+    if (shots > 0 && (!d_uniform || !d_out || !aligned(d_uniform) || !aligned(d_out)))
+        return fail(QSIM_E_INVALID, "d_uniform / d_out is NULL or not 256-byte aligned");
+    s = check_ctx(ctx);
+    if (s != QSIM_OK) return s;
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return device_fail("hipSetDevice", g.err);
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    hipError_t e = launch_sample(n_qubits, d_prob, d_uniform, shots, d_out, ctx->d_scratch + kProbeScratchOffset, hs);
+    return e == hipSuccess ? ok() : device_fail("sample launch", e);
+}
+
 }  // extern "C"

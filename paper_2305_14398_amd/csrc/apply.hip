@@ -95,7 +95,62 @@ __global__ __launch_bounds__(256) void prob_kernel(int n, const float* __restric
     prob[i] = (re * re + im * im) / norm2[0];
 }
 
+// Measurement (the paper's simulateAndCollapse, Section 5.2.3): the
+// cumulative distribution of the float64 probabilities in a fixed order (each
+// of 1024 threads sums a contiguous chunk, then an exclusive scan of the chunk
+// totals), then one binary search per shot.
+__global__ __launch_bounds__(1024) void cdf_kernel(int n, const double* __restrict__ prob, double* __restrict__ cdf) {
+    const int N = 1 << n;
+    const int chunk = (N + 1023) / 1024;
+    const int lo = threadIdx.x * chunk;
+    const int hi = min(lo + chunk, N);
+    __shared__ double tot[1024];
+    double s = 0.0;
+    for (int i = lo; i < hi; ++i) s += prob[i];
+    tot[threadIdx.x] = s;
+    __syncthreads();
+    // Hillis-Steele inclusive scan of the chunk totals (fixed order)
+    for (int off = 1; off < 1024; off <<= 1) {
+        const double v = (int)threadIdx.x >= off ? tot[threadIdx.x - off] : 0.0;
+        __syncthreads();
+        tot[threadIdx.x] += v;
+        __syncthreads();
+    }
+    double run = threadIdx.x ? tot[threadIdx.x - 1] : 0.0;
+    for (int i = lo; i < hi; ++i) {
+        run += prob[i];
+        cdf[i] = run;
+    }
+}
+
+// Shot k: the smallest index i with u_k * cdf[N-1] < cdf[i].
+__global__ __launch_bounds__(256) void sample_kernel(int n, const double* __restrict__ cdf, const double* __restrict__ u,
+                                                     int shots, int64_t* __restrict__ out) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= shots) return;
+    const int N = 1 << n;
+    const double target = u[k] * cdf[N - 1];
+    int lo = 0, hi = N - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (cdf[mid] > target)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    out[k] = lo;
+}
+
 }  // namespace
+
+hipError_t launch_sample(int n, const double* prob, const double* uniforms, int shots, int64_t* out, double* cdf,
+                         hipStream_t stream) {
+    hipLaunchKernelGGL(cdf_kernel, dim3(1), dim3(1024), 0, stream, n, prob, cdf);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || shots == 0) return e;
+    hipLaunchKernelGGL(sample_kernel, dim3((shots + 255) / 256), dim3(256), 0, stream, n, cdf, uniforms, shots, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_apply_state(int n, const float* U_row, const float* psi0, float* psi, double* prob, double* d_norm2,
                               hipStream_t stream) {

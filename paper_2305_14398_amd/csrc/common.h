@@ -86,6 +86,8 @@ hipError_t launch_grouped_gemm(int prec, const GemmJob* jobs, int njobs, int tot
                                hipStream_t stream);
 hipError_t launch_apply_state(int n, const float* U_row, const float* psi0, float* psi, double* prob,
                               double* d_norm2, hipStream_t stream);
+hipError_t launch_sample(int n, const double* prob, const double* uniforms, int shots, int64_t* out, double* cdf,
+                         hipStream_t stream);
 hipError_t launch_drift(int n, const float* U_row, double* partials, int max_partials, double* d_out,
                         hipStream_t stream);
 

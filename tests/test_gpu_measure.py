@@ -1,0 +1,126 @@
+"""Measurement (the collapsing method of the Simulator interface, Section 5.2.3) on the GPU.
+
+The outcome of a shot is an index, decided by float64 comparisons against the
+cumulative distribution.  The GPU and the oracle build that distribution in
+different summation orders, so two results can legitimately differ only where
+u * C_{N-1} falls within rounding distance of a boundary C_i; every other shot
+must agree exactly, and a differing shot must be a valid outcome under the
+oracle's distribution widened by that rounding distance.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import measure, unitary as UA  # noqa: E402
+from paper_2305_14398_amd import binding as B  # noqa: E402
+from paper_2305_14398_amd import workloads as W  # noqa: E402
+from tests import gpu_util as G  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = G.DEV
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = B.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_sample(ctx, n, prob, u):
+    d_prob = torch.as_tensor(np.asarray(prob, dtype=np.float64), device=DEV)
+    shots = len(u)
+    d_u = torch.as_tensor(np.asarray(u, dtype=np.float64), device=DEV) if shots else None
+    d_out = torch.full((max(shots, 1),), -1, dtype=torch.int64, device=DEV)
+    B.qsim_sample(ctx, n, d_prob, d_u, shots, d_out if shots else None)
+    G.sync()
+    return d_out[:shots].cpu().numpy()
+
+
+def assert_same_outcomes(got, prob, u):
+    ref = measure.sample(prob, u)
+    c = measure.cumulative(prob)
+    t = np.asarray(u) * c[-1]
+    eps = 64 * np.finfo(np.float64).eps * c[-1]
+    bad = np.nonzero(got != ref)[0]
+    assert np.all((got >= 0) & (got < len(prob)))
+    for k in bad:
+        g = int(got[k])
+        lo = c[g - 1] if g > 0 else 0.0
+        assert lo - eps <= t[k] < c[g] + eps, (k, g, int(ref[k]))
+    assert bad.size <= max(2, len(u) // 10000), bad.size
+
+
+@pytest.mark.parametrize("n,shots", [(1, 7), (3, 1000), (6, 0), (10, 1), (11, 100003), (16, 65536)])
+def test_sampler_matches_oracle_on_same_probabilities(ctx, n, shots):
+    rng = np.random.default_rng(100 + n)
+    p = rng.random(1 << n) ** 4
+    p[rng.random(1 << n) < 0.3] = 0.0
+    p[-1] = 0.0
+    u = rng.random(shots)
+    got = gpu_sample(ctx, n, p, u)
+    assert got.shape == (shots,)
+    assert_same_outcomes(got, p, u)
+    if shots:
+        assert np.all(p[got] > 0), "a zero-probability outcome was drawn"
+
+
+@pytest.mark.parametrize("n", [4, 16])
+def test_sampler_uniform_grid_is_exact(ctx, n):
+    """Uniform p = 2^-n sums exactly in float64, so u = (k + 1/2) / N must land on k for every k."""
+    N = 1 << n
+    p = np.full(N, 1.0 / N)
+    k = np.arange(N)
+    np.testing.assert_array_equal(gpu_sample(ctx, n, p, (k + 0.5) / N), k)
+    edge = gpu_sample(ctx, n, p, np.array([0.0, np.nextafter(1.0, 0.0)]))
+    np.testing.assert_array_equal(edge, [0, N - 1])
+
+
+def test_sampler_one_hot_and_unnormalised(ctx):
+    p = np.zeros(1 << 9)
+    p[300] = 2.5
+    u = np.random.default_rng(1).random(5000)
+    assert np.all(gpu_sample(ctx, 9, p, u) == 300)
+    p = np.array([1.0, 3.0, 0.0, 4.0])
+    u = np.array([0.0, 0.124, 0.125, 0.49, 0.5, 0.999])
+    np.testing.assert_array_equal(gpu_sample(ctx, 2, p, u), [0, 0, 1, 1, 3, 3])
+
+
+@pytest.mark.parametrize("n", [5, 11])
+def test_simulate_and_collapse_deutsch_jozsa(ctx, n):
+    """Whole path on the GPU (chain, state and probabilities, sampling): the input register reads
+    the oracle mask on every shot and the ancilla is an even coin, as the oracle predicts."""
+    N = 1 << n
+    u = np.random.default_rng(n).random(20000)
+    for mask in (0, W.dj_mask(n, 7)):
+        circ = W.dj(n, mask)
+        U = G.planar(n)
+        ws = G.workspace(B.qsim_chain_workspace_bytes(n, B.QSIM_FP32_4M))
+        B.qsim_unitary_chain(ctx, n, circ.gates, B.QSIM_FP32_4M, U, ws)
+        psi = torch.empty(2 * N, dtype=torch.float32, device=DEV)
+        prob = torch.empty(N, dtype=torch.float64, device=DEV)
+        B.qsim_apply_state(ctx, n, U, None, psi, prob)
+        d_u = torch.as_tensor(u, device=DEV)
+        out = torch.empty(len(u), dtype=torch.int64, device=DEV)
+        B.qsim_sample(ctx, n, prob, d_u, len(u), out)
+        G.sync()
+        shots = out.cpu().numpy()
+        assert np.all((shots & ((1 << (n - 1)) - 1)) == mask)
+        ref = measure.sample(UA.probabilities(UA.simulate_full_state(n, W.gate_tuples(circ))), u)
+        # the two outcomes differ only in the ancilla bit, split at u = 1/2 (up to float32 rounding of p)
+        keep = np.abs(u - 0.5) > 1e-5
+        np.testing.assert_array_equal(shots[keep] >> (n - 1), ref[keep] >> (n - 1))
+
+
+def test_sampler_validation(ctx):
+    p = torch.ones(8, dtype=torch.float64, device=DEV)
+    out = torch.empty(4, dtype=torch.int64, device=DEV)
+    u = torch.zeros(4, dtype=torch.float64, device=DEV)
+    with pytest.raises(B.QsimError, match="negative"):
+        B.qsim_sample(ctx, 3, p, u, -1, out)
+    with pytest.raises(B.QsimError, match="d_uniform"):
+        B.qsim_sample(ctx, 3, p, None, 4, out)
+    with pytest.raises(B.QsimError):
+        B.qsim_sample(ctx, 17, p, u, 4, out)

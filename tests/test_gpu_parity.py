@@ -293,3 +293,43 @@ def test_random_thirteen_qubits_fp32(ctx):
     cols = W.random_columns(n, 16, 2)
     Uc = U[:, :, cols].cpu().numpy().astype(np.float64)
     assert np.abs((Uc[0] + 1j * Uc[1]) - fsv.unitary_columns(n, g, cols)).max() <= AMP_TOL
+
+
+# --- maximum sizes --------------------------------------------------------------------------
+
+def test_expand_sixteen_qubits_sixteen_gates(ctx):
+    """The largest step: n = 16 (a 32 GiB operator) with 16 gates, one per qubit; sampled columns."""
+    n = 16
+    rng = np.random.default_rng(16)
+    names = ["H", "X", "Y", "Z", "S", "T", "RX", "RY", "RZ", "R"]
+    step = []
+    for q in range(n):
+        nm = names[int(rng.integers(0, len(names)))]
+        step.append((nm, (q,), float(rng.uniform(0, 2 * math.pi)) if nm in W.ANGLED else None))
+    S = torch.empty((2, 1 << n, 1 << n), dtype=torch.float32, device=G.DEV)
+    B.qsim_build_step(ctx, n, step, B.QSIM_FP32_4M, B.QSIM_LAYOUT_ROW, S)
+    G.sync()
+    cols = W.random_columns(n, 6, 3)
+    ref = fsv.unitary_columns(n, step, cols)
+    got = S[:, :, cols].cpu().numpy().astype(np.float64)
+    got = got[0] + 1j * got[1]
+    assert np.all(np.abs(got - ref) <= 2.0 ** -23 * np.abs(ref) + 1e-30)
+    del S
+    torch.cuda.empty_cache()
+
+
+def test_chain_fourteen_qubits_sampled(ctx):
+    n = 14
+    c = W.random_layers(n, 1, np.random.default_rng(14))  # a few steps of 16384^3 products
+    g = W.gate_tuples(c)
+    U = gpu_chain(ctx, n, c.gates, B.QSIM_FP32_4M)
+    cols = W.random_columns(n, 8, 4)
+    Uc = U[:, :, cols].cpu().numpy().astype(np.float64)
+    assert np.abs((Uc[0] + 1j * Uc[1]) - fsv.unitary_columns(n, g, cols)).max() <= AMP_TOL
+    d_psi = torch.empty(2 << n, dtype=torch.float32, device=G.DEV)
+    B.qsim_apply_state(ctx, n, U, None, d_psi)
+    assert np.abs(G.vec_to_complex(d_psi) - fsv.final_state(n, g)).max() <= AMP_TOL
+    mx, _ = B.qsim_unitarity_drift_probe(ctx, n, U)
+    assert mx < 1e-5
+    del U
+    torch.cuda.empty_cache()

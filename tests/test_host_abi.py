@@ -154,6 +154,15 @@ def test_multiply_apply_drift_validation_without_device():
     _expect(B.QSIM_E_INVALID, B.qsim_unitarity_drift, None, 5, FAKE, match="context is NULL")
 
 
+def test_sample_validation_without_device():
+    _expect(B.QSIM_E_RANGE, B.qsim_sample, None, 0, FAKE, FAKE, 4, FAKE)
+    _expect(B.QSIM_E_RANGE, B.qsim_sample, None, 17, FAKE, FAKE, 4, FAKE)
+    _expect(B.QSIM_E_INVALID, B.qsim_sample, None, 3, FAKE, FAKE, -1, FAKE, match="negative")
+    _expect(B.QSIM_E_INVALID, B.qsim_sample, None, 3, FAKE + 8, FAKE, 4, FAKE, match="aligned")
+    _expect(B.QSIM_E_INVALID, B.qsim_sample, None, 3, FAKE, None, 4, FAKE, match="d_uniform")
+    _expect(B.QSIM_E_INVALID, B.qsim_sample, None, 3, FAKE, None, 0, None, match="context is NULL")
+
+
 def test_last_error_is_thread_local_and_resets():
     _expect(B.QSIM_E_RANGE, B.qsim_pack_steps, 0, [])
     msg = B.qsim_last_error()

@@ -251,3 +251,73 @@ def test_metrics():
     assert metrics.unitarity_drift(np.eye(8)) == (0.0, 0.0)
     other = W.random_state(5, 2)
     assert metrics.fidelity(other, psi) == pytest.approx(abs(np.vdot(psi, other)) ** 2, abs=1e-14)
+
+
+# --- Measurement by inverse-CDF sampling (Section 5.2.3, simulateAndCollapse) -------------
+
+def test_sampler_one_hot_and_zero_probability_outcomes():
+    from oracle import measure
+    rng = np.random.default_rng(5)
+    u = rng.random(1000)
+    for N, hot in ((1, 0), (8, 0), (8, 5), (8, 7), (64, 33)):
+        p = np.zeros(N)
+        p[hot] = 1.0
+        assert np.all(measure.sample(p, u) == hot)
+    # an outcome with zero probability is never drawn, whatever the uniform
+    p = np.array([0.0, 0.25, 0.0, 0.0, 0.75, 0.0])
+    s = measure.sample(p, np.linspace(0.0, 1.0, 10001, endpoint=False))
+    assert set(np.unique(s)) == {1, 4}
+
+
+def test_sampler_uniform_grid_closed_form():
+    """Uniform p over N outcomes: u = (k + 1/2) / N lands on outcome k, and any u on floor(u N)."""
+    from oracle import measure
+    for N in (2, 16, 1024):
+        p = np.full(N, 1.0 / N)
+        k = np.arange(N)
+        np.testing.assert_array_equal(measure.sample(p, (k + 0.5) / N), k)
+        u = np.random.default_rng(N).random(4096)
+        np.testing.assert_array_equal(measure.sample(p * 7.0, u), np.floor(u * N).astype(np.int64))
+
+
+def test_sampler_grid_counts_equal_probabilities():
+    """On the grid u = j / M each outcome receives M * p_i points, to within one, and the map is monotone."""
+    from oracle import measure
+    rng = np.random.default_rng(11)
+    p = rng.random(37) ** 3
+    p[[3, 17]] = 0.0
+    p /= p.sum()
+    M = 200_000
+    s = measure.sample(p, np.arange(M) / M)
+    assert np.all(np.diff(s) >= 0)
+    counts = np.bincount(s, minlength=p.size)
+    assert np.max(np.abs(counts - M * p)) <= 1.0 + 1e-9
+    assert counts[3] == 0 and counts[17] == 0
+
+
+def test_sampler_unnormalised_input_is_scaled_by_its_total():
+    from oracle import measure
+    p = np.array([1.0, 3.0, 0.0, 4.0])
+    u = np.array([0.0, 0.124, 0.125, 0.49, 0.5, 0.999])
+    np.testing.assert_array_equal(measure.sample(p, u), [0, 0, 1, 1, 3, 3])
+
+
+@pytest.mark.parametrize("n", [3, 5, 7])
+def test_deutsch_jozsa_measurement_reads_the_mask(n):
+    """Deutsch-Jozsa (Section 2.5): the input register collapses to |0...0> for the constant
+    function; with f(x) = parity(mask & x) it collapses to |mask>, so never to all zeros when
+    balanced.  The ancilla stays in (|0> - |1>)/sqrt(2) and reads 0 or 1 with probability 1/2."""
+    from oracle import measure
+    u = np.random.default_rng(n).random(4000)
+    for mask in (0, 1, (1 << (n - 1)) - 1, W.dj_mask(n, 3)):
+        psi = UA.simulate_full_state(n, W.gate_tuples(W.dj(n, mask)))
+        shots = measure.sample(UA.probabilities(psi), u)
+        assert np.all((shots & ((1 << (n - 1)) - 1)) == mask)
+        ancilla = (shots >> (n - 1)) & 1
+        assert 0.45 < ancilla.mean() < 0.55
+
+
+def test_collapse_is_the_basis_state():
+    from oracle import measure
+    psi = measure.collapse(3, 6)
+    assert psi[6] == 1.0 and np.count_nonzero(psi) == 1
