@@ -192,6 +192,45 @@ def bench_served(B, ctx, torch, count: int, rate: float, seed: int, prec_name: s
     }
 
 
+def bench_fsv(B, ctx, torch, n: int, reps: int):
+    """Full-state-vector path: qft(n) and random_layers(n, 20) from |0...0>, in place on a 2^n state.
+    HBM roofline: every pass reads and writes the state once, 16 bytes per amplitude."""
+    import numpy as np
+    from paper_2305_14398_amd import workloads as W
+    N = 1 << n
+    psi = torch.empty(2 * N, dtype=torch.float32, device=torch.device("cuda:0"))
+    out = {}
+    for name, c in (("qft", W.qft(n)), ("random_layers_20", W.random_layers(n, 20, np.random.default_rng(0)))):
+        g = W.gate_tuples(c)
+        with B.FsvPlan(ctx, n, g) as plan:
+            info = plan.info()
+            B.qsim_fsv_init_basis(ctx, n, 0, psi)
+            plan.run(psi)  # warm-up
+            torch.cuda.synchronize()
+            B.qsim_profile_enable(ctx, 1)
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                plan.run(psi)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / reps
+            launches, kernel_ms = B.qsim_profile_read(ctx)["fsv"]
+            B.qsim_profile_enable(ctx, 0)
+        per_pass_ms = kernel_ms / max(launches, 1)
+        achieved = 16.0 * N / (per_pass_ms * 1e-3) / 1e9
+        out[name] = {"gates": len(g), "ops": info["ops"], "passes": info["passes"], "ms": round(wall * 1e3, 3),
+                     "gates_per_s": round(len(g) / wall, 1), "avg_pass_ms": round(per_pass_ms, 4),
+                     "hbm_gb_per_s": round(achieved, 1), "hbm_frac": round(achieved / 8000.0, 4),
+                     "one_launch_per_gate_ms_at_peak": round(info["ops"] * 16.0 * N / 8e12 * 1e3, 3)}
+        progress(f"fsv {name}({n}): {out[name]['passes']} passes, {out[name]['ms']} ms, {achieved:.0f} GB/s per pass")
+    del psi
+    torch.cuda.empty_cache()
+    out["workload"] = f"full-state-vector simulation of {n} qubits (planar complex64, {8 * N / 2**30:g} GiB), " \
+                      f"in place from |0...0>; {reps} runs each"
+    out["roofline"] = {"bound": "hbm", "peak": 8000.0, "unit": "GB/s",
+                       "traffic_model": "16 bytes per amplitude per pass (read + write of the state)"}
+    return out
+
+
 def counted_traffic(profile: str, source: str):
     """HBM bytes per launch from a committed rocprofv3 counter summary, or None when the kernel source changed
     since the counters were taken (the summary stores the source's sha256)."""
@@ -254,6 +293,7 @@ def main() -> int:
     ap.add_argument("--served", type=int, default=200, help="requests in the served trace (0: skip)")
     ap.add_argument("--served-rate", type=float, default=200.0)
     ap.add_argument("--served-prec", default="split_bf16", choices=sorted(PEAK_TFLOPS))
+    ap.add_argument("--fsv", type=int, default=30, help="qubits of the full-state-vector workload (0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a known-size kernel that "
                          "scales the HBM byte counters of a profiler run)")
@@ -410,6 +450,9 @@ def main() -> int:
     if args.served:
         out["served"] = bench_served(B, ctx, torch, args.served, args.served_rate, 0, args.served_prec, 96)
         progress("served done")
+    if args.fsv:
+        out["full_state"] = bench_fsv(B, ctx, torch, args.fsv, reps=3)
+        progress("full-state done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_seconds)
         progress("cpu baseline done")

@@ -79,20 +79,41 @@ typedef enum qsim_precision {
  *   RX, RY, RZ(theta) = exp(-i theta sigma_{x,y,z} / 2);
  *   U2 = the caller's 2x2 matrix in u[] (row-major (re, im) pairs);
  *   SWAP exchanges qubits `target` and `control` (the second qubit; not a
- *   controlled gate; used by the QFT figure of Section 2.5). */
+ *   controlled gate; used by the QFT figure of Section 2.5);
+ *   CUSTOM = a registered unitary (qsim_register_unitary) of m qubits applied
+ *   to the range target .. target+m-1 (Section 5.2.2: custom functions are
+ *   registered with the operation data provider, then applied to a range of
+ *   qubits); `op_id` names it, `control` must be -1. */
 typedef enum qsim_kind {
     QSIM_H = 0, QSIM_X = 1, QSIM_Y = 2, QSIM_Z = 3, QSIM_S = 4, QSIM_T = 5,
-    QSIM_R = 6, QSIM_RX = 7, QSIM_RY = 8, QSIM_RZ = 9, QSIM_U2 = 10, QSIM_SWAP = 11
+    QSIM_R = 6, QSIM_RX = 7, QSIM_RY = 8, QSIM_RZ = 9, QSIM_U2 = 10, QSIM_SWAP = 11,
+    QSIM_CUSTOM = 12
 } qsim_kind;
 
 typedef struct qsim_gate {
     int32_t kind;      /* qsim_kind */
-    int32_t target;    /* qubit the 2x2 acts on; first qubit of a SWAP */
+    int32_t target;    /* qubit the 2x2 acts on; first qubit of a SWAP; lowest qubit of a CUSTOM range */
     int32_t control;   /* control qubit, -1 if none; second qubit of a SWAP */
-    int32_t reserved;  /* must be 0 */
+    int32_t op_id;     /* QSIM_CUSTOM: id from qsim_register_unitary; 0 for every other kind */
     double theta;      /* angle of R, RX, RY, RZ; ignored otherwise */
     double u[8];       /* QSIM_U2 only: u00 re, u00 im, u01 re, u01 im, u10 .., u11 .. */
 } qsim_gate;           /* 88 bytes */
+
+/* ---- Operation data provider (Section 5.2.2) -------------------------------------------------
+ * Registers a custom unitary of m = n_qubits qubits (1 <= m <= QSIM_CUSTOM_MAX_QUBITS) under a
+ * unique name.  `matrix` is 2^m x 2^m, row-major, (re, im) float64 pairs (2 * 4^m doubles); row
+ * and column index bit k is qubit target+k of the range the operation is applied to.  The
+ * matrix is checked to be unitary (max |M^H M - I| <= 1e-9), copied, and uploaded to every
+ * visible device; entries live until the process ends.  Process-wide and thread-safe; host
+ * only when no device is visible.  QSIM_E_INVALID for a duplicate name, a non-finite entry or
+ * a non-unitary matrix; QSIM_E_RANGE for m out of range or a full registry
+ * (QSIM_CUSTOM_MAX_OPS entries).  *id_out receives the id (>= 1). */
+#define QSIM_CUSTOM_MAX_QUBITS 6
+#define QSIM_CUSTOM_MAX_OPS 4096
+qsim_status qsim_register_unitary(const char* name, int n_qubits, const double* matrix, int32_t* id_out);
+/* Looks up a registered operation by name: its id and qubit count (either out pointer may be
+ * NULL).  QSIM_E_UNKNOWN_ID if no operation has that name. */
+qsim_status qsim_find_unitary(const char* name, int32_t* id_out, int* n_qubits_out);
 
 typedef enum qsim_layout { QSIM_LAYOUT_ROW = 0, QSIM_LAYOUT_COL = 1 } qsim_layout;
 
@@ -352,13 +373,14 @@ qsim_status qsim_serve_get_stats(qsim_ctx* ctx, qsim_serve_stats* out);
  * recorded on the launch stream; qsim_profile_read waits for the timed
  * launches and returns per-class launch counts and summed durations.
  * Classes: expansion (stage 4), chain product (stage 5), apply incl. the
- * float64 norm/probabilities (stage 6), unitarity drift.  Enabling resets the
+ * float64 norm/probabilities (stage 6), unitarity drift, full-state passes.  Enabling resets the
  * totals; use from one host thread at a time. */
 #define QSIM_PROFILE_EXPAND 0
 #define QSIM_PROFILE_PRODUCT 1
 #define QSIM_PROFILE_APPLY 2
 #define QSIM_PROFILE_DRIFT 3
-#define QSIM_PROFILE_KINDS 4
+#define QSIM_PROFILE_FSV 4
+#define QSIM_PROFILE_KINDS 5
 typedef struct qsim_kernel_stats {
     int64_t count[QSIM_PROFILE_KINDS];
     double total_ms[QSIM_PROFILE_KINDS];
@@ -366,6 +388,59 @@ typedef struct qsim_kernel_stats {
 
 qsim_status qsim_profile_enable(qsim_ctx* ctx, int enable);
 qsim_status qsim_profile_read(qsim_ctx* ctx, qsim_kernel_stats* out);
+
+/* ---- Full-state-vector simulation (Appendix A, Eq. 12) ------------------------------------
+ * The gate-by-gate method that the paper names as the next backend to
+ * accelerate (Section 7): each gate updates the pairs of amplitudes whose
+ * indices differ in its target bit (only those whose control bit is 1 for a
+ * controlled gate), in place, without any 2^n x 2^n operator.  States are
+ * planar complex64: 2^n float re values then 2^n float im values (8 * 2^n
+ * bytes, 256-byte aligned, caller-owned); up to QSIM_FSV_MAX_QUBITS qubits.
+ *
+ * The library lowers each SWAP to three CNOTs and groups consecutive gates
+ * into passes over the state.  A pass names 12 local qubits: qubits
+ * 0..low_qubits-1 and n_high others; it holds only gates whose target is
+ * local, or that are diagonal (Z, S, T, R, RZ and their controlled forms,
+ * which need no local qubit); controls may be any qubit; a custom operation
+ * needs its whole range local (its matrix is rounded to float32).  Each pass reads and
+ * writes the whole state once (16 bytes per amplitude), whatever its gate
+ * count.  For n <= 12 one pass holds every gate.  Gate matrices are the
+ * float64 ones of the unitary path rounded once to float32; amplitude
+ * arithmetic is float32. */
+#define QSIM_FSV_MAX_QUBITS 34
+#define QSIM_FSV_MAX_HIGH 6
+typedef struct qsim_fsv_plan qsim_fsv_plan;
+typedef struct qsim_fsv_pass_info {
+    int32_t low_qubits;             /* qubits 0..low_qubits-1 are local */
+    int32_t n_high;                 /* further local qubits, ascending in high[] */
+    int32_t high[QSIM_FSV_MAX_HIGH]; /* -1 past n_high */
+    int32_t first_op;               /* the pass's operations (a SWAP counts three) */
+    int32_t n_ops;
+} qsim_fsv_pass_info;
+
+/* Host only (no device, no context): the pass schedule of a gate list.
+ * Writes min(capacity, passes) records and *n_passes; QSIM_E_RANGE if
+ * capacity > 0 and the schedule needs more records (capacity 0 just counts). */
+qsim_status qsim_fsv_schedule(int n_qubits, const qsim_gate* gates, int n_gates, qsim_fsv_pass_info* passes,
+                              int capacity, int* n_passes);
+/* Validates the gates, schedules them and uploads the operation table to the
+ * context's device (a synchronous copy; the plan owns that memory).  The gate
+ * array may be freed on return. */
+qsim_status qsim_fsv_plan_create(qsim_ctx* ctx, int n_qubits, const qsim_gate* gates, int n_gates,
+                                 qsim_fsv_plan** out);
+qsim_status qsim_fsv_plan_info(const qsim_fsv_plan* plan, int* n_qubits, int* n_passes, int* n_ops);
+/* Frees the plan; work already enqueued with it must have finished. */
+qsim_status qsim_fsv_plan_destroy(qsim_fsv_plan* plan);
+/* Applies the plan's circuit to d_psi in place: one launch per pass on
+ * `stream`, asynchronous.  A plan may run any number of times, on any stream
+ * of its device. */
+qsim_status qsim_fsv_run(qsim_ctx* ctx, const qsim_fsv_plan* plan, void* d_psi, void* stream);
+/* d_psi <- |basis> (asynchronous). */
+qsim_status qsim_fsv_init_basis(qsim_ctx* ctx, int n_qubits, int64_t basis, void* d_psi, void* stream);
+/* *h_norm2 <- sum |psi_i|^2 accumulated in float64 in a fixed order (waits
+ * for the stream).  Uses the context's scratch: calls on one context must not
+ * overlap on different streams. */
+qsim_status qsim_fsv_norm2(qsim_ctx* ctx, int n_qubits, const void* d_psi, double* h_norm2, void* stream);
 
 #ifdef __cplusplus
 }

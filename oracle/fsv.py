@@ -5,7 +5,9 @@ amplitudes whose indices differ only in bit i (Appendix A, Eq. 12):
     a[..0_i..] <- Ua a[..0_i..] + Ub a[..1_i..]
     a[..1_i..] <- Uc a[..0_i..] + Ud a[..1_i..]
 A controlled gate applies that update only to the pairs whose control bit is 1
-(Eq. 7); SWAP exchanges the amplitudes whose bits a and b differ.  Applied to
+(Eq. 7); SWAP exchanges the amplitudes whose bits a and b differ.  A custom
+operation M on the range a..a+m-1 (Section 5.2.2) maps, for every fixed value
+of the other bits, the 2^m amplitudes indexed by the range bits by M.  Applied to
 the columns of the identity this yields the circuit unitary column by column
 (U[:, j] = C e_j) without building any step operator, so it is independent of
 route A's Kronecker construction and of step formation.
@@ -34,8 +36,23 @@ def _pair_update(v: np.ndarray, q: int, U: np.ndarray, ctrl: int = -1) -> np.nda
     return v
 
 
+def _range_update(v: np.ndarray, a: int, M: np.ndarray) -> np.ndarray:
+    """Amplitude index i = (hi * 2^m + mid) * 2^a + lo; new[hi, r, lo] = sum_s M[r, s] v[hi, s, lo]."""
+    N, cols = v.shape
+    W = M.shape[0]
+    v4 = v.reshape(N // (W << a), W, 1 << a, cols)
+    return np.einsum("rs,hslc->hrlc", M, v4).reshape(N, cols)
+
+
 def apply_gate(v: np.ndarray, g) -> np.ndarray:
-    name, qubits, theta = g
+    name, qubits, theta = g[0], g[1], g[2]
+    if len(g) == 4:
+        if list(qubits) != list(range(min(qubits), max(qubits) + 1)):
+            raise ValueError("a custom operation acts on a contiguous ascending range of qubits")
+        M = np.asarray(g[3], dtype=np.complex128)
+        if M.shape != (1 << len(qubits),) * 2:
+            raise ValueError("custom matrix size does not match its qubit range")
+        return _range_update(v, qubits[0], M)
     if len(qubits) == 1:
         return _pair_update(v, qubits[0], G.one_qubit(name, theta))
     if name == "SWAP":

@@ -18,6 +18,12 @@ P0(control) (x) I + P1(control) (x) U(target), identities elsewhere in the
 span; SWAP is built as the product CNOT(a,b) CNOT(b,a) CNOT(a,b) of three such
 operands (the paper's operation set has no SWAP; the QFT figure uses it).
 
+A custom operation (Section 5.2.2: data registered with the operation data
+provider, applied to a range of qubits) is the 4-tuple
+(name, (a, a+1, ..., a+m-1), None, M) with M of size 2^m whose index bit k is
+qubit a+k; its range is its span, so M itself is its operand.  ("U2", (q,),
+None, M) is the one-qubit case.
+
 Step formation (Section 5.2.1 says only that steps are created dynamically as
 gates are added): a gate joins the most recent step if its span is disjoint
 from the span of every gate already in that step, otherwise it opens a new
@@ -67,7 +73,15 @@ def _span_embed(by_qubit: dict, lo: int, hi: int) -> np.ndarray:
 
 def span_operand(g: GateT) -> np.ndarray:
     """Stage 3: the operand a gate contributes to its step, of size 2^m for a span of m qubits."""
-    name, qubits, theta = g
+    name, qubits, theta = g[0], g[1], g[2]
+    if len(g) == 4:
+        lo, hi = span(g)
+        if list(qubits) != list(range(lo, hi + 1)):
+            raise ValueError("a custom operation acts on a contiguous ascending range of qubits")
+        M = np.asarray(g[3], dtype=np.complex128)
+        if M.shape != (1 << len(qubits),) * 2:
+            raise ValueError("custom matrix size does not match its qubit range")
+        return M
     if len(qubits) == 1:
         return G.one_qubit(name, theta)
     lo, hi = span(g)

@@ -26,23 +26,35 @@ QSIM_FP32_4M, QSIM_FP32_3M, QSIM_SPLIT_BF16, QSIM_SPLIT_FP16 = 0, 1, 2, 3
 PRECISIONS = {"fp32_4m": 0, "fp32_3m": 1, "split_bf16": 2, "split_fp16": 3}
 QSIM_LAYOUT_ROW, QSIM_LAYOUT_COL = 0, 1
 
-KIND = {"H": 0, "X": 1, "Y": 2, "Z": 3, "S": 4, "T": 5, "R": 6, "RX": 7, "RY": 8, "RZ": 9, "U2": 10, "SWAP": 11}
+KIND = {"H": 0, "X": 1, "Y": 2, "Z": 3, "S": 4, "T": 5, "R": 6, "RX": 7, "RY": 8, "RZ": 9, "U2": 10, "SWAP": 11,
+        "CUSTOM": 12}
+QSIM_CUSTOM_MAX_QUBITS = 6
 # controlled names -> kind of the gate applied to the target
 CONTROLLED = {"CNOT": "X", "CY": "Y", "CZ": "Z", "CR": "R"}
 
 
 class qsim_gate(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("target", ctypes.c_int32), ("control", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("theta", ctypes.c_double), ("u", ctypes.c_double * 8)]
+                ("op_id", ctypes.c_int32), ("theta", ctypes.c_double), ("u", ctypes.c_double * 8)]
 
 
 assert ctypes.sizeof(qsim_gate) == 88
 
-PROFILE_KINDS = ("expand", "product", "apply", "drift")
+PROFILE_KINDS = ("expand", "product", "apply", "drift", "fsv")
 
 
 class qsim_kernel_stats(ctypes.Structure):
-    _fields_ = [("count", ctypes.c_int64 * 4), ("total_ms", ctypes.c_double * 4)]
+    _fields_ = [("count", ctypes.c_int64 * 5), ("total_ms", ctypes.c_double * 5)]
+
+
+QSIM_FSV_MAX_QUBITS = 34
+QSIM_FSV_MAX_HIGH = 6
+
+
+class qsim_fsv_pass_info(ctypes.Structure):
+    _fields_ = [("low_qubits", ctypes.c_int32), ("n_high", ctypes.c_int32),
+                ("high", ctypes.c_int32 * QSIM_FSV_MAX_HIGH), ("first_op", ctypes.c_int32),
+                ("n_ops", ctypes.c_int32)]
 
 
 class qsim_circuit_desc(ctypes.Structure):
@@ -128,6 +140,16 @@ def lib() -> ctypes.CDLL:
         "qsim_autotune": (i32, [vp, i32, i32, i32, ctypes.POINTER(dbl)]),
         "qsim_unitarity_drift_probe": (i32, [vp, i32, vp, ctypes.POINTER(dbl), vp]),
         "qsim_sample": (i32, [vp, i32, vp, vp, i32, vp, vp]),
+        "qsim_register_unitary": (i32, [ctypes.c_char_p, i32, ctypes.POINTER(dbl), ctypes.POINTER(i32)]),
+        "qsim_find_unitary": (i32, [ctypes.c_char_p, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "qsim_fsv_schedule": (i32, [i32, vp, i32, ctypes.POINTER(qsim_fsv_pass_info), i32,
+                                    ctypes.POINTER(i32)]),
+        "qsim_fsv_plan_create": (i32, [vp, i32, vp, i32, ctypes.POINTER(vp)]),
+        "qsim_fsv_plan_info": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "qsim_fsv_plan_destroy": (i32, [vp]),
+        "qsim_fsv_run": (i32, [vp, vp, vp, vp]),
+        "qsim_fsv_init_basis": (i32, [vp, i32, ctypes.c_int64, vp, vp]),
+        "qsim_fsv_norm2": (i32, [vp, i32, vp, ctypes.POINTER(dbl), vp]),
         "qsim_serve_start": (i32, [vp, ctypes.POINTER(qsim_serve_config)]),
         "qsim_serve_stop": (i32, [vp]),
         "qsim_submit": (i32, [vp, ctypes.POINTER(qsim_request), ctypes.POINTER(ctypes.c_uint64)]),
@@ -167,10 +189,17 @@ def _stream(stream, device: int = 0):
 
 
 def gate_record(g) -> qsim_gate:
-    """Marshal one gate (workloads.Gate or (name, qubits, theta[, u])) into a qsim_gate."""
+    """Marshal one gate (workloads.Gate, (name, qubits, theta[, u]) or ("CUSTOM", range, None, op_id))
+    into a qsim_gate."""
     name, qubits, theta = (g.name, g.qubits, g.theta) if hasattr(g, "name") else (g[0], g[1], g[2])
     rec = qsim_gate()
-    rec.reserved = 0
+    rec.op_id = 0
+    if name == "CUSTOM":
+        rec.kind = KIND["CUSTOM"]
+        rec.target = int(qubits[0])
+        rec.control = -1
+        rec.op_id = int(g[3])
+        return rec
     rec.theta = 0.0 if theta is None else float(theta)
     if name in CONTROLLED:
         rec.kind = KIND[CONTROLLED[name]]
@@ -459,3 +488,85 @@ def qsim_serve_get_stats(ctx) -> dict:
 def qsim_sample(ctx, n_qubits: int, d_prob, d_uniform, shots: int, d_out, stream=None) -> None:
     st = _stream(stream, _dev(ctx)) if _h(ctx) else None
     _check(lib().qsim_sample(_h(ctx), n_qubits, _ptr(d_prob), _ptr(d_uniform), shots, _ptr(d_out), st), "qsim_sample")
+
+
+# --- full-state-vector simulation ---
+
+def qsim_fsv_schedule(n_qubits: int, gates) -> list:
+    """Pass schedule of a gate list (host only): [(low_qubits, high_qubits, first_op, n_ops), ...]."""
+    arr, count = gate_array(gates)
+    n = ctypes.c_int32(0)
+    _check(lib().qsim_fsv_schedule(n_qubits, arr, count, None, 0, ctypes.byref(n)), "qsim_fsv_schedule")
+    buf = (qsim_fsv_pass_info * max(n.value, 1))()
+    _check(lib().qsim_fsv_schedule(n_qubits, arr, count, buf, n.value, ctypes.byref(n)), "qsim_fsv_schedule")
+    return [(p.low_qubits, tuple(p.high[:p.n_high]), p.first_op, p.n_ops) for p in buf[:n.value]]
+
+
+class FsvPlan:
+    """Owns a qsim_fsv_plan (qsim_fsv_plan_create / qsim_fsv_plan_destroy)."""
+
+    def __init__(self, ctx, n_qubits: int, gates):
+        arr, count = gate_array(gates)
+        h = ctypes.c_void_p()
+        _check(lib().qsim_fsv_plan_create(_h(ctx), n_qubits, arr, count, ctypes.byref(h)), "qsim_fsv_plan_create")
+        self.handle = h.value
+        self.ctx = ctx
+
+    def info(self) -> dict:
+        n, p, o = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().qsim_fsv_plan_info(self.handle, ctypes.byref(n), ctypes.byref(p), ctypes.byref(o)),
+               "qsim_fsv_plan_info")
+        return {"n_qubits": n.value, "passes": p.value, "ops": o.value}
+
+    def run(self, d_psi, stream=None) -> None:
+        st = _stream(stream, _dev(self.ctx)) if _h(self.ctx) else None
+        _check(lib().qsim_fsv_run(_h(self.ctx), self.handle, _ptr(d_psi), st), "qsim_fsv_run")
+
+    def close(self):
+        if self.handle:
+            _check(lib().qsim_fsv_plan_destroy(self.handle), "qsim_fsv_plan_destroy")
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def qsim_fsv_init_basis(ctx, n_qubits: int, basis: int, d_psi, stream=None) -> None:
+    st = _stream(stream, _dev(ctx)) if _h(ctx) else None
+    _check(lib().qsim_fsv_init_basis(_h(ctx), n_qubits, basis, _ptr(d_psi), st), "qsim_fsv_init_basis")
+
+
+def qsim_fsv_norm2(ctx, n_qubits: int, d_psi, stream=None) -> float:
+    out = ctypes.c_double(float("nan"))
+    st = _stream(stream, _dev(ctx)) if _h(ctx) else None
+    _check(lib().qsim_fsv_norm2(_h(ctx), n_qubits, _ptr(d_psi), ctypes.byref(out), st), "qsim_fsv_norm2")
+    return out.value
+
+
+# --- operation data provider ---
+
+def qsim_register_unitary(name: str, matrix) -> int:
+    """Register a 2^m x 2^m unitary (index bit k = qubit a+k of the range it is applied to); returns its id."""
+    import numpy as np
+    M = np.asarray(matrix, dtype=np.complex128)
+    D = M.shape[0]
+    m = D.bit_length() - 1
+    if M.shape != (D, D) or (1 << m) != D:
+        raise ValueError("custom matrix must be 2^m x 2^m")
+    flat = np.empty(2 * D * D, dtype=np.float64)
+    flat[0::2] = M.real.ravel()
+    flat[1::2] = M.imag.ravel()
+    out = ctypes.c_int32(0)
+    _check(lib().qsim_register_unitary(name.encode(), m, flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       ctypes.byref(out)), "qsim_register_unitary")
+    return out.value
+
+
+def qsim_find_unitary(name: str):
+    """(id, qubit count) of a registered operation."""
+    i, m = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(lib().qsim_find_unitary(name.encode(), ctypes.byref(i), ctypes.byref(m)), "qsim_find_unitary")
+    return i.value, m.value

@@ -50,10 +50,19 @@ bool valid_prec(int p) { return p >= QSIM_FP32_4M && p <= QSIM_SPLIT_FP16; }
 static bool built_prec(int p) { return valid_prec(p); }
 
 static qsim_status check_gate(int n, const qsim_gate& g, int idx) {
-    if (g.kind < QSIM_H || g.kind > QSIM_SWAP) return fail(QSIM_E_INVALID, "gate %d: unknown kind %d", idx, g.kind);
-    if (g.reserved != 0) return fail(QSIM_E_INVALID, "gate %d: reserved field must be 0", idx);
+    if (g.kind < QSIM_H || g.kind > QSIM_CUSTOM) return fail(QSIM_E_INVALID, "gate %d: unknown kind %d", idx, g.kind);
+    if (g.kind != QSIM_CUSTOM && g.op_id != 0) return fail(QSIM_E_INVALID, "gate %d: op_id must be 0 unless CUSTOM", idx);
     if (g.target < 0 || g.target >= n)
         return fail(QSIM_E_INVALID, "gate %d: qubit %d outside 0..%d", idx, g.target, n - 1);
+    if (g.kind == QSIM_CUSTOM) {
+        const int m = custom_qubits(g.op_id);
+        if (m == 0) return fail(QSIM_E_INVALID, "gate %d: custom operation %d is not registered", idx, g.op_id);
+        if (g.control != -1) return fail(QSIM_E_INVALID, "gate %d: a custom operation takes no control", idx);
+        if (g.target + m > n)
+            return fail(QSIM_E_INVALID, "gate %d: custom range %d..%d outside 0..%d", idx, g.target, g.target + m - 1,
+                        n - 1);
+        return QSIM_OK;
+    }
     if (g.kind == QSIM_SWAP && g.control < 0)
         return fail(QSIM_E_INVALID, "gate %d: SWAP needs its second qubit in `control`", idx);
     if (g.control >= n || g.control < -1)
@@ -89,6 +98,10 @@ qsim_status check_gates(int n, const qsim_gate* gates, int n_gates) {
 static void span_of(const qsim_gate& g, int& lo, int& hi) {
     lo = g.target;
     hi = g.target;
+    if (g.kind == QSIM_CUSTOM) {
+        hi = g.target + custom_qubits(g.op_id) - 1;
+        return;
+    }
     if (g.control >= 0) {
         lo = g.control < lo ? g.control : lo;
         hi = g.control > hi ? g.control : hi;
@@ -102,7 +115,7 @@ static uint32_t span_mask(const qsim_gate& g) {
 }
 
 // 2x2 float64 matrix of a gate kind, rows = output bit, (re, im) pairs.
-static void gate_matrix(const qsim_gate& g, double m[8]) {
+void gate_matrix(const qsim_gate& g, double m[8]) {
     const double r2 = 0.70710678118654752440;
     for (int i = 0; i < 8; ++i) m[i] = 0.0;
     auto set = [&](int idx, double re, double im) {
@@ -151,6 +164,18 @@ qsim_status make_step(int n, const qsim_gate* gates, int count, DevStep& st) {
         if (sm & used_span) return fail(QSIM_E_INVALID, "step gate %d overlaps the span of an earlier gate of the step", i);
         used_span |= sm;
         DevGate& d = st.g[i];
+        if (g.kind == QSIM_CUSTOM) {
+            d.type = GATE_CUSTOM;
+            d.q0 = g.target;
+            d.q1 = custom_qubits(g.op_id);
+            int dev = 0;
+            hipError_t e = hipGetDevice(&dev);
+            if (e != hipSuccess) return device_fail("hipGetDevice", e);
+            qsim_status cs = custom_device(g.op_id, dev, &d.ext);
+            if (cs != QSIM_OK) return cs;
+            touched |= sm;
+            continue;
+        }
         if (g.kind == QSIM_SWAP) {
             d.type = GATE_SWAP;
             d.q0 = g.target;

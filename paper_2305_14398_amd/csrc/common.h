@@ -10,13 +10,15 @@ namespace qsim {
 
 // One gate of a step, as the expansion kernel reads it.  The 2x2 matrix is
 // float64, row-major (re, im) pairs, rows indexed by the output bit.
-enum : int32_t { GATE_ONE = 1, GATE_CTRL = 2, GATE_SWAP = 3 };
+enum : int32_t { GATE_ONE = 1, GATE_CTRL = 2, GATE_SWAP = 3, GATE_CUSTOM = 4 };
 
 struct DevGate {
-    int32_t type;  // GATE_ONE: q0 = qubit; GATE_CTRL: q0 = control, q1 = target; GATE_SWAP: q0, q1
+    int32_t type;  // GATE_ONE: q0 = qubit; GATE_CTRL: q0 = control, q1 = target; GATE_SWAP: q0, q1;
+                   // GATE_CUSTOM: qubits q0 .. q0+q1-1, matrix at ext
     int32_t q0;
     int32_t q1;
     int32_t pad;
+    const double* ext;  // GATE_CUSTOM: 2^q1 x 2^q1 row-major (re, im) float64 on the launch device
     double m[8];
 };
 

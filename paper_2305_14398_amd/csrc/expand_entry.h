@@ -9,9 +9,11 @@
 //   one-qubit gate G on q   : G[r_q][s_q]
 //   controlled-U (c -> t)   : [r_c == s_c] * (s_c == 0 ? [r_t == s_t] : U[r_t][s_t])   (Eq. 7)
 //   SWAP(a, b)              : [r_a == s_b] * [r_b == s_a]
+//   custom M on a..a+m-1    : M[r_{a..a+m-1}][s_{a..a+m-1}]   (a registered unitary, Section 5.2.2)
 // and the entry is the product of these factors.  Every entry is computed in
-// float64 and rounded once to the output format, so the kernel is a pure
-// streaming writer: 8 bytes of HBM traffic per entry and no reads.
+// float64 and rounded once to the output format, so the kernel is a streaming
+// writer: 8 bytes of HBM traffic per entry, and no reads beyond the (cached)
+// matrices of custom operations.
 #pragma once
 
 #include "common.h"
@@ -34,6 +36,15 @@ __device__ __forceinline__ void step_entry(const DevStep& st, uint32_t r, uint32
         const int q0 = st.g[g].q0, q1 = st.g[g].q1;
         int idx = 0;
         bool use = true;
+        if (type == GATE_CUSTOM) {
+            const uint32_t mask = (1u << q1) - 1u;
+            const uint32_t e = (((r >> q0) & mask) << q1) | ((s >> q0) & mask);
+            const double ar = st.g[g].ext[2 * e], ai = st.g[g].ext[2 * e + 1];
+            const double t = pr * ar - pi * ai;
+            pi = pr * ai + pi * ar;
+            pr = t;
+            continue;
+        }
         if (type == GATE_ONE) {
             idx = (((r >> q0) & 1u) << 1) | ((s >> q0) & 1u);
         } else if (type == GATE_CTRL) {

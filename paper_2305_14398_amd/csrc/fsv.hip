@@ -1,0 +1,635 @@
+// Full-state-vector simulation: the per-amplitude gate update of Appendix A
+// (Eq. 12), the backend the paper proposes to accelerate next (Section 7).
+// The state (planar complex64: re plane then im plane, N = 2^n floats each)
+// is updated in place; no 2^n x 2^n operator exists, so n reaches 34 qubits
+// (a 128 GiB state) instead of 16.
+//
+// Design.  Applying gates one launch at a time would stream the whole state
+// through HBM once per gate.  Instead the host groups consecutive gates into
+// passes; a pass names 12 "local" qubits (the low L qubits 0..L-1 plus up to
+// 12 - L others) and contains only gates whose non-diagonal target is local.
+// One launch per pass: workgroup w takes the 4096 amplitudes that share w's
+// values of the other n - 12 qubits, applies every gate of the pass to them
+// in registers and writes them back, so a pass costs 16 bytes of HBM traffic
+// per amplitude however many gates it holds.
+//
+// Inside a workgroup, 256 threads hold 16 amplitudes each.  Of the 12 local
+// index bits, 4 live in a thread's registers and 8 in its thread index; three
+// layouts put bits 0-3, 4-7 or 8-11 in registers.  A gate whose target bit is
+// in the register group updates 8 register pairs per thread with no exchange;
+// otherwise the workgroup first changes layout through LDS (32 KiB, XOR
+// swizzled so each wave's 64 accesses hit distinct banks in every layout).
+// Controls never need to be local: a control on a local bit is a per-register
+// predicate, one on any other qubit is the same for the whole workgroup.
+// Diagonal gates (Z, S, T, R, RZ, CZ, controlled phases) only scale
+// amplitudes, so they need no local target at all.  SWAP runs as three CNOTs,
+// which permute amplitudes exactly.  A custom operation on m qubits (Section
+// 5.2.2) needs its whole range local; it is applied through LDS: every
+// amplitude is written out, then each thread forms its 16 outputs as sums of
+// 2^m products with the operation's float32 matrix.
+//
+// Gate entries are the float64 matrices of the unitary path rounded once to
+// float32; amplitude arithmetic is float32 with fused multiply-adds.
+#include <algorithm>
+#include <vector>
+
+#include "host.h"
+
+namespace qsim {
+
+constexpr int kFsvLocal = 12;     // local qubits per workgroup: 4096 amplitudes
+constexpr int kFsvMinLow = 6;     // low qubits always local: 64 lanes x 4 B contiguous per plane
+constexpr int kFsvMaxHigh = kFsvLocal - kFsvMinLow;
+constexpr int kFsvNormBlocks = 1024;
+
+enum : int32_t { FSV_GENERAL = 0, FSV_DIAG = 1, FSV_DENSE = 2 };
+
+struct FsvGate {
+    int32_t kind;
+    int32_t tloc;   // local bit of the target (dense: of the range's lowest qubit), or -1 (diagonal only)
+    int32_t tglob;  // the target qubit when it is not local
+    int32_t cloc;   // local bit of the control, or -1
+    int32_t cglob;  // a non-local control qubit, or -1
+    int32_t width;  // dense: qubits in the range
+    int32_t moff;   // dense: offset of its 2^w x 2^w (re, im) float32 matrix in the plan's pool
+    int32_t pad;
+    float m[8];  // row-major 2x2 (re, im); a diagonal gate uses m[0..1] and m[6..7]
+};
+
+struct FsvPass {
+    int32_t L;   // local bits 0..L-1 are qubits 0..L-1
+    int32_t nh;  // local bits L..L+nh-1 are qubits high[0..nh-1], ascending
+    int32_t high[kFsvMaxHigh];
+    int32_t g0, g1;  // the pass's gates in the plan's table
+};
+
+namespace {
+
+// Bank-spreading map of a local index to its LDS slot (a bijection on 0..4095
+// that only changes bits 0-5).
+__device__ __forceinline__ int fsv_swz(int j) { return j ^ ((j >> 6) & 15) ^ (((j >> 8) & 3) << 4); }
+
+// The local index bits a thread contributes in layout k (its 8 index bits
+// around the register nibble 4k..4k+3).
+__device__ __forceinline__ int fsv_thread_bits(int t, int k) {
+    const int s = 4 * k;
+    return (t & ((1 << s) - 1)) | ((t >> s) << (s + 4));
+}
+
+__device__ __forceinline__ int fsv_pos(const FsvPass& p, int b) {
+    int q = b;
+#pragma unroll
+    for (int h = 0; h < kFsvMaxHigh; ++h)
+        if (h < p.nh && b == p.L + h) q = p.high[h];
+    return q;
+}
+
+template <int RB>
+__device__ __forceinline__ void fsv_general(float (&ar)[16], float (&ai)[16], const FsvGate& g, int jt, int sh) {
+    const float m0r = g.m[0], m0i = g.m[1], m1r = g.m[2], m1i = g.m[3];
+    const float m2r = g.m[4], m2i = g.m[5], m3r = g.m[6], m3i = g.m[7];
+#pragma unroll
+    for (int r0 = 0; r0 < 16; ++r0) {
+        if ((r0 >> RB) & 1) continue;
+        const int r1 = r0 | (1 << RB);
+        const bool on = g.cloc < 0 || (((jt | (r0 << sh)) >> g.cloc) & 1);
+        const float x0r = ar[r0], x0i = ai[r0], x1r = ar[r1], x1i = ai[r1];
+        const float y0r = fmaf(m0r, x0r, fmaf(-m0i, x0i, fmaf(m1r, x1r, -m1i * x1i)));
+        const float y0i = fmaf(m0r, x0i, fmaf(m0i, x0r, fmaf(m1r, x1i, m1i * x1r)));
+        const float y1r = fmaf(m2r, x0r, fmaf(-m2i, x0i, fmaf(m3r, x1r, -m3i * x1i)));
+        const float y1i = fmaf(m2r, x0i, fmaf(m2i, x0r, fmaf(m3r, x1i, m3i * x1r)));
+        ar[r0] = on ? y0r : x0r;
+        ai[r0] = on ? y0i : x0i;
+        ar[r1] = on ? y1r : x1r;
+        ai[r1] = on ? y1i : x1i;
+    }
+}
+
+__device__ __forceinline__ void fsv_diag(float (&ar)[16], float (&ai)[16], const FsvGate& g, int jt, int sh,
+                                         uint64_t base) {
+    const int tb_uniform = g.tloc < 0 ? (int)((base >> g.tglob) & 1) : 0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int j = jt | (r << sh);
+        const bool on = g.cloc < 0 || ((j >> g.cloc) & 1);
+        const int bit = g.tloc < 0 ? tb_uniform : ((j >> g.tloc) & 1);
+        const float dr = bit ? g.m[6] : g.m[0];
+        const float di = bit ? g.m[7] : g.m[1];
+        const float xr = ar[r], xi = ai[r];
+        const float yr = fmaf(dr, xr, -di * xi);
+        const float yi = fmaf(dr, xi, di * xr);
+        ar[r] = on ? yr : xr;
+        ai[r] = on ? yi : xi;
+    }
+}
+
+// A dense operation on local bits lb .. lb+w-1: out[j] = sum_s M[row(j)][s] in[j with
+// those bits = s], through LDS; the register layout is unchanged.
+__device__ __forceinline__ void fsv_dense(float (&ar)[16], float (&ai)[16], int t, int cur, const FsvGate& g,
+                                          const float* __restrict__ pool, float* s_re, float* s_im) {
+    __syncthreads();
+    const int jt = fsv_thread_bits(t, cur), sh = 4 * cur;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int a = fsv_swz(jt | (r << sh));
+        s_re[a] = ar[r];
+        s_im[a] = ai[r];
+    }
+    __syncthreads();
+    const int lb = g.tloc, W = 1 << g.width;
+    const int field = (W - 1) << lb;
+    const float* M = pool + g.moff;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int j = jt | (r << sh);
+        const int row = (j >> lb) & (W - 1);
+        const int rest = j & ~field;
+        const float* mr = M + 2 * row * W;
+        float yr = 0.f, yi = 0.f;
+        for (int c = 0; c < W; ++c) {
+            const int a = fsv_swz(rest | (c << lb));
+            const float xr = s_re[a], xi = s_im[a];
+            const float er = mr[2 * c], ei = mr[2 * c + 1];
+            yr = fmaf(er, xr, fmaf(-ei, xi, yr));
+            yi = fmaf(er, xi, fmaf(ei, xr, yi));
+        }
+        ar[r] = yr;
+        ai[r] = yi;
+    }
+}
+
+// Layout change cur -> k through LDS.
+__device__ __forceinline__ void fsv_relayout(float (&ar)[16], float (&ai)[16], int t, int cur, int k, float* s_re,
+                                             float* s_im) {
+    __syncthreads();  // earlier readers of the buffer are done
+    const int jt = fsv_thread_bits(t, cur), sh = 4 * cur;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int a = fsv_swz(jt | (r << sh));
+        s_re[a] = ar[r];
+        s_im[a] = ai[r];
+    }
+    __syncthreads();
+    const int jn = fsv_thread_bits(t, k), shn = 4 * k;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int a = fsv_swz(jn | (r << shn));
+        ar[r] = s_re[a];
+        ai[r] = s_im[a];
+    }
+}
+
+__global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const FsvGate* __restrict__ gates,
+                                                      const float* __restrict__ pool, float* __restrict__ re,
+                                                      float* __restrict__ im) {
+    __shared__ float s_re[1 << kFsvLocal], s_im[1 << kFsvLocal];
+    const int t = threadIdx.x;
+
+    // Global index of local index 0: the workgroup number with zero bits
+    // inserted at the local positions above the low L qubits.
+    uint64_t base = 0;
+    if (n > kFsvLocal) {
+        base = (uint64_t)blockIdx.x << p.L;
+#pragma unroll
+        for (int h = 0; h < kFsvMaxHigh; ++h) {
+            if (h < p.nh) {
+                const uint64_t low = ((uint64_t)1 << p.high[h]) - 1;
+                base = ((base & ~low) << 1) | (base & low);
+            }
+        }
+    }
+    // Load/store layout 2: local bits 0-7 = thread index, 8-11 = register.
+    uint64_t gt = 0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+        if ((t >> b) & 1) gt |= (uint64_t)1 << fsv_pos(p, b);
+    uint64_t gh[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) gh[b] = (uint64_t)1 << fsv_pos(p, 8 + b);
+    const bool full = n >= kFsvLocal;
+    const int nloc = full ? (1 << kFsvLocal) : (1 << n);
+
+    float ar[16], ai[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int j = t | (r << 8);
+        uint64_t g = base | gt;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            if ((r >> b) & 1) g |= gh[b];
+        if (j < nloc) {
+            ar[r] = re[g];
+            ai[r] = im[g];
+        } else {
+            ar[r] = 0.f;
+            ai[r] = 0.f;
+        }
+    }
+
+    int cur = 2;
+    for (int gi = p.g0; gi < p.g1; ++gi) {
+        const FsvGate g = gates[gi];
+        if (g.cglob >= 0 && !((base >> g.cglob) & 1)) continue;  // non-local control is 0 here
+        if (g.kind == FSV_GENERAL) {
+            const int k = g.tloc >> 2;
+            if (k != cur) {
+                fsv_relayout(ar, ai, t, cur, k, s_re, s_im);
+                cur = k;
+            }
+            const int jt = fsv_thread_bits(t, cur), sh = 4 * cur;
+            switch (g.tloc & 3) {
+                case 0: fsv_general<0>(ar, ai, g, jt, sh); break;
+                case 1: fsv_general<1>(ar, ai, g, jt, sh); break;
+                case 2: fsv_general<2>(ar, ai, g, jt, sh); break;
+                default: fsv_general<3>(ar, ai, g, jt, sh); break;
+            }
+        } else if (g.kind == FSV_DIAG) {
+            fsv_diag(ar, ai, g, fsv_thread_bits(t, cur), 4 * cur, base);
+        } else {
+            fsv_dense(ar, ai, t, cur, g, pool, s_re, s_im);
+        }
+    }
+    if (cur != 2) fsv_relayout(ar, ai, t, cur, 2, s_re, s_im);
+
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int j = t | (r << 8);
+        uint64_t g = base | gt;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            if ((r >> b) & 1) g |= gh[b];
+        if (j < nloc) {
+            re[g] = ar[r];
+            im[g] = ai[r];
+        }
+    }
+}
+
+// |basis> in planar complex64, written as float4 (2N floats, N >= 2).
+__global__ __launch_bounds__(256) void fsv_basis_kernel(uint64_t n4, uint64_t basis, float4* __restrict__ psi) {
+    for (uint64_t v = (uint64_t)blockIdx.x * 256 + threadIdx.x; v < n4; v += (uint64_t)gridDim.x * 256) {
+        float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (v == (basis >> 2)) {
+            const int c = (int)(basis & 3);
+            x.x = c == 0 ? 1.f : 0.f;
+            x.y = c == 1 ? 1.f : 0.f;
+            x.z = c == 2 ? 1.f : 0.f;
+            x.w = c == 3 ? 1.f : 0.f;
+        }
+        psi[v] = x;
+    }
+}
+
+// sum |psi_i|^2 in float64: fixed-order per-block partials, then one block.
+__global__ __launch_bounds__(256) void fsv_norm_partial(uint64_t N, const float* __restrict__ re,
+                                                       const float* __restrict__ im, double* __restrict__ part) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (uint64_t)gridDim.x * 256) {
+        const double a = re[i], b = im[i];
+        s += a * a + b * b;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void fsv_norm_final(int parts, const double* __restrict__ part,
+                                                     double* __restrict__ out) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < parts; i += 256) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// --- host planning -------------------------------------------------------------------------
+
+struct LoweredGate {
+    int kind;
+    int tq, cq;     // target (dense: lowest qubit of the range), control (-1: none)
+    int width = 0;  // dense: qubits in the range
+    int32_t op = 0; // dense: registered operation
+    float m[8];
+};
+
+void lower(const qsim_gate* gates, int n_gates, std::vector<LoweredGate>& out) {
+    out.clear();
+    for (int i = 0; i < n_gates; ++i) {
+        const qsim_gate& g = gates[i];
+        if (g.kind == QSIM_CUSTOM) {
+            LoweredGate l{};
+            l.kind = FSV_DENSE;
+            l.tq = g.target;
+            l.cq = -1;
+            l.width = custom_qubits(g.op_id);
+            l.op = g.op_id;
+            out.push_back(l);
+            continue;
+        }
+        if (g.kind == QSIM_SWAP) {
+            const float x[8] = {0, 0, 1, 0, 1, 0, 0, 0};
+            const int a = g.target, b = g.control;
+            for (int rep = 0; rep < 3; ++rep) {
+                LoweredGate l{};
+                l.kind = FSV_GENERAL;
+                l.tq = rep == 1 ? a : b;
+                l.cq = rep == 1 ? b : a;
+                std::copy(x, x + 8, l.m);
+                out.push_back(l);
+            }
+            continue;
+        }
+        double m[8];
+        gate_matrix(g, m);
+        LoweredGate l{};
+        l.kind = (m[2] == 0 && m[3] == 0 && m[4] == 0 && m[5] == 0) ? FSV_DIAG : FSV_GENERAL;
+        l.tq = g.target;
+        l.cq = g.control;
+        for (int k = 0; k < 8; ++k) l.m[k] = (float)m[k];
+        out.push_back(l);
+    }
+}
+
+int popcount64(uint64_t x) { return __builtin_popcountll(x); }
+
+// Largest L in [kFsvMinLow, kFsvLocal] that leaves room for every target at or
+// above L among the 12 - L other local slots; -1 if none.
+int fit_low(uint64_t targets) {
+    for (int L = kFsvLocal; L >= kFsvMinLow; --L)
+        if (L + popcount64(targets >> L) <= kFsvLocal) return L;
+    return -1;
+}
+
+// Qubits a gate needs local: the target of a non-diagonal 2x2, the whole range of a dense operation.
+uint64_t local_need(const LoweredGate& l) {
+    if (l.kind == FSV_GENERAL) return (uint64_t)1 << l.tq;
+    if (l.kind == FSV_DENSE) return (((uint64_t)1 << l.width) - 1) << l.tq;
+    return 0;
+}
+
+// Pool offsets (floats) of each dense operation's float32 matrix, appended to `pool` once per id.
+int pool_offset(int32_t op, int width, std::vector<float>& pool, std::vector<std::pair<int32_t, int>>& seen) {
+    for (auto& kv : seen)
+        if (kv.first == op) return kv.second;
+    const int off = (int)pool.size();
+    const double* h = custom_host(op);
+    const int count = 2 << (2 * width);
+    for (int i = 0; i < count; ++i) pool.push_back((float)h[i]);
+    seen.emplace_back(op, off);
+    return off;
+}
+
+void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass>& passes,
+                  std::vector<FsvGate>& table, std::vector<float>& pool) {
+    passes.clear();
+    table.clear();
+    pool.clear();
+    std::vector<std::pair<int32_t, int>> seen;
+    size_t i = 0;
+    while (i < gs.size()) {
+        FsvPass p{};
+        uint64_t T = 0;
+        size_t j = i;
+        if (n <= kFsvLocal) {
+            p.L = n;
+            p.nh = 0;
+            j = gs.size();
+        } else {
+            int L = kFsvLocal;
+            for (; j < gs.size(); ++j) {
+                const uint64_t T2 = T | local_need(gs[j]);
+                const int L2 = fit_low(T2);
+                if (L2 < 0) break;
+                T = T2;
+                L = L2;
+            }
+            p.L = L;
+            p.nh = kFsvLocal - L;
+            std::vector<int> hs;
+            for (int q = L; q < n; ++q)
+                if ((T >> q) & 1) hs.push_back(q);
+            for (int q = L; q < n && (int)hs.size() < p.nh; ++q)
+                if (!((T >> q) & 1)) hs.push_back(q);
+            std::sort(hs.begin(), hs.end());
+            for (int h = 0; h < p.nh; ++h) p.high[h] = hs[h];
+        }
+        auto local_bit = [&](int q) {
+            if (q < 0) return -1;
+            if (q < p.L) return q;
+            for (int h = 0; h < p.nh; ++h)
+                if (p.high[h] == q) return p.L + h;
+            return -1;
+        };
+        p.g0 = (int)table.size();
+        for (size_t k = i; k < j; ++k) {
+            const LoweredGate& l = gs[k];
+            FsvGate d{};
+            d.kind = l.kind;
+            d.tloc = local_bit(l.tq);
+            d.tglob = d.tloc < 0 ? l.tq : -1;
+            d.cloc = local_bit(l.cq);
+            d.cglob = (l.cq >= 0 && d.cloc < 0) ? l.cq : -1;
+            if (l.kind == FSV_DENSE) {
+                d.width = l.width;
+                d.moff = pool_offset(l.op, l.width, pool, seen);
+            }
+            std::copy(l.m, l.m + 8, d.m);
+            table.push_back(d);
+        }
+        p.g1 = (int)table.size();
+        passes.push_back(p);
+        i = j;
+    }
+}
+
+}  // namespace
+}  // namespace qsim
+
+struct qsim_fsv_plan {
+    int n = 0;
+    int device = 0;
+    int n_ops = 0;
+    std::vector<qsim::FsvPass> passes;
+    qsim::FsvGate* d_gates = nullptr;
+    float* d_pool = nullptr;  // float32 matrices of the plan's custom operations
+};
+
+using namespace qsim;
+
+namespace {
+
+qsim_status fsv_check(int n_qubits, const qsim_gate* gates, int n_gates) {
+    if (n_qubits < 1 || n_qubits > QSIM_FSV_MAX_QUBITS)
+        return fail(QSIM_E_RANGE, "n_qubits %d outside 1..%d", n_qubits, QSIM_FSV_MAX_QUBITS);
+    return check_gates(n_qubits, gates, n_gates);
+}
+
+}  // namespace
+
+extern "C" {
+
+qsim_status qsim_fsv_schedule(int n_qubits, const qsim_gate* gates, int n_gates, qsim_fsv_pass_info* passes,
+                              int capacity, int* n_passes) {
+    qsim_status s = fsv_check(n_qubits, gates, n_gates);
+    if (s != QSIM_OK) return s;
+    if (n_passes == nullptr) return fail(QSIM_E_INVALID, "n_passes is NULL");
+    if (capacity < 0 || (capacity > 0 && passes == nullptr)) return fail(QSIM_E_INVALID, "bad pass buffer");
+    std::vector<LoweredGate> gs;
+    lower(gates, n_gates, gs);
+    std::vector<FsvPass> ps;
+    std::vector<FsvGate> table;
+    std::vector<float> pool;
+    fsv_schedule(n_qubits, gs, ps, table, pool);
+    *n_passes = (int)ps.size();
+    if ((int)ps.size() > capacity && capacity > 0)
+        return fail(QSIM_E_RANGE, "%d passes do not fit the buffer of %d", (int)ps.size(), capacity);
+    for (int i = 0; i < (int)ps.size() && i < capacity; ++i) {
+        qsim_fsv_pass_info& o = passes[i];
+        o.low_qubits = ps[i].L;
+        o.n_high = ps[i].nh;
+        for (int h = 0; h < QSIM_FSV_MAX_HIGH; ++h) o.high[h] = h < ps[i].nh ? ps[i].high[h] : -1;
+        o.first_op = ps[i].g0;
+        o.n_ops = ps[i].g1 - ps[i].g0;
+    }
+    return ok();
+}
+
+qsim_status qsim_fsv_plan_create(qsim_ctx* ctx, int n_qubits, const qsim_gate* gates, int n_gates,
+                                 qsim_fsv_plan** out) {
+    if (out == nullptr) return fail(QSIM_E_INVALID, "out is NULL");
+    *out = nullptr;
+    qsim_status s = fsv_check(n_qubits, gates, n_gates);
+    if (s != QSIM_OK) return s;
+    s = check_ctx(ctx);
+    if (s != QSIM_OK) return s;
+    auto* plan = new qsim_fsv_plan();
+    plan->n = n_qubits;
+    plan->device = ctx->device;
+    std::vector<LoweredGate> gs;
+    lower(gates, n_gates, gs);
+    std::vector<FsvGate> table;
+    std::vector<float> pool;
+    fsv_schedule(n_qubits, gs, plan->passes, table, pool);
+    plan->n_ops = (int)table.size();
+    if (!table.empty()) {
+        DeviceGuard g(ctx->device);
+        hipError_t e = g.err;
+        if (e == hipSuccess) e = hipMalloc(&plan->d_gates, table.size() * sizeof(FsvGate));
+        if (e == hipSuccess)
+            e = hipMemcpy(plan->d_gates, table.data(), table.size() * sizeof(FsvGate), hipMemcpyHostToDevice);
+        if (e == hipSuccess && !pool.empty()) e = hipMalloc(&plan->d_pool, pool.size() * sizeof(float));
+        if (e == hipSuccess && !pool.empty())
+            e = hipMemcpy(plan->d_pool, pool.data(), pool.size() * sizeof(float), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            if (plan->d_gates) (void)hipFree(plan->d_gates);
+            if (plan->d_pool) (void)hipFree(plan->d_pool);
+            delete plan;
+            return e == hipErrorOutOfMemory ? fail(QSIM_E_OOM, "gate table: out of device memory")
+                                            : device_fail("gate table upload", e);
+        }
+    }
+    *out = plan;
+    return ok();
+}
+
+qsim_status qsim_fsv_plan_info(const qsim_fsv_plan* plan, int* n_qubits, int* n_passes, int* n_ops) {
+    if (plan == nullptr) return fail(QSIM_E_INVALID, "plan is NULL");
+    if (n_qubits) *n_qubits = plan->n;
+    if (n_passes) *n_passes = (int)plan->passes.size();
+    if (n_ops) *n_ops = plan->n_ops;
+    return ok();
+}
+
+qsim_status qsim_fsv_plan_destroy(qsim_fsv_plan* plan) {
+    if (plan == nullptr) return ok();
+    if (plan->d_gates || plan->d_pool) {
+        DeviceGuard g(plan->device);
+        if (plan->d_gates) (void)hipFree(plan->d_gates);
+        if (plan->d_pool) (void)hipFree(plan->d_pool);
+    }
+    delete plan;
+    return ok();
+}
+
+qsim_status qsim_fsv_run(qsim_ctx* ctx, const qsim_fsv_plan* plan, void* d_psi, void* stream) {
+    if (plan == nullptr) return fail(QSIM_E_INVALID, "plan is NULL");
+    if (d_psi == nullptr || !aligned(d_psi)) return fail(QSIM_E_INVALID, "d_psi is NULL or not 256-byte aligned");
+    qsim_status s = check_ctx(ctx);
+    if (s != QSIM_OK) return s;
+    if (ctx->device != plan->device) return fail(QSIM_E_INVALID, "plan was made for device %d", plan->device);
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return device_fail("hipSetDevice", g.err);
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const int n = plan->n;
+    const uint64_t N = (uint64_t)1 << n;
+    float* re = static_cast<float*>(d_psi);
+    float* im = re + N;
+    const unsigned blocks = n > kFsvLocal ? 1u << (n - kFsvLocal) : 1u;
+    for (const FsvPass& p : plan->passes) {
+        hipError_t e = timed(ctx->prof, QSIM_PROFILE_FSV, hs, [&] {
+            hipLaunchKernelGGL(fsv_pass_kernel, dim3(blocks), dim3(256), 0, hs, n, p, plan->d_gates, plan->d_pool, re,
+                               im);
+            return hipGetLastError();
+        });
+        if (e != hipSuccess) return device_fail("full-state pass launch", e);
+    }
+    return ok();
+}
+
+qsim_status qsim_fsv_init_basis(qsim_ctx* ctx, int n_qubits, int64_t basis, void* d_psi, void* stream) {
+    if (n_qubits < 1 || n_qubits > QSIM_FSV_MAX_QUBITS)
+        return fail(QSIM_E_RANGE, "n_qubits %d outside 1..%d", n_qubits, QSIM_FSV_MAX_QUBITS);
+    if (basis < 0 || basis >= ((int64_t)1 << n_qubits))
+        return fail(QSIM_E_RANGE, "basis index %lld outside 0..2^%d-1", (long long)basis, n_qubits);
+    if (d_psi == nullptr || !aligned(d_psi)) return fail(QSIM_E_INVALID, "d_psi is NULL or not 256-byte aligned");
+    qsim_status s = check_ctx(ctx);
+    if (s != QSIM_OK) return s;
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return device_fail("hipSetDevice", g.err);
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const uint64_t n4 = ((uint64_t)2 << n_qubits) / 4;
+    const uint64_t want = (n4 + 255) / 256;
+    const unsigned blocks = (unsigned)std::min<uint64_t>(want, 65536);
+    hipLaunchKernelGGL(fsv_basis_kernel, dim3(blocks), dim3(256), 0, hs, n4, (uint64_t)basis,
+                       static_cast<float4*>(d_psi));
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? ok() : device_fail("basis-state launch", e);
+}
+
+qsim_status qsim_fsv_norm2(qsim_ctx* ctx, int n_qubits, const void* d_psi, double* h_norm2, void* stream) {
+    if (n_qubits < 1 || n_qubits > QSIM_FSV_MAX_QUBITS)
+        return fail(QSIM_E_RANGE, "n_qubits %d outside 1..%d", n_qubits, QSIM_FSV_MAX_QUBITS);
+    if (d_psi == nullptr || !aligned(d_psi)) return fail(QSIM_E_INVALID, "d_psi is NULL or not 256-byte aligned");
+    if (h_norm2 == nullptr) return fail(QSIM_E_INVALID, "h_norm2 is NULL");
+    qsim_status s = check_ctx(ctx);
+    if (s != QSIM_OK) return s;
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return device_fail("hipSetDevice", g.err);
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const uint64_t N = (uint64_t)1 << n_qubits;
+    const float* re = static_cast<const float*>(d_psi);
+    const int parts = (int)std::min<uint64_t>(kFsvNormBlocks, (N + 255) / 256);
+    double* part = ctx->d_scratch + 8;
+    double* res = ctx->d_scratch + 6;
+    hipLaunchKernelGGL(fsv_norm_partial, dim3(parts), dim3(256), 0, hs, N, re, re + N, part);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(fsv_norm_final, dim3(1), dim3(256), 0, hs, parts, part, res);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(h_norm2, res, sizeof(double), hipMemcpyDeviceToHost, hs);
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    return e == hipSuccess ? ok() : device_fail("norm", e);
+}
+
+}  // extern "C"

@@ -22,6 +22,13 @@ bool valid_n(int n);
 bool valid_prec(int p);
 qsim_status check_gates(int n, const qsim_gate* gates, int n_gates);
 qsim_status check_offsets(const int32_t* off, int n_steps, int n_gates);
+// Operation data provider (registry.hip): qubit count of a registered custom
+// operation (0 if unknown), its host matrix, and its float64 copy on device `dev`.
+int custom_qubits(int32_t id);
+const double* custom_host(int32_t id);
+qsim_status custom_device(int32_t id, int dev, const double** out);
+// 2x2 float64 matrix of a gate (row-major (re, im) pairs, rows = output bit); SWAP has none.
+void gate_matrix(const qsim_gate& g, double m[8]);
 // Descriptor of one step (gates validated and pairwise span-disjoint).
 qsim_status make_step(int n, const qsim_gate* gates, int count, DevStep& st);
 // Step formation rule (see qsim_pack_steps).

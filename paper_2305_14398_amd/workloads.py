@@ -29,6 +29,9 @@ import numpy as np
 ONE_QUBIT = ("H", "X", "Y", "Z", "S", "T", "R", "RX", "RY", "RZ")
 TWO_QUBIT = ("CNOT", "CY", "CZ", "CR", "SWAP")
 ANGLED = ("R", "RX", "RY", "RZ", "CR")
+# Largest register: the full-state-vector path (a 2^34 complex64 state); the
+# unitary path itself stops at 16.
+MAX_QUBITS = 34
 # Random-layer gate set, in the order used to index the uniform draw.
 RANDOM_1Q = ("H", "X", "Y", "Z", "S", "T", "RX", "RY", "RZ")
 
@@ -65,8 +68,8 @@ class Circuit:
     family: str = "custom"
 
     def __post_init__(self):
-        if not (1 <= self.n <= 16):
-            raise ValueError(f"qubit count {self.n} outside 1..16")
+        if not (1 <= self.n <= MAX_QUBITS):
+            raise ValueError(f"qubit count {self.n} outside 1..{MAX_QUBITS}")
         for g in self.gates:
             for q in g.qubits:
                 if not (0 <= q < self.n):
@@ -274,3 +277,27 @@ def random_columns(n: int, count: int, seed: int) -> np.ndarray:
         cols[0] = 0
     return np.sort(cols)
 
+
+def random_unitary(m: int, seed: int) -> np.ndarray:
+    """A seeded Haar-random 2^m x 2^m unitary (QR of a complex Gaussian matrix with the phases of R's
+    diagonal divided out): the data of a custom operation on m qubits."""
+    rng = np.random.default_rng(seed)
+    D = 1 << m
+    z = (rng.standard_normal((D, D)) + 1j * rng.standard_normal((D, D))) / np.sqrt(2.0)
+    q, r = np.linalg.qr(z)
+    d = np.diag(r)
+    return q * (d / np.abs(d))
+
+
+def with_custom_ops(gates, n: int, m_values, seed: int):
+    """Insert custom operations (name, range, None, matrix) on random ranges into a gate list at seeded
+    positions; returns the new list (oracle form, 4-tuples for the custom operations)."""
+    rng = np.random.default_rng(seed)
+    out = list(gates)
+    for i, m in enumerate(m_values):
+        if m > n:
+            continue
+        a = int(rng.integers(0, n - m + 1))
+        pos = int(rng.integers(0, len(out) + 1))
+        out.insert(pos, (f"custom{m}_{seed}_{i}", tuple(range(a, a + m)), None, random_unitary(m, seed * 131 + i)))
+    return out

@@ -1,0 +1,248 @@
+"""Full-state-vector simulation (Appendix A, Eq. 12) on the GPU against the oracle's route B.
+
+Tolerance.  Each operation applies a 2x2 complex matrix rounded to float32
+(relative error u = 2^-24 per entry) in float32 fused multiply-adds; for a
+unitary matrix that perturbs the state by at most about 7u in 2-norm, and the
+later operations are unitary, so after G operations
+    ||psi_gpu - psi_exact||_2 <= 8 G u.
+The tests check that bound on the whole state (and hence on every amplitude).
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import fsv  # noqa: E402
+from paper_2305_14398_amd import binding as B  # noqa: E402
+from paper_2305_14398_amd import workloads as W  # noqa: E402
+from tests import gpu_util as G  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = B.Context(0)
+    yield c
+    c.close()
+
+
+def n_ops(gates):
+    return sum(3 if g[0] == "SWAP" else 1 for g in gates)
+
+
+def bound(gates):
+    return 8 * max(n_ops(gates), 1) * U32
+
+
+def run_fsv(ctx, n, gates, psi0):
+    psi = G.planar_vec(psi0)
+    with B.FsvPlan(ctx, n, gates) as plan:
+        plan.run(psi)
+        G.sync()
+        info = plan.info()
+    return G.vec_to_complex(psi), info
+
+
+def all_kinds(n, rng, count):
+    """Every gate kind, with controls and SWAP partners drawn from the whole register."""
+    out = []
+    one = ("H", "X", "Y", "Z", "S", "T", "R", "RX", "RY", "RZ")
+    two = ("CNOT", "CY", "CZ", "CR", "SWAP")
+    for _ in range(count):
+        if n >= 2 and rng.random() < 0.45:
+            nm = two[int(rng.integers(0, len(two)))]
+            a, b = (int(x) for x in rng.choice(n, 2, replace=False))
+            out.append((nm, (a, b), float(rng.uniform(0, 2 * math.pi)) if nm in W.ANGLED else None))
+        else:
+            nm = one[int(rng.integers(0, len(one)))]
+            out.append((nm, (int(rng.integers(0, n)),), float(rng.uniform(0, 2 * math.pi)) if nm in W.ANGLED else None))
+    return out
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 11, 12, 13, 14, 16])
+def test_fsv_matches_route_b_all_kinds(ctx, n):
+    rng = np.random.default_rng(500 + n)
+    g = all_kinds(n, rng, 40 + 4 * n)
+    psi0 = W.random_state(n, n)
+    got, info = run_fsv(ctx, n, g, psi0)
+    ref = fsv.final_state(n, g, psi0)
+    assert np.linalg.norm(got - ref) <= bound(g), (np.linalg.norm(got - ref), bound(g), info)
+    assert info["ops"] == n_ops(g)
+
+
+@pytest.mark.parametrize("n,family", [(13, "qft"), (15, "qft"), (14, "random"), (17, "random"), (18, "ghz_fanout"),
+                                      (20, "dj")])
+def test_fsv_paper_families(ctx, n, family):
+    rng = np.random.default_rng(n)
+    c = {"qft": lambda: W.qft(n), "random": lambda: W.random_layers(n, 6, rng),
+         "ghz_fanout": lambda: W.ghz_fanout(n), "dj": lambda: W.dj(n, W.dj_mask(n, 5))}[family]()
+    g = W.gate_tuples(c)
+    psi0 = W.random_state(n, 2 * n)
+    got, info = run_fsv(ctx, n, g, psi0)
+    ref = fsv.final_state(n, g, psi0)
+    assert np.linalg.norm(got - ref) <= bound(g)
+    assert info["passes"] == len(B.qsim_fsv_schedule(n, g))
+
+
+def test_fsv_custom_matrix_equals_named_gate(ctx):
+    n = 14
+    r = 1 / math.sqrt(2)
+    named = [("H", (13,), None), ("CNOT", (13, 2), None), ("H", (5,), None)]
+    custom = [("U2", (13,), None, [[r, r], [r, -r]]), ("CNOT", (13, 2), None), ("U2", (5,), None, [[r, r], [r, -r]])]
+    psi0 = W.random_state(n, 3)
+    a, _ = run_fsv(ctx, n, named, psi0)
+    b, _ = run_fsv(ctx, n, custom, psi0)
+    np.testing.assert_array_equal(a, b)
+
+
+def test_fsv_plan_reuse_and_empty(ctx):
+    n = 13
+    g = W.gate_tuples(W.random_layers(n, 3, np.random.default_rng(9)))
+    psi0 = W.random_state(n, 4)
+    psi = G.planar_vec(psi0)
+    with B.FsvPlan(ctx, n, g) as plan:
+        plan.run(psi)
+        plan.run(psi)
+        G.sync()
+    ref = fsv.final_state(n, g + g, psi0)
+    assert np.linalg.norm(G.vec_to_complex(psi) - ref) <= bound(g + g)
+    # no gates: no passes, state untouched
+    before = psi.clone()
+    with B.FsvPlan(ctx, n, []) as plan:
+        assert plan.info()["passes"] == 0
+        plan.run(psi)
+        G.sync()
+    assert torch.equal(before, psi)
+
+
+def test_fsv_init_basis_and_norm(ctx):
+    for n, b in ((1, 1), (2, 3), (12, 4095), (20, 123457)):
+        psi = torch.full((2 << n,), 7.0, dtype=torch.float32, device=G.DEV)
+        B.qsim_fsv_init_basis(ctx, n, b, psi)
+        G.sync()
+        v = G.vec_to_complex(psi)
+        e = np.zeros(1 << n)
+        e[b] = 1
+        np.testing.assert_array_equal(v, e)
+        assert B.qsim_fsv_norm2(ctx, n, psi) == 1.0
+    psi0 = W.random_state(16, 1) * 3.0
+    ref = float(np.sum(np.abs(psi0.astype(np.complex64).astype(np.complex128)) ** 2))
+    assert abs(B.qsim_fsv_norm2(ctx, 16, G.planar_vec(psi0)) - ref) <= 1e-12 * ref
+
+
+# --- full-size states (2-8 GiB), checked against closed forms on the device ------------------
+
+def _err_vs(psi, ref_re, ref_im):
+    N = psi.numel() // 2
+    d = (psi[:N].double() - ref_re) ** 2 + (psi[N:].double() - ref_im) ** 2
+    return math.sqrt(float(d.sum()))
+
+
+def test_fsv_qft_28_of_basis_state_is_the_dft_column(ctx):
+    """QFT|x> has amplitude exp(2 pi i x k / N) / sqrt(N) at k (the DFT, Section 2.5; the closed form
+    the oracle is pinned to), evaluated in float64 on the device from exact integer phases."""
+    n, x = 28, 91_233_457
+    N = 1 << n
+    g = W.gate_tuples(W.qft(n))
+    psi = torch.empty(2 * N, dtype=torch.float32, device=G.DEV)
+    B.qsim_fsv_init_basis(ctx, n, x, psi)
+    with B.FsvPlan(ctx, n, g) as plan:
+        plan.run(psi)
+        G.sync()
+    k = torch.arange(N, dtype=torch.int64, device=G.DEV)
+    ph = ((k * x) % N).double() * (2 * math.pi / N)
+    del k
+    err = _err_vs(psi, torch.cos(ph) / math.sqrt(N), torch.sin(ph) / math.sqrt(N))
+    assert err <= bound(g), (err, bound(g))
+    assert abs(B.qsim_fsv_norm2(ctx, n, psi) - 1.0) <= bound(g)
+
+
+def test_fsv_mirror_28_returns_to_zero_state(ctx):
+    n = 28
+    c = W.mirror(W.random_layers(n, 4, np.random.default_rng(28)))
+    g = W.gate_tuples(c)
+    N = 1 << n
+    psi = torch.empty(2 * N, dtype=torch.float32, device=G.DEV)
+    B.qsim_fsv_init_basis(ctx, n, 0, psi)
+    with B.FsvPlan(ctx, n, g) as plan:
+        plan.run(psi)
+        G.sync()
+    ref_re = torch.zeros(N, dtype=torch.float64, device=G.DEV)
+    ref_re[0] = 1.0
+    err = _err_vs(psi, ref_re, torch.zeros_like(ref_re))
+    assert err <= bound(g), (err, bound(g))
+
+
+def test_fsv_ghz_30(ctx):
+    """GHZ (Section 2.5): (|0...0> + |1...1>)/sqrt(2) on 30 qubits, an 8 GiB state."""
+    n = 30
+    N = 1 << n
+    g = W.gate_tuples(W.ghz_fanout(n))
+    psi = torch.empty(2 * N, dtype=torch.float32, device=G.DEV)
+    B.qsim_fsv_init_basis(ctx, n, 0, psi)
+    with B.FsvPlan(ctx, n, g) as plan:
+        plan.run(psi)
+        G.sync()
+    r = 1 / math.sqrt(2)
+    ends = psi[torch.tensor([0, N - 1, N, 2 * N - 1], device=G.DEV)].cpu().numpy()
+    assert abs(ends[0] - r) <= 1e-7 and abs(ends[1] - r) <= 1e-7 and ends[2] == 0 and ends[3] == 0
+    # the two amplitudes carry the whole norm, so every other amplitude is zero to rounding
+    assert abs(B.qsim_fsv_norm2(ctx, n, psi) - 2 * float(ends[0]) * float(ends[0])) <= 1e-6
+    del psi
+    torch.cuda.empty_cache()
+
+
+def test_fsv_validation(ctx):
+    psi = torch.zeros(64, dtype=torch.float32, device=G.DEV)
+    with pytest.raises(B.QsimError, match="basis"):
+        B.qsim_fsv_init_basis(ctx, 5, 32, psi)
+    with pytest.raises(B.QsimError):
+        B.FsvPlan(ctx, 35, [])
+    with pytest.raises(B.QsimError, match="outside"):
+        B.FsvPlan(ctx, 5, [("H", (5,), None)])
+
+
+# --- custom operations (Section 5.2.2) ------------------------------------------------------
+
+def custom_bound(gates):
+    """8 u per 2x2 operation; a dense 2^m operation in float32 costs about (2^m + 2) 2^(m/2) u."""
+    total = 0.0
+    for g in gates:
+        if len(g) == 4 and g[0] != "U2":
+            D = 1 << len(g[1])
+            total += 2 * (D + 2) * math.sqrt(D)
+        else:
+            total += 8 * (3 if g[0] == "SWAP" else 1)
+    return total * U32
+
+
+@pytest.mark.parametrize("n", [4, 9, 12, 14, 17])
+def test_fsv_custom_ops_match_route_b(ctx, n):
+    from tests.custom_ops import lib_gates
+    g = W.with_custom_ops(W.gate_tuples(W.random_layers(n, 3, np.random.default_rng(n))), n, [1, 2, 3, 5, 6, 6],
+                          700 + n)
+    psi0 = W.random_state(n, 5 * n)
+    got, _ = run_fsv(ctx, n, lib_gates(g), psi0)
+    ref = fsv.final_state(n, g, psi0)
+    assert np.linalg.norm(got - ref) <= custom_bound(g), (np.linalg.norm(got - ref), custom_bound(g))
+
+
+def test_fsv_custom_dft_on_high_qubits_equals_qft_gates(ctx):
+    """The 4-qubit DFT registered as one operation on qubits 20..23 of a 24-qubit state equals the
+    QFT gates on those qubits (both on the GPU, compared with the bound of each)."""
+    from tests.custom_ops import lib_gates
+    n, a, D = 24, 20, 16
+    j = np.arange(D)
+    dft = np.exp(2j * np.pi * np.outer(j, j) / D) / math.sqrt(D)
+    pre = [("H", (q,), None) for q in range(0, n, 3)] + [("CNOT", (0, 22), None), ("RY", (21,), 0.7)]
+    qft_gates = [(nm, tuple(q + a for q in qs), th) for nm, qs, th in W.gate_tuples(W.qft(4))]
+    psi0 = np.zeros(1 << n, dtype=np.complex128)
+    psi0[0] = 1
+    x, _ = run_fsv(ctx, n, lib_gates(pre + [("dft4_on_20", (20, 21, 22, 23), None, dft)]), psi0)
+    y, _ = run_fsv(ctx, n, pre + qft_gates, psi0)
+    assert np.linalg.norm(x - y) <= custom_bound(pre + [("d", (20, 21, 22, 23), None, dft)]) + bound(pre + qft_gates)

@@ -333,3 +333,31 @@ def test_chain_fourteen_qubits_sampled(ctx):
     assert mx < 1e-5
     del U
     torch.cuda.empty_cache()
+
+
+# --- custom operations on qubit ranges (Section 5.2.2) --------------------------------------
+
+@pytest.mark.parametrize("n", [3, 6, 9])
+def test_build_step_custom_ranges(ctx, n):
+    from tests.custom_ops import lib_gates
+    for m in range(1, min(n, 6) + 1):
+        for a in sorted({0, n - m, (n - m) // 2}):
+            M = W.random_unitary(m, 10 * m + a)
+            st = [(f"step_custom_{m}", tuple(range(a, a + m)), None, M)]
+            if a + m < n:
+                st.append(("RY", (a + m,), 0.4))
+            for layout in (B.QSIM_LAYOUT_ROW, B.QSIM_LAYOUT_COL):
+                assert_step_close(gpu_step(ctx, n, lib_gates(st), layout), UA.step_operator(n, st))
+
+
+@pytest.mark.parametrize("n", [5, 11])
+def test_chain_with_custom_ops(ctx, n):
+    from tests.custom_ops import lib_gates
+    g = W.with_custom_ops(W.gate_tuples(W.random_layers(n, 4, np.random.default_rng(n))), n, [1, 2, 3, 4, 6], 300 + n)
+    for prec in FP32_PRECS:
+        U = G.to_complex(gpu_chain(ctx, n, lib_gates(g), prec))
+        if n <= 6:
+            ref = UA.circuit_unitary(n, g)
+            assert np.abs(U - ref).max() <= AMP_TOL
+        cols = W.random_columns(n, 8, 5)
+        assert np.abs(U[:, cols] - fsv.unitary_columns(n, g, cols)).max() <= AMP_TOL

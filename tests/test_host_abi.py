@@ -102,8 +102,8 @@ def test_gate_validation_in_pack():
     nan.theta = math.nan
     _expect(B.QSIM_E_INVALID, B.qsim_pack_steps, 3, [nan], match="angle")
     res = B.gate_record(("H", (0,), None))
-    res.reserved = 1
-    _expect(B.QSIM_E_INVALID, B.qsim_pack_steps, 3, [res], match="reserved")
+    res.op_id = 1
+    _expect(B.QSIM_E_INVALID, B.qsim_pack_steps, 3, [res], match="op_id")
     _expect(B.QSIM_E_RANGE, B.qsim_pack_steps, 0, [])
     _expect(B.QSIM_E_RANGE, B.qsim_pack_steps, 17, [])
 
@@ -208,3 +208,105 @@ def test_serving_validation_without_device():
         B.qsim_submit(None, 3, [("H", (0,), None)], FAKE)
     with pytest.raises(B.QsimError, match="NULL"):
         B.qsim_poll(None, 1)
+
+
+# --- full-state-vector pass schedule (host only) ---------------------------------------------
+
+def _check_schedule(n, gates):
+    from oracle import gates as OG
+    sched = B.qsim_fsv_schedule(n, gates)
+    ops = []
+    for nm, qs, th in gates:
+        if nm == "SWAP":
+            ops += [("X", qs[0]), ("X", qs[1]), ("X", qs[0])]
+        elif len(qs) == 1:
+            ops.append((nm, qs[0]))
+        else:
+            ops.append((nm, qs[1]))
+    nxt = 0
+    for low, highs, first, cnt in sched:
+        assert first == nxt and cnt >= 1
+        nxt += cnt
+        if n <= 12:
+            assert low == n and highs == ()
+        else:
+            assert 6 <= low <= 12 and len(highs) == 12 - low
+            assert list(highs) == sorted(set(highs)) and all(low <= q < n for q in highs)
+        local = set(range(low)) | set(highs)
+        for nm, t in ops[first:first + cnt]:
+            diagonal = nm in ("Z", "S", "T", "R", "RZ", "CZ", "CR")
+            assert diagonal or t in local, (nm, t, low, highs)
+    assert nxt == len(ops)
+    return sched
+
+
+@pytest.mark.parametrize("n", [1, 5, 12, 13, 20, 34])
+def test_fsv_schedule_invariants(n):
+    rng = np.random.default_rng(n)
+    gates = W.gate_tuples(W.random_layers(n, 4, rng)) + W.gate_tuples(W.qft(min(n, 20)))
+    gates.append(("SWAP", (0, n - 1), None) if n > 1 else ("H", (0,), None))
+    sched = _check_schedule(n, gates)
+    if n <= 12:
+        assert len(sched) == 1
+
+
+def test_fsv_schedule_counts():
+    # all targets inside 12 qubits: one pass; diagonal gates never split a pass
+    assert len(B.qsim_fsv_schedule(30, [("H", (q,), None) for q in range(12)])) == 1
+    assert len(B.qsim_fsv_schedule(30, [("H", (0,), None)] + [("RZ", (q,), 0.1) for q in range(30)])) == 1
+    # one H per qubit on 30 qubits: 6 low qubits are always local, 6 more per pass -> 4 passes
+    assert len(B.qsim_fsv_schedule(30, [("H", (q,), None) for q in range(30)])) == 4
+    assert B.qsim_fsv_schedule(5, []) == []
+
+
+def test_fsv_schedule_validation():
+    _expect(B.QSIM_E_RANGE, B.qsim_fsv_schedule, 35, [])
+    _expect(B.QSIM_E_RANGE, B.qsim_fsv_schedule, 0, [])
+    _expect(B.QSIM_E_INVALID, B.qsim_fsv_schedule, 20, [("H", (20,), None)], match="outside")
+    _expect(B.QSIM_E_INVALID, B.FsvPlan, None, 5, [("H", (0,), None)], match="context is NULL")
+
+
+# --- operation data provider and custom ranges (host only) -----------------------------------
+
+def test_register_and_find_unitary():
+    from tests.custom_ops import op_id
+    M = W.random_unitary(3, 1)
+    i = B.qsim_register_unitary("host_test_u3", M)
+    assert i >= 1 and B.qsim_find_unitary("host_test_u3") == (i, 3)
+    assert op_id("host_test_u3", M) == i
+    _expect(B.QSIM_E_INVALID, B.qsim_register_unitary, "host_test_u3", M, match="already")
+    _expect(B.QSIM_E_INVALID, B.qsim_register_unitary, "host_bad", np.ones((4, 4)), match="not unitary")
+    _expect(B.QSIM_E_RANGE, B.qsim_register_unitary, "host_big", np.eye(128))
+    _expect(B.QSIM_E_UNKNOWN_ID, B.qsim_find_unitary, "no_such_op")
+    nan = np.eye(2, dtype=complex)
+    nan[0, 0] = np.nan
+    _expect(B.QSIM_E_INVALID, B.qsim_register_unitary, "host_nan", nan, match="finite")
+
+
+def test_custom_gate_validation_and_spans():
+    from tests.custom_ops import op_id
+    i = op_id("host_span_u2", W.random_unitary(2, 2))
+    # a 2-qubit range spans 2 qubits: an H on the next qubit shares the step, one inside does not
+    assert B.qsim_pack_steps(5, [("CUSTOM", (1, 2), None, i), ("H", (3,), None)]) == [0, 2]
+    assert B.qsim_pack_steps(5, [("CUSTOM", (1, 2), None, i), ("H", (2,), None)]) == [0, 1, 2]
+    _expect(B.QSIM_E_INVALID, B.qsim_pack_steps, 3, [("CUSTOM", (2, 3), None, i)], match="range")
+    _expect(B.QSIM_E_INVALID, B.qsim_pack_steps, 3, [("CUSTOM", (0, 1), None, 99999)], match="not registered")
+    bad = B.gate_record(("H", (0,), None))
+    bad.op_id = 1
+    _expect(B.QSIM_E_INVALID, B.qsim_pack_steps, 3, [bad], match="op_id")
+
+
+def test_fsv_schedule_keeps_custom_ranges_local():
+    from tests.custom_ops import lib_gates
+    n = 24
+    g = W.with_custom_ops(W.gate_tuples(W.random_layers(n, 2, np.random.default_rng(3))), n, [2, 3, 6, 6, 1], 77)
+    lg = lib_gates(g)
+    sched = B.qsim_fsv_schedule(n, lg)
+    ops = []
+    for x in lg:
+        ops += [x] * (3 if x[0] == "SWAP" else 1)
+    for low, highs, first, cnt in sched:
+        local = set(range(low)) | set(highs)
+        for x in ops[first:first + cnt]:
+            if x[0] == "CUSTOM":
+                assert set(x[1]) <= local, (x[1], low, highs)

@@ -321,3 +321,68 @@ def test_collapse_is_the_basis_state():
     from oracle import measure
     psi = measure.collapse(3, 6)
     assert psi[6] == 1.0 and np.count_nonzero(psi) == 1
+
+
+# --- custom operations on qubit ranges (Section 5.2.2) --------------------------------------
+
+def _relabel(gates, offset):
+    return [(nm, tuple(q + offset for q in qs), th) for nm, qs, th in gates]
+
+
+def test_custom_matches_named_gates():
+    n = 5
+    H = OG.one_qubit("H")
+    # one qubit: the matrix of H is H
+    for route in (UA.circuit_unitary, fsv.circuit_unitary):
+        np.testing.assert_allclose(route(n, [("U2", (3,), None, H)]), route(n, [("H", (3,), None)]), atol=TOL)
+    # two qubits, index bit 0 = qubit a: CNOT(a -> a+1) flips bit 1 where bit 0 is set
+    cnot_le = np.zeros((4, 4))
+    for s_ in range(4):
+        r_ = s_ ^ 2 if s_ & 1 else s_
+        cnot_le[r_, s_] = 1
+    for a in (0, 2, 3):
+        for route in (UA.circuit_unitary, fsv.circuit_unitary):
+            np.testing.assert_allclose(route(n, [("cnot", (a, a + 1), None, cnot_le)]),
+                                       route(n, [("CNOT", (a, a + 1), None)]), atol=TOL)
+
+
+@pytest.mark.parametrize("a", [0, 1, 3])
+def test_custom_dft_equals_qft_subcircuit(a):
+    """A registered 3-qubit DFT matrix (omega^{jk} / sqrt 8) on qubits a..a+2 equals the QFT gates on them."""
+    n = 6
+    D = 8
+    j = np.arange(D)
+    dft = np.exp(2j * np.pi * np.outer(j, j) / D) / math.sqrt(D)
+    rng = np.random.default_rng(a)
+    pre = W.gate_tuples(W.random_layers(n, 2, rng))
+    custom = pre + [("dft3", (a, a + 1, a + 2), None, dft)] + [("H", (5,), None)]
+    named = pre + _relabel(W.gate_tuples(W.qft(3)), a) + [("H", (5,), None)]
+    for route in (UA.circuit_unitary, fsv.circuit_unitary):
+        np.testing.assert_allclose(route(n, custom), route(n, named), atol=1e-12)
+
+
+def test_custom_brute_force_entries():
+    """U[r][s] = M[r_range][s_range] * [r and s agree outside the range], entry by entry."""
+    n, a, m = 4, 1, 2
+    M = W.random_unitary(m, 7)
+    U = UA.circuit_unitary(n, [("c", (a, a + 1), None, M)])
+    mask = ((1 << m) - 1) << a
+    for r_ in range(1 << n):
+        for s_ in range(1 << n):
+            want = M[(r_ & mask) >> a, (s_ & mask) >> a] if (r_ & ~mask) == (s_ & ~mask) else 0
+            assert abs(U[r_, s_] - want) < 1e-14
+
+
+@pytest.mark.parametrize("n", [3, 6, 8])
+def test_custom_route_a_equals_route_b(n):
+    g = W.with_custom_ops(W.gate_tuples(W.random_layers(n, 3, np.random.default_rng(n))), n, [1, 2, 3, n], 40 + n)
+    A = UA.circuit_unitary(n, g)
+    np.testing.assert_allclose(A, fsv.circuit_unitary(n, g), atol=1e-12)
+    np.testing.assert_allclose(A.conj().T @ A, np.eye(1 << n), atol=1e-12)
+
+
+def test_custom_range_checks():
+    with pytest.raises(ValueError):
+        UA.circuit_unitary(3, [("c", (0, 2), None, np.eye(4))])
+    with pytest.raises(ValueError):
+        fsv.circuit_unitary(3, [("c", (0, 1), None, np.eye(8))])
