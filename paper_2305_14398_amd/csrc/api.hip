@@ -152,7 +152,9 @@ void gate_matrix(const qsim_gate& g, double m[8]) {
 }
 
 // Stage 3-4 input: the descriptor of one step (gates must be validated and
-// pairwise span-disjoint).
+// pairwise span-disjoint).  Custom operations point at their matrix on the
+// current device, so a descriptor that will be launched is built with the
+// launch device current.
 qsim_status make_step(int n, const qsim_gate* gates, int count, DevStep& st) {
     if (count > QSIM_MAX_GATES_PER_STEP)
         return fail(QSIM_E_INVALID, "step has %d gates (max %d)", count, QSIM_MAX_GATES_PER_STEP);
@@ -391,12 +393,14 @@ qsim_status qsim_build_step(qsim_ctx* ctx, int n_qubits, const qsim_gate* gates,
     s = check_gates(n_qubits, gates, n_gates);
     if (s != QSIM_OK) return s;
     DevStep st;
-    s = make_step(n_qubits, gates, n_gates, st);
+    s = make_step(n_qubits, gates, n_gates, st);  // validation (the device pointers are rebuilt below)
     if (s != QSIM_OK) return s;
     s = check_ctx(ctx);
     if (s != QSIM_OK) return s;
     DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return device_fail("hipSetDevice", g.err);
+    s = make_step(n_qubits, gates, n_gates, st);
+    if (s != QSIM_OK) return s;
     hipStream_t hs = static_cast<hipStream_t>(stream);
     hipError_t e = timed(ctx->prof, QSIM_PROFILE_EXPAND, hs,
                          [&] { return launch_expand_step(st, n_qubits, layout, format_of(prec), d_op, hs); });

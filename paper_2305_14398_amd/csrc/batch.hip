@@ -128,6 +128,9 @@ qsim_status qsim_batch_plan_create(qsim_ctx* ctx, const qsim_circuit_desc* circu
     }
     qsim_status s = check_ctx(ctx);
     if (s != QSIM_OK) return s;
+    // Step descriptors hold device pointers of custom operations: build them on the context's device.
+    DeviceGuard dg(ctx->device);
+    if (dg.err != hipSuccess) return device_fail("hipSetDevice", dg.err);
 
     const OpFormat fmt = format_of(prec);
     const bool split = fmt != FMT_F32;

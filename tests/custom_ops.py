@@ -5,12 +5,21 @@ import numpy as np
 from paper_2305_14398_amd import binding as B
 
 
+_seen = {}
+
+
 def op_id(name: str, matrix) -> int:
+    M = np.asarray(matrix, dtype=np.complex128)
+    if name in _seen:
+        if not np.array_equal(_seen[name], M):
+            raise ValueError(f"{name} is already registered with another matrix")
+    else:
+        _seen[name] = M.copy()
     try:
         i, m = B.qsim_find_unitary(name)
     except B.QsimError:
-        return B.qsim_register_unitary(name, matrix)
-    if (1 << m) != np.asarray(matrix).shape[0]:
+        return B.qsim_register_unitary(name, M)
+    if (1 << m) != M.shape[0]:
         raise ValueError(f"{name} is registered with another size")
     return i
 

@@ -343,7 +343,7 @@ def test_build_step_custom_ranges(ctx, n):
     for m in range(1, min(n, 6) + 1):
         for a in sorted({0, n - m, (n - m) // 2}):
             M = W.random_unitary(m, 10 * m + a)
-            st = [(f"step_custom_{m}", tuple(range(a, a + m)), None, M)]
+            st = [(f"step_custom_{m}_{a}", tuple(range(a, a + m)), None, M)]
             if a + m < n:
                 st.append(("RY", (a + m,), 0.4))
             for layout in (B.QSIM_LAYOUT_ROW, B.QSIM_LAYOUT_COL):
