@@ -13,7 +13,10 @@
 // in registers and writes them back, so a pass costs 16 bytes of HBM traffic
 // per amplitude however many gates it holds.
 //
-// Inside a workgroup, 256 threads hold 16 amplitudes each.  Of the 12 local
+// A workgroup copies the pass's operation records (at most 256 per pass) into
+// LDS before it starts.  Inside a workgroup, 256 threads hold 16 amplitudes
+// each (16-wide vector registers, so no amplitude ever goes through scratch).
+// Of the 12 local
 // index bits, 4 live in a thread's registers and 8 in its thread index; three
 // layouts put bits 0-3, 4-7 or 8-11 in registers.  A gate whose target bit is
 // in the register group updates 8 register pairs per thread with no exchange;
@@ -22,11 +25,13 @@
 // Controls never need to be local: a control on a local bit is a per-register
 // predicate, one on any other qubit is the same for the whole workgroup.
 // Diagonal gates (Z, S, T, R, RZ, CZ, controlled phases) only scale
-// amplitudes, so they need no local target at all.  SWAP runs as three CNOTs,
-// which permute amplitudes exactly.  A custom operation on m qubits (Section
-// 5.2.2) needs its whole range local; it is applied through LDS: every
-// amplitude is written out, then each thread forms its 16 outputs as sums of
-// 2^m products with the operation's float32 matrix.
+// amplitudes, so they need no local target at all; when neither of their
+// qubits is a register bit, their factor is the same for a thread's 16
+// amplitudes and is folded into one per-thread phase that is applied once.
+// SWAP runs as three CNOTs, which permute amplitudes exactly.  A custom
+// operation on m qubits (Section 5.2.2) needs its whole range local; it is
+// applied through LDS: every amplitude is written out, then each thread forms
+// its 16 outputs as sums of 2^m products with the operation's float32 matrix.
 //
 // Gate entries are the float64 matrices of the unitary path rounded once to
 // float32; amplitude arithmetic is float32 with fused multiply-adds.
@@ -41,8 +46,11 @@ constexpr int kFsvLocal = 12;     // local qubits per workgroup: 4096 amplitudes
 constexpr int kFsvMinLow = 6;     // low qubits always local: 64 lanes x 4 B contiguous per plane
 constexpr int kFsvMaxHigh = kFsvLocal - kFsvMinLow;
 constexpr int kFsvNormBlocks = 1024;
+constexpr int kFsvMaxOps = 256;   // operations per pass, staged in LDS (16 KiB)
 
-enum : int32_t { FSV_GENERAL = 0, FSV_DIAG = 1, FSV_DENSE = 2 };
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+enum : int32_t { FSV_GENERAL = 0, FSV_DIAG = 1, FSV_DENSE = 2, FSV_TABLE = 3 };
 
 struct FsvGate {
     int32_t kind;
@@ -51,8 +59,8 @@ struct FsvGate {
     int32_t cloc;   // local bit of the control, or -1
     int32_t cglob;  // a non-local control qubit, or -1
     int32_t width;  // dense: qubits in the range
-    int32_t moff;   // dense: offset of its 2^w x 2^w (re, im) float32 matrix in the plan's pool
-    int32_t pad;
+    int32_t moff;   // dense / table: offset of its float32 (re, im) data in the plan's pool
+    int32_t real;   // general: 1 if every matrix entry is real
     float m[8];  // row-major 2x2 (re, im); a diagonal gate uses m[0..1] and m[6..7]
 };
 
@@ -60,7 +68,8 @@ struct FsvPass {
     int32_t L;   // local bits 0..L-1 are qubits 0..L-1
     int32_t nh;  // local bits L..L+nh-1 are qubits high[0..nh-1], ascending
     int32_t high[kFsvMaxHigh];
-    int32_t g0, g1;  // the pass's gates in the plan's table
+    int32_t g0, g1;  // the pass's records in the plan's table
+    int32_t op0, op1;  // the operations (SWAP = three) the pass covers
 };
 
 namespace {
@@ -84,52 +93,154 @@ __device__ __forceinline__ int fsv_pos(const FsvPass& p, int b) {
     return q;
 }
 
-template <int RB>
-__device__ __forceinline__ void fsv_general(float (&ar)[16], float (&ai)[16], const FsvGate& g, int jt, int sh) {
+// Complex multiply-accumulate helpers (float32, fused).
+__device__ __forceinline__ void cmul(float& xr, float& xi, float fr, float fi) {
+    const float yr = fmaf(fr, xr, -fi * xi);
+    const float yi = fmaf(fr, xi, fi * xr);
+    xr = yr;
+    xi = yi;
+}
+
+__device__ __forceinline__ void cmul_at(f32x16& ar, f32x16& ai, int r, float fr, float fi) {
+    const float xr = ar[r], xi = ai[r];
+    ar[r] = fmaf(fr, xr, -fi * xi);
+    ai[r] = fmaf(fr, xi, fi * xr);
+}
+
+// Non-diagonal 2x2 on register bit RB.  CP = register bit of the control
+// (compile time), or -1 (no control, or a control on a lane index bit,
+// applied by a whole-register select).  REAL:
+// every entry is real (H, X, RY, CNOT), half the multiply-adds.
+template <int RB, int CP, bool REAL>
+__device__ __forceinline__ void fsv_general(f32x16& ar, f32x16& ai, const FsvGate& g) {
     const float m0r = g.m[0], m0i = g.m[1], m1r = g.m[2], m1i = g.m[3];
     const float m2r = g.m[4], m2i = g.m[5], m3r = g.m[6], m3i = g.m[7];
-#pragma unroll
+#pragma clang loop unroll(full)
     for (int r0 = 0; r0 < 16; ++r0) {
         if ((r0 >> RB) & 1) continue;
+        if constexpr (CP >= 0) {
+            if (!((r0 >> CP) & 1)) continue;
+        }
         const int r1 = r0 | (1 << RB);
-        const bool on = g.cloc < 0 || (((jt | (r0 << sh)) >> g.cloc) & 1);
         const float x0r = ar[r0], x0i = ai[r0], x1r = ar[r1], x1i = ai[r1];
-        const float y0r = fmaf(m0r, x0r, fmaf(-m0i, x0i, fmaf(m1r, x1r, -m1i * x1i)));
-        const float y0i = fmaf(m0r, x0i, fmaf(m0i, x0r, fmaf(m1r, x1i, m1i * x1r)));
-        const float y1r = fmaf(m2r, x0r, fmaf(-m2i, x0i, fmaf(m3r, x1r, -m3i * x1i)));
-        const float y1i = fmaf(m2r, x0i, fmaf(m2i, x0r, fmaf(m3r, x1i, m3i * x1r)));
-        ar[r0] = on ? y0r : x0r;
-        ai[r0] = on ? y0i : x0i;
-        ar[r1] = on ? y1r : x1r;
-        ai[r1] = on ? y1i : x1i;
+        float y0r, y0i, y1r, y1i;
+        if (REAL) {
+            y0r = fmaf(m0r, x0r, m1r * x1r);
+            y0i = fmaf(m0r, x0i, m1r * x1i);
+            y1r = fmaf(m2r, x0r, m3r * x1r);
+            y1i = fmaf(m2r, x0i, m3r * x1i);
+        } else {
+            y0r = fmaf(m0r, x0r, fmaf(-m0i, x0i, fmaf(m1r, x1r, -m1i * x1i)));
+            y0i = fmaf(m0r, x0i, fmaf(m0i, x0r, fmaf(m1r, x1i, m1i * x1r)));
+            y1r = fmaf(m2r, x0r, fmaf(-m2i, x0i, fmaf(m3r, x1r, -m3i * x1i)));
+            y1i = fmaf(m2r, x0i, fmaf(m2i, x0r, fmaf(m3r, x1i, m3i * x1r)));
+        }
+        ar[r0] = y0r;
+        ai[r0] = y0i;
+        ar[r1] = y1r;
+        ai[r1] = y1i;
     }
 }
 
-__device__ __forceinline__ void fsv_diag(float (&ar)[16], float (&ai)[16], const FsvGate& g, int jt, int sh,
-                                         uint64_t base) {
-    const int tb_uniform = g.tloc < 0 ? (int)((base >> g.tglob) & 1) : 0;
-#pragma unroll
+template <int RB, bool REAL>
+__device__ __forceinline__ void fsv_general_cp(f32x16& ar, f32x16& ai, const FsvGate& g, int cp, bool lane_ctrl,
+                                               bool lane_on) {
+    switch (cp) {
+        case 0: if constexpr (RB != 0) fsv_general<RB, 0, REAL>(ar, ai, g); break;
+        case 1: if constexpr (RB != 1) fsv_general<RB, 1, REAL>(ar, ai, g); break;
+        case 2: if constexpr (RB != 2) fsv_general<RB, 2, REAL>(ar, ai, g); break;
+        case 3: if constexpr (RB != 3) fsv_general<RB, 3, REAL>(ar, ai, g); break;
+        default:
+            // a control on one of the lane's index bits selects per lane
+            if (lane_ctrl) {
+                f32x16 br = ar, bi = ai;
+                fsv_general<RB, -1, REAL>(br, bi, g);
+                ar = lane_on ? br : ar;
+                ai = lane_on ? bi : ai;
+            } else {
+                fsv_general<RB, -1, REAL>(ar, ai, g);
+            }
+            break;
+    }
+}
+
+template <int RB>
+__device__ __forceinline__ void fsv_general_rb(f32x16& ar, f32x16& ai, const FsvGate& g, int cp,
+                                               bool lane_ctrl, bool lane_on) {
+    if (g.real)
+        fsv_general_cp<RB, true>(ar, ai, g, cp, lane_ctrl, lane_on);
+    else
+        fsv_general_cp<RB, false>(ar, ai, g, cp, lane_ctrl, lane_on);
+}
+
+// A run of diagonal operations on local qubits, multiplied out on the host:
+// amplitude j (local index) times tab[j].
+__device__ __forceinline__ void fsv_table(f32x16& ar, f32x16& ai, const float* __restrict__ tab, int jt, int sh) {
+#pragma clang loop unroll(full)
     for (int r = 0; r < 16; ++r) {
         const int j = jt | (r << sh);
-        const bool on = g.cloc < 0 || ((j >> g.cloc) & 1);
-        const int bit = g.tloc < 0 ? tb_uniform : ((j >> g.tloc) & 1);
-        const float dr = bit ? g.m[6] : g.m[0];
-        const float di = bit ? g.m[7] : g.m[1];
-        const float xr = ar[r], xi = ai[r];
-        const float yr = fmaf(dr, xr, -di * xi);
-        const float yi = fmaf(dr, xi, di * xr);
-        ar[r] = on ? yr : xr;
-        ai[r] = on ? yi : xi;
+        const float2 f = *reinterpret_cast<const float2*>(tab + 2 * j);
+        cmul_at(ar, ai, r, f.x, f.y);
+    }
+}
+
+// Registers whose bit P is set (or all, P < 0) times the per-lane factor f.
+template <int P>
+__device__ __forceinline__ void fsv_scale(f32x16& ar, f32x16& ai, float fr, float fi) {
+#pragma clang loop unroll(full)
+    for (int r = 0; r < 16; ++r) {
+        if constexpr (P >= 0) {
+            if (!((r >> P) & 1)) continue;
+        }
+        cmul_at(ar, ai, r, fr, fi);
+    }
+}
+
+// Registers with bit CP set (all if CP < 0) times d1 where bit TP is set, else d0
+// (d0 skipped when it is exactly 1).
+template <int TP, int CP>
+__device__ __forceinline__ void fsv_diag_reg(f32x16& ar, f32x16& ai, float d0r, float d0i, float d1r,
+                                             float d1i, bool d0_one) {
+#pragma clang loop unroll(full)
+    for (int r = 0; r < 16; ++r) {
+        if constexpr (CP >= 0) {
+            if (!((r >> CP) & 1)) continue;
+        }
+        if ((r >> TP) & 1)
+            cmul_at(ar, ai, r, d1r, d1i);
+        else if (!d0_one)
+            cmul_at(ar, ai, r, d0r, d0i);
+    }
+}
+
+__device__ __forceinline__ void fsv_flush(f32x16& ar, f32x16& ai, float& lpr, float& lpi, bool& pending) {
+    if (pending) {
+        fsv_scale<-1>(ar, ai, lpr, lpi);
+        lpr = 1.f;
+        lpi = 0.f;
+        pending = false;
+    }
+}
+
+template <int TP>
+__device__ __forceinline__ void fsv_diag_tp(f32x16& ar, f32x16& ai, int cp, float d0r, float d0i, float d1r,
+                                            float d1i, bool d0_one) {
+    switch (cp) {
+        case 0: if constexpr (TP != 0) fsv_diag_reg<TP, 0>(ar, ai, d0r, d0i, d1r, d1i, d0_one); break;
+        case 1: if constexpr (TP != 1) fsv_diag_reg<TP, 1>(ar, ai, d0r, d0i, d1r, d1i, d0_one); break;
+        case 2: if constexpr (TP != 2) fsv_diag_reg<TP, 2>(ar, ai, d0r, d0i, d1r, d1i, d0_one); break;
+        case 3: if constexpr (TP != 3) fsv_diag_reg<TP, 3>(ar, ai, d0r, d0i, d1r, d1i, d0_one); break;
+        default: fsv_diag_reg<TP, -1>(ar, ai, d0r, d0i, d1r, d1i, d0_one); break;
     }
 }
 
 // A dense operation on local bits lb .. lb+w-1: out[j] = sum_s M[row(j)][s] in[j with
 // those bits = s], through LDS; the register layout is unchanged.
-__device__ __forceinline__ void fsv_dense(float (&ar)[16], float (&ai)[16], int t, int cur, const FsvGate& g,
+__device__ __forceinline__ void fsv_dense(f32x16& ar, f32x16& ai, int t, int cur, const FsvGate& g,
                                           const float* __restrict__ pool, float* s_re, float* s_im) {
     __syncthreads();
     const int jt = fsv_thread_bits(t, cur), sh = 4 * cur;
-#pragma unroll
+#pragma clang loop unroll(full)
     for (int r = 0; r < 16; ++r) {
         const int a = fsv_swz(jt | (r << sh));
         s_re[a] = ar[r];
@@ -139,7 +250,7 @@ __device__ __forceinline__ void fsv_dense(float (&ar)[16], float (&ai)[16], int 
     const int lb = g.tloc, W = 1 << g.width;
     const int field = (W - 1) << lb;
     const float* M = pool + g.moff;
-#pragma unroll
+#pragma clang loop unroll(full)
     for (int r = 0; r < 16; ++r) {
         const int j = jt | (r << sh);
         const int row = (j >> lb) & (W - 1);
@@ -159,11 +270,11 @@ __device__ __forceinline__ void fsv_dense(float (&ar)[16], float (&ai)[16], int 
 }
 
 // Layout change cur -> k through LDS.
-__device__ __forceinline__ void fsv_relayout(float (&ar)[16], float (&ai)[16], int t, int cur, int k, float* s_re,
+__device__ __forceinline__ void fsv_relayout(f32x16& ar, f32x16& ai, int t, int cur, int k, float* s_re,
                                              float* s_im) {
     __syncthreads();  // earlier readers of the buffer are done
     const int jt = fsv_thread_bits(t, cur), sh = 4 * cur;
-#pragma unroll
+#pragma clang loop unroll(full)
     for (int r = 0; r < 16; ++r) {
         const int a = fsv_swz(jt | (r << sh));
         s_re[a] = ar[r];
@@ -171,7 +282,7 @@ __device__ __forceinline__ void fsv_relayout(float (&ar)[16], float (&ai)[16], i
     }
     __syncthreads();
     const int jn = fsv_thread_bits(t, k), shn = 4 * k;
-#pragma unroll
+#pragma clang loop unroll(full)
     for (int r = 0; r < 16; ++r) {
         const int a = fsv_swz(jn | (r << shn));
         ar[r] = s_re[a];
@@ -183,6 +294,7 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
                                                       const float* __restrict__ pool, float* __restrict__ re,
                                                       float* __restrict__ im) {
     __shared__ float s_re[1 << kFsvLocal], s_im[1 << kFsvLocal];
+    __shared__ FsvGate s_ops[kFsvMaxOps];
     const int t = threadIdx.x;
 
     // Global index of local index 0: the workgroup number with zero bits
@@ -209,8 +321,8 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
     const bool full = n >= kFsvLocal;
     const int nloc = full ? (1 << kFsvLocal) : (1 << n);
 
-    float ar[16], ai[16];
-#pragma unroll
+    f32x16 ar, ai;
+#pragma clang loop unroll(full)
     for (int r = 0; r < 16; ++r) {
         const int j = t | (r << 8);
         uint64_t g = base | gt;
@@ -226,32 +338,120 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
         }
     }
 
+    // Diagonal factors that depend only on this lane's index bits (and the
+    // workgroup's) are gathered into one per-lane phase and applied to all 16
+    // registers only when the layout changes, a non-diagonal operation comes,
+    // or the pass ends.
+    float lpr = 1.f, lpi = 0.f;
+    bool lp_pending = false;
+
     int cur = 2;
-    for (int gi = p.g0; gi < p.g1; ++gi) {
-        const FsvGate g = gates[gi];
+    // Stage the pass's operation records in LDS once per workgroup: every
+    // thread then reads each record at LDS latency instead of a scalar-cache miss.
+    const int nops = p.g1 - p.g0;
+    {
+        const int* src = reinterpret_cast<const int*>(gates + p.g0);
+        int* dst = reinterpret_cast<int*>(s_ops);
+        const int words = nops * (int)(sizeof(FsvGate) / sizeof(int));
+        for (int w = t; w < words; w += 256) dst[w] = src[w];
+    }
+    __syncthreads();
+    // The next record is read from LDS while the current one executes.
+    FsvGate nxt = nops > 0 ? s_ops[0] : FsvGate{};
+    for (int gi = 0; gi < nops; ++gi) {
+        FsvGate g;
+        g.kind = __builtin_amdgcn_readfirstlane(nxt.kind);
+        g.tloc = __builtin_amdgcn_readfirstlane(nxt.tloc);
+        g.tglob = __builtin_amdgcn_readfirstlane(nxt.tglob);
+        g.cloc = __builtin_amdgcn_readfirstlane(nxt.cloc);
+        g.cglob = __builtin_amdgcn_readfirstlane(nxt.cglob);
+        g.width = __builtin_amdgcn_readfirstlane(nxt.width);
+        g.moff = __builtin_amdgcn_readfirstlane(nxt.moff);
+        g.real = __builtin_amdgcn_readfirstlane(nxt.real);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) g.m[k] = nxt.m[k];
+        if (gi + 1 < nops) nxt = s_ops[gi + 1];
         if (g.cglob >= 0 && !((base >> g.cglob) & 1)) continue;  // non-local control is 0 here
+        if (g.kind == FSV_TABLE) {
+            fsv_table(ar, ai, pool + g.moff, fsv_thread_bits(t, cur), 4 * cur);
+            continue;
+        }
+        if (g.kind == FSV_DENSE) {
+            fsv_flush(ar, ai, lpr, lpi, lp_pending);
+            fsv_dense(ar, ai, t, cur, g, pool, s_re, s_im);
+            continue;
+        }
         if (g.kind == FSV_GENERAL) {
             const int k = g.tloc >> 2;
+            fsv_flush(ar, ai, lpr, lpi, lp_pending);
             if (k != cur) {
                 fsv_relayout(ar, ai, t, cur, k, s_re, s_im);
                 cur = k;
             }
-            const int jt = fsv_thread_bits(t, cur), sh = 4 * cur;
-            switch (g.tloc & 3) {
-                case 0: fsv_general<0>(ar, ai, g, jt, sh); break;
-                case 1: fsv_general<1>(ar, ai, g, jt, sh); break;
-                case 2: fsv_general<2>(ar, ai, g, jt, sh); break;
-                default: fsv_general<3>(ar, ai, g, jt, sh); break;
+        }
+        const int jt = fsv_thread_bits(t, cur);
+        // control: a register bit (cp >= 0), a lane bit, or none
+        int cp = -1;
+        bool lane_ctrl = false, lane_on = true;
+        if (g.cloc >= 0) {
+            if ((g.cloc >> 2) == cur) {
+                cp = g.cloc & 3;
+            } else {
+                lane_ctrl = true;
+                lane_on = (jt >> g.cloc) & 1;
             }
-        } else if (g.kind == FSV_DIAG) {
-            fsv_diag(ar, ai, g, fsv_thread_bits(t, cur), 4 * cur, base);
+        }
+        if (g.kind == FSV_GENERAL) {
+            switch (g.tloc & 3) {
+                case 0: fsv_general_rb<0>(ar, ai, g, cp, lane_ctrl, lane_on); break;
+                case 1: fsv_general_rb<1>(ar, ai, g, cp, lane_ctrl, lane_on); break;
+                case 2: fsv_general_rb<2>(ar, ai, g, cp, lane_ctrl, lane_on); break;
+                default: fsv_general_rb<3>(ar, ai, g, cp, lane_ctrl, lane_on); break;
+            }
+            continue;
+        }
+        // diagonal: target a register bit (tp >= 0), a lane bit or a workgroup bit
+        const float d0r = g.m[0], d0i = g.m[1], d1r = g.m[6], d1i = g.m[7];
+        int tp = -1, tval = 0;
+        if (g.tloc < 0)
+            tval = (int)((base >> g.tglob) & 1);
+        else if ((g.tloc >> 2) == cur)
+            tp = g.tloc & 3;
+        else
+            tval = (jt >> g.tloc) & 1;
+        if (tp < 0 && cp < 0) {
+            // one factor per lane: d_tval where the control holds, else 1
+            const bool on = lane_on;
+            const float fr = on ? (tval ? d1r : d0r) : 1.f;
+            const float fi = on ? (tval ? d1i : d0i) : 0.f;
+            cmul(lpr, lpi, fr, fi);
+            lp_pending = true;
+        } else if (tp < 0) {
+            // control on register bit cp: those registers times d_tval
+            const float fr = tval ? d1r : d0r, fi = tval ? d1i : d0i;
+            switch (cp) {
+                case 0: fsv_scale<0>(ar, ai, fr, fi); break;
+                case 1: fsv_scale<1>(ar, ai, fr, fi); break;
+                case 2: fsv_scale<2>(ar, ai, fr, fi); break;
+                default: fsv_scale<3>(ar, ai, fr, fi); break;
+            }
         } else {
-            fsv_dense(ar, ai, t, cur, g, pool, s_re, s_im);
+            // target on register bit tp; a lane control folds into the factors
+            const bool d0_one = d0r == 1.f && d0i == 0.f;
+            const float e0r = lane_on ? d0r : 1.f, e0i = lane_on ? d0i : 0.f;
+            const float e1r = lane_on ? d1r : 1.f, e1i = lane_on ? d1i : 0.f;
+            switch (tp) {
+                case 0: fsv_diag_tp<0>(ar, ai, cp, e0r, e0i, e1r, e1i, d0_one); break;
+                case 1: fsv_diag_tp<1>(ar, ai, cp, e0r, e0i, e1r, e1i, d0_one); break;
+                case 2: fsv_diag_tp<2>(ar, ai, cp, e0r, e0i, e1r, e1i, d0_one); break;
+                default: fsv_diag_tp<3>(ar, ai, cp, e0r, e0i, e1r, e1i, d0_one); break;
+            }
         }
     }
+    fsv_flush(ar, ai, lpr, lpi, lp_pending);
     if (cur != 2) fsv_relayout(ar, ai, t, cur, 2, s_re, s_im);
 
-#pragma unroll
+#pragma clang loop unroll(full)
     for (int r = 0; r < 16; ++r) {
         const int j = t | (r << 8);
         uint64_t g = base | gt;
@@ -320,6 +520,7 @@ struct LoweredGate {
     int width = 0;  // dense: qubits in the range
     int32_t op = 0; // dense: registered operation
     float m[8];
+    double md[8];   // the float64 matrix (diagonal runs are multiplied out from it)
 };
 
 void lower(const qsim_gate* gates, int n_gates, std::vector<LoweredGate>& out) {
@@ -345,6 +546,7 @@ void lower(const qsim_gate* gates, int n_gates, std::vector<LoweredGate>& out) {
                 l.tq = rep == 1 ? a : b;
                 l.cq = rep == 1 ? b : a;
                 std::copy(x, x + 8, l.m);
+                std::copy(x, x + 8, l.md);
                 out.push_back(l);
             }
             continue;
@@ -355,7 +557,10 @@ void lower(const qsim_gate* gates, int n_gates, std::vector<LoweredGate>& out) {
         l.kind = (m[2] == 0 && m[3] == 0 && m[4] == 0 && m[5] == 0) ? FSV_DIAG : FSV_GENERAL;
         l.tq = g.target;
         l.cq = g.control;
-        for (int k = 0; k < 8; ++k) l.m[k] = (float)m[k];
+        for (int k = 0; k < 8; ++k) {
+            l.m[k] = (float)m[k];
+            l.md[k] = m[k];
+        }
         out.push_back(l);
     }
 }
@@ -403,10 +608,10 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
         if (n <= kFsvLocal) {
             p.L = n;
             p.nh = 0;
-            j = gs.size();
+            j = std::min(gs.size(), i + kFsvMaxOps);
         } else {
             int L = kFsvLocal;
-            for (; j < gs.size(); ++j) {
+            for (; j < gs.size() && j - i < (size_t)kFsvMaxOps; ++j) {
                 const uint64_t T2 = T | local_need(gs[j]);
                 const int L2 = fit_low(T2);
                 if (L2 < 0) break;
@@ -431,8 +636,9 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
             return -1;
         };
         p.g0 = (int)table.size();
-        for (size_t k = i; k < j; ++k) {
-            const LoweredGate& l = gs[k];
+        p.op0 = (int)i;
+        p.op1 = (int)j;
+        auto record = [&](const LoweredGate& l) {
             FsvGate d{};
             d.kind = l.kind;
             d.tloc = local_bit(l.tq);
@@ -443,8 +649,105 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
                 d.width = l.width;
                 d.moff = pool_offset(l.op, l.width, pool, seen);
             }
+            d.real = (l.m[1] == 0.f && l.m[3] == 0.f && l.m[5] == 0.f && l.m[7] == 0.f) ? 1 : 0;
             std::copy(l.m, l.m + 8, d.m);
-            table.push_back(d);
+            return d;
+        };
+        // Reorder the pass's operations where they commute (disjoint qubits, or
+        // both diagonal) so that fewer layout changes are needed: ready
+        // diagonal and custom operations first, then non-diagonal ones in the
+        // current register layout, else the earliest ready one.
+        std::vector<size_t> order;
+        {
+            const size_t m = j - i;
+            std::vector<uint64_t> qm(m);
+            std::vector<char> dg(m);
+            for (size_t a = 0; a < m; ++a) {
+                const LoweredGate& l = gs[i + a];
+                qm[a] = l.kind == FSV_DENSE ? (((uint64_t)1 << l.width) - 1) << l.tq
+                                            : ((uint64_t)1 << l.tq) | (l.cq >= 0 ? (uint64_t)1 << l.cq : 0);
+                dg[a] = l.kind == FSV_DIAG;
+            }
+            std::vector<std::vector<int>> succ(m);
+            std::vector<int> indeg(m, 0);
+            for (size_t b = 0; b < m; ++b)
+                for (size_t a = 0; a < b; ++a)
+                    if ((qm[a] & qm[b]) && !(dg[a] && dg[b])) {
+                        succ[a].push_back((int)b);
+                        ++indeg[b];
+                    }
+            std::vector<char> done(m, 0);
+            int cur = 2;
+            while (order.size() < m) {
+                int pick = -1, pick_general = -1;
+                for (size_t a = 0; a < m; ++a) {
+                    if (done[a] || indeg[a] != 0) continue;
+                    const LoweredGate& l = gs[i + a];
+                    if (l.kind != FSV_GENERAL) {
+                        pick = (int)a;
+                        break;
+                    }
+                    if ((local_bit(l.tq) >> 2) == cur) {
+                        if (pick < 0) pick = (int)a;
+                    } else if (pick_general < 0) {
+                        pick_general = (int)a;
+                    }
+                }
+                if (pick < 0) {
+                    pick = pick_general;
+                    cur = local_bit(gs[i + pick].tq) >> 2;
+                }
+                done[pick] = 1;
+                order.push_back(i + pick);
+                for (int b : succ[pick]) --indeg[b];
+            }
+        }
+        for (size_t k = 0; k < order.size();) {
+            if (gs[order[k]].kind != FSV_DIAG) {
+                table.push_back(record(gs[order[k]]));
+                ++k;
+                continue;
+            }
+            // A run of diagonal operations (they commute): those whose qubits
+            // are all local become one table of 4096 float64 products rounded
+            // once; the others stay individual records after it.
+            size_t e = k;
+            while (e < order.size() && gs[order[e]].kind == FSV_DIAG) ++e;
+            std::vector<size_t> local_ops, other_ops;
+            for (size_t x = k; x < e; ++x) {
+                const size_t q = order[x];
+                const bool local = local_bit(gs[q].tq) >= 0 && (gs[q].cq < 0 || local_bit(gs[q].cq) >= 0);
+                (local ? local_ops : other_ops).push_back(q);
+            }
+            if (local_ops.size() >= 2) {
+                FsvGate d{};
+                d.kind = FSV_TABLE;
+                d.tloc = d.tglob = d.cloc = d.cglob = -1;
+                d.moff = (int)pool.size();
+                const int nl = std::min(n, kFsvLocal);
+                for (int jj = 0; jj < (1 << kFsvLocal); ++jj) {
+                    double fr = 1.0, fi = 0.0;
+                    if (jj < (1 << nl)) {
+                        for (size_t q : local_ops) {
+                            const LoweredGate& l = gs[q];
+                            const int tb = local_bit(l.tq), cb = local_bit(l.cq);
+                            if (l.cq >= 0 && !((jj >> cb) & 1)) continue;
+                            const int bit = (jj >> tb) & 1;
+                            const double dr = bit ? l.md[6] : l.md[0], di = bit ? l.md[7] : l.md[1];
+                            const double nr = fr * dr - fi * di;
+                            fi = fr * di + fi * dr;
+                            fr = nr;
+                        }
+                    }
+                    pool.push_back((float)fr);
+                    pool.push_back((float)fi);
+                }
+                table.push_back(d);
+            } else {
+                for (size_t q : local_ops) other_ops.push_back(q);
+            }
+            for (size_t q : other_ops) table.push_back(record(gs[q]));
+            k = e;
         }
         p.g1 = (int)table.size();
         passes.push_back(p);
@@ -498,8 +801,8 @@ qsim_status qsim_fsv_schedule(int n_qubits, const qsim_gate* gates, int n_gates,
         o.low_qubits = ps[i].L;
         o.n_high = ps[i].nh;
         for (int h = 0; h < QSIM_FSV_MAX_HIGH; ++h) o.high[h] = h < ps[i].nh ? ps[i].high[h] : -1;
-        o.first_op = ps[i].g0;
-        o.n_ops = ps[i].g1 - ps[i].g0;
+        o.first_op = ps[i].op0;
+        o.n_ops = ps[i].op1 - ps[i].op0;
     }
     return ok();
 }
@@ -520,7 +823,7 @@ qsim_status qsim_fsv_plan_create(qsim_ctx* ctx, int n_qubits, const qsim_gate* g
     std::vector<FsvGate> table;
     std::vector<float> pool;
     fsv_schedule(n_qubits, gs, plan->passes, table, pool);
-    plan->n_ops = (int)table.size();
+    plan->n_ops = (int)gs.size();
     if (!table.empty()) {
         DeviceGuard g(ctx->device);
         hipError_t e = g.err;
