@@ -6,7 +6,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from oracle import unitary as UA  # noqa: E402
+from oracle import fsv, unitary as UA  # noqa: E402
 from paper_2305_14398_amd import binding as B  # noqa: E402
 from paper_2305_14398_amd import workloads as W  # noqa: E402
 from tests import gpu_util as G  # noqa: E402
@@ -148,3 +148,20 @@ def test_large_circuits_batch_equals_single(ctx, prec):
         assert mx < (1e-3 if prec == B.QSIM_SPLIT_BF16 else 1e-5), (c.family, c.n, mx)
         del U, wss
     torch.cuda.empty_cache()
+
+
+def test_batch_with_custom_ops_matches_single_and_oracle(ctx):
+    """Registered custom operations (Section 5.2.2) inside a mixed batch: bit-identical to the single-circuit
+    chain and within the complex64 tolerance of the oracle."""
+    from types import SimpleNamespace
+    from tests.custom_ops import lib_gates
+    circuits, refs = [], []
+    for i, n in enumerate([3, 6, 7, 9, 11]):
+        g = W.with_custom_ops(W.gate_tuples(W.random_layers(n, 3, np.random.default_rng(i))), n, [2, 3, 6], 900 + i)
+        circuits.append(SimpleNamespace(n=n, gates=lib_gates(g), family="custom"))
+        refs.append(g)
+    (res,), _ = run_batch(ctx, circuits, B.QSIM_FP32_4M)
+    for c, g, U in zip(circuits, refs, res):
+        cols = W.random_columns(c.n, 8, 3)
+        assert np.abs(U[:, cols] - fsv.unitary_columns(c.n, g, cols)).max() <= 1e-5
+        np.testing.assert_array_equal(U, single(ctx, c, B.QSIM_FP32_4M))

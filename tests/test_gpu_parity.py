@@ -361,3 +361,32 @@ def test_chain_with_custom_ops(ctx, n):
             assert np.abs(U - ref).max() <= AMP_TOL
         cols = W.random_columns(n, 8, 5)
         assert np.abs(U[:, cols] - fsv.unitary_columns(n, g, cols)).max() <= AMP_TOL
+
+
+@pytest.mark.parametrize("prec", FP32_PRECS)
+def test_tree_of_step_products_equals_chain(ctx, prec):
+    """Association (a left fold and a pairwise tree of the same step operators) changes only rounding: both
+    GPU results match the oracle to the complex64 tolerance."""
+    n = 9
+    c = W.random_layers(n, 5, np.random.default_rng(19))
+    steps = UA.pack_steps(W.gate_tuples(c))
+    level = []
+    for st in steps:
+        S = G.planar(n)
+        B.qsim_build_step(ctx, n, st, B.QSIM_FP32_4M, B.QSIM_LAYOUT_ROW, S)
+        level.append(S)
+    while len(level) > 1:
+        nxt = []
+        for i in range(0, len(level) - 1, 2):
+            left = level[i + 1].transpose(1, 2).contiguous()  # the left operand is read column-major
+            out = G.planar(n)
+            B.qsim_step_multiply(ctx, n, prec, left, level[i], out)
+            nxt.append(out)
+        if len(level) % 2:
+            nxt.append(level[-1])
+        level = nxt
+    G.sync()
+    tree = G.to_complex(level[0])
+    chain = G.to_complex(gpu_chain(ctx, n, c.gates, prec))
+    ref = UA.circuit_unitary(n, W.gate_tuples(c))
+    assert np.abs(tree - ref).max() <= AMP_TOL and np.abs(chain - ref).max() <= AMP_TOL

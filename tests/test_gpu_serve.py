@@ -179,3 +179,17 @@ def test_policy_validation(ctx):
         B.qsim_serve_start(ctx, B.QSIM_FP32_4M, arena, policy=5)
     with pytest.raises(B.QsimError, match="budget"):
         B.qsim_serve_start(ctx, B.QSIM_FP32_4M, arena, policy=B.QSIM_POLICY_SHORTEST, iter_budget_tflop=0.0)
+
+
+def test_served_custom_ops_match_oracle(ctx):
+    from types import SimpleNamespace
+    from tests.custom_ops import lib_gates
+    circuits, refs = [], []
+    for i, n in enumerate([4, 8, 10]):
+        g = W.with_custom_ops(W.gate_tuples(W.random_layers(n, 3, np.random.default_rng(i))), n, [1, 4, 5], 950 + i)
+        circuits.append(SimpleNamespace(n=n, gates=lib_gates(g)))
+        refs.append(g)
+    out, _ = serve(ctx, circuits, B.QSIM_FP32_4M)
+    for c, g, (psi, res, _) in zip(circuits, refs, out):
+        assert res["status"] == B.QSIM_OK
+        assert np.abs(psi - fsv.final_state(c.n, g)).max() <= 1e-5

@@ -386,3 +386,19 @@ def test_custom_range_checks():
         UA.circuit_unitary(3, [("c", (0, 2), None, np.eye(4))])
     with pytest.raises(ValueError):
         fsv.circuit_unitary(3, [("c", (0, 1), None, np.eye(8))])
+
+
+def test_chain_association_left_fold_equals_tree():
+    """The product of the step operators is associative: Algorithm 1's left fold and a pairwise tree give the
+    same matrix (only rounding differs)."""
+    n = 6
+    steps = UA.pack_steps(W.gate_tuples(W.random_layers(n, 4, np.random.default_rng(12))))
+    ops = [UA.step_operator(n, st) for st in steps]
+    fold = UA.circuit_unitary(n, W.gate_tuples(W.random_layers(n, 4, np.random.default_rng(12))))
+    level = ops
+    while len(level) > 1:
+        nxt = [level[i + 1] @ level[i] for i in range(0, len(level) - 1, 2)]
+        if len(level) % 2:
+            nxt.append(level[-1])
+        level = nxt
+    np.testing.assert_allclose(level[0], fold, atol=1e-12)
