@@ -231,6 +231,62 @@ def bench_served_sweep(B, ctx, torch, rates, seconds: float, prec_name: str, are
             "throughput_bound_rate": round(capacity / mean_work, 2)}
 
 
+def bench_precision_sweep(B, ctx, torch, sizes, depth: int):
+    """Config 3: seeded random_layers(n, depth) chains at 12 and 13 qubits in every precision, timed, with the
+    product's roofline fraction and the float64 drift of each result; and the QFT chain at the same n in every
+    precision against its closed form U[j][k] = w^{jk}/sqrt(N) (max |dU| over sampled columns, and the fidelity of
+    U e_0 with the uniform state). No oracle is involved: random circuits are judged by drift, QFT by its formula."""
+    import numpy as np
+    from paper_2305_14398_amd import workloads as W
+    dev = torch.device("cuda:0")
+    out = {}
+    for n in sizes:
+        N = 1 << n
+        U = torch.empty((2, N, N), dtype=torch.float32, device=dev)
+        rand = W.random_layers(n, depth, np.random.default_rng(0))
+        qft = W.qft(n)
+        cols = W.random_columns(n, 16, 1)
+        w = np.exp(2j * np.pi / N)
+        closed = np.stack([w ** ((np.arange(N) * c) % N) for c in cols], axis=1) / math.sqrt(N)
+        for pname in ("fp32_4m", "fp32_3m", "split_bf16", "split_fp16"):
+            prec = B.PRECISIONS[pname]
+            ws = torch.empty(B.qsim_chain_workspace_bytes(n, prec), dtype=torch.uint8, device=dev)
+            B.qsim_unitary_chain(ctx, n, rand.gates, prec, U, ws)  # warm-up
+            torch.cuda.synchronize()
+            B.qsim_profile_enable(ctx, 1)
+            t0 = time.perf_counter()
+            B.qsim_unitary_chain(ctx, n, rand.gates, prec, U, ws)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            launches, kms = B.qsim_profile_read(ctx)["product"]
+            B.qsim_profile_enable(ctx, 0)
+            drift = B.qsim_unitarity_drift(ctx, n, U)
+            B.qsim_unitary_chain(ctx, n, qft.gates, prec, U, ws)
+            torch.cuda.synchronize()
+            Uc = U[:, :, cols].double().cpu().numpy()
+            Uc = Uc[0] + 1j * Uc[1]
+            col0 = U[:, :, 0].double().cpu().numpy()
+            psi = col0[0] + 1j * col0[1]
+            fid = abs(np.sum(psi) / math.sqrt(N)) ** 2 / float(np.sum(np.abs(psi) ** 2))
+            fl = flops_of(B, rand)
+            per = 8.0 * N ** 3 / (kms / max(launches, 1) * 1e-3) / 1e12
+            ceiling = PEAK_TFLOPS[pname] / ISSUED_PER_COUNTED[pname]
+            out[f"{n}q_{pname}"] = {
+                "chain_ms": round(wall * 1e3, 2), "products": launches, "chain_tflops": round(fl / wall / 1e12, 1),
+                "product_tflops": round(per, 1), "product_frac_of_ceiling": round(per / ceiling, 4),
+                "ceiling_tflops": round(ceiling, 1),
+                "random_drift_max": drift[0], "random_drift_fro": drift[1],
+                "qft_max_abs_dU_sampled": float(np.abs(Uc - closed).max()), "qft_state_fidelity": fid}
+            progress(f"precision sweep {n}q {pname}: {wall*1e3:.1f} ms, product {per:.1f} TFLOP/s, "
+                     f"qft |dU| {out[f'{n}q_{pname}']['qft_max_abs_dU_sampled']:.2e}")
+            del ws
+        del U
+        torch.cuda.empty_cache()
+    out["workload"] = (f"random_layers(n, {depth}, default_rng(0)) and qft(n) for n in {list(sizes)}; "
+                       "chain timing with HIP events per product; errors against closed forms and float64 drift")
+    return out
+
+
 def bench_fsv(B, ctx, torch, n: int, reps: int):
     """Full-state-vector path: qft(n) and random_layers(n, 20) from |0...0>, in place on a 2^n state.
     HBM roofline: every pass reads and writes the state once, 16 bytes per amplitude."""
@@ -333,6 +389,7 @@ def main() -> int:
     ap.add_argument("--served-rate", type=float, default=200.0)
     ap.add_argument("--served-prec", default="split_bf16", choices=sorted(PEAK_TFLOPS))
     ap.add_argument("--fsv", type=int, default=30, help="qubits of the full-state-vector workload (0: skip)")
+    ap.add_argument("--sweep-qubits", default="12,13", help="qubit counts of the precision sweep ('' to skip)")
     ap.add_argument("--served-sweep", default="", help="comma-separated Poisson rates for an offered-rate sweep")
     ap.add_argument("--served-sweep-seconds", type=float, default=10.0)
     ap.add_argument("--served-slo-ms", type=float, default=2500.0)
@@ -492,6 +549,9 @@ def main() -> int:
     if args.served:
         out["served"] = bench_served(B, ctx, torch, args.served, args.served_rate, 0, args.served_prec, 96)
         progress("served done")
+    if args.sweep_qubits:
+        out["precision_sweep"] = bench_precision_sweep(B, ctx, torch, [int(x) for x in args.sweep_qubits.split(",")], 20)
+        progress("precision sweep done")
     if args.served_sweep:
         rates = [float(x) for x in args.served_sweep.split(",") if x]
         out["served_sweep"] = bench_served_sweep(B, ctx, torch, rates, args.served_sweep_seconds, args.served_prec, 96,
