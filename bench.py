@@ -380,7 +380,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--prec", default="fp32_3m", choices=sorted(PEAK_TFLOPS))
-    ap.add_argument("--variant", default="fp32_4m", help="second precision timed on the same workload ('' to skip)")
+    ap.add_argument("--variant", default="fp32_4m,split_fp16,split_bf16",
+                    help="comma-separated further precisions timed on the same workload ('' to skip)")
     ap.add_argument("--qubits", type=int, default=11)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -471,7 +472,8 @@ def main() -> int:
 
     main = timed_run(args.prec, check=True)
     wall, gpu_ms, stats, results = main["wall"], main["gpu_ms"], main["stats"], main["checks"]
-    variant = timed_run(args.variant, check=False) if args.variant and args.variant != args.prec else None
+    variant_names = [v for v in args.variant.split(",") if v and v != args.prec]
+    variant_runs = [(v, timed_run(v, check=False)) for v in variant_names]
 
     ms_per_step = wall * 1e3 / args.steps
     tflops = flops_per_step * args.steps / wall / 1e12
@@ -528,15 +530,15 @@ def main() -> int:
             "unit": "GB/s",
         },
         "checks": results,
-        "variant": None if variant is None else {
-            "precision": args.variant,
-            "value": round(variant["tflops"], 3),
-            "ms_per_step": round(variant["wall"] * 1e3 / args.steps, 3),
-            "avg_product_ms": round(variant["avg_product_ms"], 5),
-            "product_tflops": round(8.0 * N ** 3 / (variant["avg_product_ms"] * 1e-3) / 1e12, 2),
-            "product_frac_of_ceiling": round(8.0 * N ** 3 / (variant["avg_product_ms"] * 1e-3) / 1e12 /
-                                             (PEAK_TFLOPS[args.variant] / ISSUED_PER_COUNTED[args.variant]), 4),
-        },
+        "variants": [{
+            "precision": v,
+            "value": round(r["tflops"], 3),
+            "ms_per_step": round(r["wall"] * 1e3 / args.steps, 3),
+            "avg_product_ms": round(r["avg_product_ms"], 5),
+            "product_tflops": round(8.0 * N ** 3 / (r["avg_product_ms"] * 1e-3) / 1e12, 2),
+            "product_frac_of_ceiling": round(8.0 * N ** 3 / (r["avg_product_ms"] * 1e-3) / 1e12 /
+                                             (PEAK_TFLOPS[v] / ISSUED_PER_COUNTED[v]), 4),
+        } for v, r in variant_runs],
         "paper_context": "TornadoQSim reports end-to-end speedups over single-threaded Java of 506.5x (fully "
                          "entangled), 493.10x (Deutsch-Jozsa) and 518.12x (QFT) at 11 qubits on a Quadro GP100; "
                          "different hardware, precision and baseline",
