@@ -419,6 +419,7 @@ def main() -> int:
     psi = torch.empty(2 * N, dtype=torch.float32, device=dev)
     prob = torch.empty(N, dtype=torch.float64, device=dev)
     records = [B.gate_array(c.gates) for c in circuits]
+    gate_lists = [[arr[i] for i in range(ng)] for arr, ng in records]
     ks = [len(B.qsim_pack_steps(n, c.gates)) - 1 for c in circuits]
     flops_per_step = sum(8.0 * N ** 3 * (k - 1) for k in ks)
 
@@ -435,10 +436,17 @@ def main() -> int:
         ws = torch.empty(B.qsim_chain_workspace_bytes(n, prec), dtype=torch.uint8, device=dev)
         results = {}
 
+        drift_dev = torch.empty((len(circuits), 2), dtype=torch.float64, device=dev)
+
         def one_step(check: bool = False):
-            for c, (arr, ng) in zip(circuits, records):
-                gates = [arr[i] for i in range(ng)]
+            # No host synchronisation inside a step: the float64 norm stays on the device and each drift result
+            # goes to its own device slot; the checking step reads them back.
+            for ci, (c, gates) in enumerate(zip(circuits, gate_lists)):
                 B.qsim_unitary_chain(ctx, n, gates, prec, U, ws)
+                if not check:
+                    B.qsim_apply_state(ctx, n, U, None, psi, prob, want_norm2=False)
+                    B.qsim_unitarity_drift_async(ctx, n, U, drift_dev[ci])
+                    continue
                 norm2 = B.qsim_apply_state(ctx, n, U, None, psi, prob)
                 drift = B.qsim_unitarity_drift(ctx, n, U)
                 if check:

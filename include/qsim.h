@@ -216,6 +216,11 @@ qsim_status qsim_sample(qsim_ctx* ctx, int n_qubits, const double* d_prob, const
  * float64 matrix is stored.  Synchronises the stream. */
 qsim_status qsim_unitarity_drift(qsim_ctx* ctx, int n_qubits, const void* d_U, double* h_out,
                                  void* stream);
+/* The same check without waiting: d_out (device memory, 2 doubles, 8-byte
+ * aligned) receives max |D_ij| and ||D||_F / sqrt(N) when the stream reaches
+ * it.  Uses the context's scratch for partial sums: calls on one context must
+ * not overlap on different streams. */
+qsim_status qsim_unitarity_drift_async(qsim_ctx* ctx, int n_qubits, const void* d_U, double* d_out, void* stream);
 
 /* Probe form of the drift check for serving: with the fixed unit vector
  * x_j = exp(2 pi i frac(j g)) / sqrt(N) (g = (sqrt 5 - 1) / 2), computes

@@ -140,6 +140,7 @@ def lib() -> ctypes.CDLL:
         "qsim_autotune": (i32, [vp, i32, i32, i32, ctypes.POINTER(dbl)]),
         "qsim_unitarity_drift_probe": (i32, [vp, i32, vp, ctypes.POINTER(dbl), vp]),
         "qsim_sample": (i32, [vp, i32, vp, vp, i32, vp, vp]),
+        "qsim_unitarity_drift_async": (i32, [vp, i32, vp, vp, vp]),
         "qsim_register_unitary": (i32, [ctypes.c_char_p, i32, ctypes.POINTER(dbl), ctypes.POINTER(i32)]),
         "qsim_find_unitary": (i32, [ctypes.c_char_p, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "qsim_fsv_schedule": (i32, [i32, vp, i32, ctypes.POINTER(qsim_fsv_pass_info), i32,
@@ -435,6 +436,12 @@ def qsim_tune_get(ctx, prec: int) -> list:
 
 def qsim_tune_set(ctx, prec: int, n_qubits: int, tile: int) -> None:
     _check(lib().qsim_tune_set(_h(ctx), prec, n_qubits, tile), "qsim_tune_set")
+
+
+def qsim_unitarity_drift_async(ctx, n_qubits: int, d_U, d_out, stream=None) -> None:
+    st = _stream(stream, _dev(ctx)) if _h(ctx) else None
+    _check(lib().qsim_unitarity_drift_async(_h(ctx), n_qubits, _ptr(d_U), _ptr(d_out), st),
+           "qsim_unitarity_drift_async")
 
 
 def qsim_unitarity_drift_probe(ctx, n_qubits: int, d_U, stream=None) -> tuple:

@@ -540,6 +540,23 @@ qsim_status qsim_unitarity_drift(qsim_ctx* ctx, int n_qubits, const void* d_U, d
     return ok();
 }
 
+qsim_status qsim_unitarity_drift_async(qsim_ctx* ctx, int n_qubits, const void* d_U, double* d_out, void* stream) {
+    qsim_status s = QSIM_OK;
+    if (!valid_n(n_qubits)) return fail(QSIM_E_RANGE, "n_qubits %d outside 1..%d", n_qubits, QSIM_MAX_QUBITS);
+    if (!d_U || !aligned(d_U)) return fail(QSIM_E_INVALID, "d_U is NULL or not 256-byte aligned");
+    if (!d_out || (reinterpret_cast<uintptr_t>(d_out) & 7u)) return fail(QSIM_E_INVALID, "d_out is NULL or unaligned");
+    s = check_ctx(ctx);
+    if (s != QSIM_OK) return s;
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return device_fail("hipSetDevice", g.err);
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    hipError_t e = timed(ctx->prof, QSIM_PROFILE_DRIFT, hs, [&] {
+        return launch_drift(n_qubits, static_cast<const float*>(d_U), ctx->d_scratch + 8, kDriftMaxPartials, d_out,
+                            hs);
+    });
+    return e == hipSuccess ? ok() : device_fail("drift launch", e);
+}
+
 qsim_status qsim_profile_enable(qsim_ctx* ctx, int enable) {
     if (ctx == nullptr) return fail(QSIM_E_INVALID, "context is NULL");
     DeviceGuard g(ctx->device);

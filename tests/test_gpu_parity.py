@@ -390,3 +390,12 @@ def test_tree_of_step_products_equals_chain(ctx, prec):
     chain = G.to_complex(gpu_chain(ctx, n, c.gates, prec))
     ref = UA.circuit_unitary(n, W.gate_tuples(c))
     assert np.abs(tree - ref).max() <= AMP_TOL and np.abs(chain - ref).max() <= AMP_TOL
+
+
+def test_drift_async_equals_synchronous(ctx):
+    n = 9
+    U = gpu_chain(ctx, n, W.random_layers(n, 3, np.random.default_rng(4)).gates)
+    out = torch.full((2,), float("nan"), dtype=torch.float64, device=G.DEV)
+    B.qsim_unitarity_drift_async(ctx, n, U, out)
+    G.sync()
+    assert tuple(out.cpu().tolist()) == B.qsim_unitarity_drift(ctx, n, U)
