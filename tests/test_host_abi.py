@@ -151,6 +151,8 @@ def test_multiply_apply_drift_validation_without_device():
     _expect(B.QSIM_E_INVALID, B.qsim_apply_state, None, 5, FAKE, FAKE * 2, FAKE * 2, None, match="aliases")
     _expect(B.QSIM_E_INVALID, B.qsim_apply_state, None, 5, FAKE, None, FAKE * 2 + 4, None, match="aligned")
     _expect(B.QSIM_E_RANGE, B.qsim_unitarity_drift, None, 17, FAKE)
+    _expect(B.QSIM_E_INVALID, B.qsim_unitarity_drift_async, None, 5, FAKE, FAKE + 4, match="d_out")
+    _expect(B.QSIM_E_INVALID, B.qsim_unitarity_drift_async, None, 5, FAKE, FAKE, match="context is NULL")
     _expect(B.QSIM_E_INVALID, B.qsim_unitarity_drift, None, 5, FAKE, match="context is NULL")
 
 
