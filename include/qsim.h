@@ -446,6 +446,20 @@ qsim_status qsim_fsv_init_basis(qsim_ctx* ctx, int n_qubits, int64_t basis, void
  * for the stream).  Uses the context's scratch: calls on one context must not
  * overlap on different streams. */
 qsim_status qsim_fsv_norm2(qsim_ctx* ctx, int n_qubits, const void* d_psi, double* h_norm2, void* stream);
+/* Measurement of a full state (the collapsing method, Section 5.2.3), with
+ * the rule of qsim_sample: shot k is the smallest index i with
+ * u_k * C[N-1] < C[i], C the float64 cumulative sum of |psi_i|^2 (it need
+ * not be normalised).  The distribution is not materialised: d_ws
+ * (qsim_fsv_sample_workspace_bytes(n) bytes, 256-byte aligned) holds the
+ * float64 prefix of the probability mass of consecutive blocks of 1024
+ * amplitudes; each shot searches that prefix, then its block.  d_uniform:
+ * `shots` float64 values in [0, 1) from the caller; d_out: `shots` int64.
+ * Asynchronous.  Within rounding of C (a different summation order than a
+ * sequential sum), a shot next to a boundary may take the neighbouring
+ * outcome. */
+size_t qsim_fsv_sample_workspace_bytes(int n_qubits);
+qsim_status qsim_fsv_sample(qsim_ctx* ctx, int n_qubits, const void* d_psi, const double* d_uniform, int shots,
+                            int64_t* d_out, void* d_ws, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

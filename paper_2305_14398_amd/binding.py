@@ -151,6 +151,8 @@ def lib() -> ctypes.CDLL:
         "qsim_fsv_run": (i32, [vp, vp, vp, vp]),
         "qsim_fsv_init_basis": (i32, [vp, i32, ctypes.c_int64, vp, vp]),
         "qsim_fsv_norm2": (i32, [vp, i32, vp, ctypes.POINTER(dbl), vp]),
+        "qsim_fsv_sample_workspace_bytes": (ctypes.c_size_t, [i32]),
+        "qsim_fsv_sample": (i32, [vp, i32, vp, vp, i32, vp, vp, ctypes.c_size_t, vp]),
         "qsim_serve_start": (i32, [vp, ctypes.POINTER(qsim_serve_config)]),
         "qsim_serve_stop": (i32, [vp]),
         "qsim_submit": (i32, [vp, ctypes.POINTER(qsim_request), ctypes.POINTER(ctypes.c_uint64)]),
@@ -577,3 +579,16 @@ def qsim_find_unitary(name: str):
     i, m = ctypes.c_int32(0), ctypes.c_int32(0)
     _check(lib().qsim_find_unitary(name.encode(), ctypes.byref(i), ctypes.byref(m)), "qsim_find_unitary")
     return i.value, m.value
+
+
+def qsim_fsv_sample_workspace_bytes(n_qubits: int) -> int:
+    return int(lib().qsim_fsv_sample_workspace_bytes(n_qubits))
+
+
+def qsim_fsv_sample(ctx, n_qubits: int, d_psi, d_uniform, shots: int, d_out, d_ws, ws_bytes=None,
+                    stream=None) -> None:
+    st = _stream(stream, _dev(ctx)) if _h(ctx) else None
+    if ws_bytes is None:
+        ws_bytes = d_ws.numel() * d_ws.element_size() if hasattr(d_ws, "numel") else 0
+    _check(lib().qsim_fsv_sample(_h(ctx), n_qubits, _ptr(d_psi), _ptr(d_uniform), shots, _ptr(d_out), _ptr(d_ws),
+                                 ws_bytes, st), "qsim_fsv_sample")

@@ -498,6 +498,127 @@ __global__ __launch_bounds__(256) void fsv_norm_partial(uint64_t N, const float*
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+// ---- measurement of a full state (the collapsing simulator method, Section 5.2.3) ----
+// The cumulative distribution is never stored: amplitudes are grouped in
+// blocks of 1024 (one wave each: lane l owns amplitudes 16l .. 16l+15 of the
+// block), and only the float64 block sums and their prefix are kept.  A shot
+// finds its block by binary search over the prefix, its lane by the same
+// in-wave scan that produced the block sum (so the two agree exactly), and its
+// amplitude by a sequential scan of the lane's 16 values.
+constexpr int kSampleBlock = 1024;
+
+__device__ __forceinline__ double lane_prob_sum(const float* __restrict__ re, const float* __restrict__ im, uint64_t N,
+                                                uint64_t first) {
+    double s = 0.0;
+    if (first + 16 <= N) {  // 64-byte aligned runs: vector loads, same summation order
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 a = *reinterpret_cast<const float4*>(re + first + 4 * q);
+            const float4 b = *reinterpret_cast<const float4*>(im + first + 4 * q);
+            s += (double)a.x * a.x + (double)b.x * b.x;
+            s += (double)a.y * a.y + (double)b.y * b.y;
+            s += (double)a.z * a.z + (double)b.z * b.z;
+            s += (double)a.w * a.w + (double)b.w * b.w;
+        }
+        return s;
+    }
+    for (int k = 0; k < 16; ++k) {
+        const uint64_t i = first + k;
+        if (i < N) {
+            const double a = re[i], b = im[i];
+            s += a * a + b * b;
+        }
+    }
+    return s;
+}
+
+// Inclusive scan over the 64 lanes in a fixed order (Hillis-Steele).
+__device__ __forceinline__ double wave_incl_scan(double v, int lane) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double u = __shfl_up(v, off, 64);
+        if (lane >= off) v += u;
+    }
+    return v;
+}
+
+// One wave per block: the block's probability mass.
+__global__ __launch_bounds__(256) void fsv_block_sums(uint64_t N, uint64_t nblocks, const float* __restrict__ re,
+                                                     const float* __restrict__ im, double* __restrict__ bsum) {
+    const uint64_t b = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (b >= nblocks) return;
+    const double v = wave_incl_scan(lane_prob_sum(re, im, N, b * kSampleBlock + 16 * lane), lane);
+    if (lane == 63) bsum[b] = v;
+}
+
+// In place: bsum[b] <- bsum[0] + ... + bsum[b], one 1024-thread block, fixed order
+// (each thread a contiguous chunk, chunk totals scanned, chunks re-summed from their offset).
+__global__ __launch_bounds__(1024) void fsv_block_prefix(uint64_t nblocks, double* __restrict__ bsum) {
+    __shared__ double tot[1024];
+    const uint64_t chunk = (nblocks + 1023) / 1024;
+    const uint64_t lo = (uint64_t)threadIdx.x * chunk;
+    const uint64_t hi = lo + chunk < nblocks ? lo + chunk : nblocks;
+    double s = 0.0;
+    for (uint64_t i = lo; i < hi; ++i) s += bsum[i];
+    tot[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const double v = (int)threadIdx.x >= off ? tot[threadIdx.x - off] : 0.0;
+        __syncthreads();
+        tot[threadIdx.x] += v;
+        __syncthreads();
+    }
+    double run = threadIdx.x ? tot[threadIdx.x - 1] : 0.0;
+    for (uint64_t i = lo; i < hi; ++i) {
+        run += bsum[i];
+        bsum[i] = run;
+    }
+}
+
+// One wave per shot.
+__global__ __launch_bounds__(256) void fsv_sample_kernel(uint64_t N, uint64_t nblocks, const float* __restrict__ re,
+                                                        const float* __restrict__ im, const double* __restrict__ pre,
+                                                        const double* __restrict__ u, int shots,
+                                                        int64_t* __restrict__ out) {
+    const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (k >= shots) return;
+    const double target = u[k] * pre[nblocks - 1];
+    // smallest block b with target < pre[b]
+    uint64_t lo = 0, hi = nblocks - 1;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (pre[mid] > target)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    const uint64_t b = lo;
+    const double base = b ? pre[b - 1] : 0.0;
+    const uint64_t first = b * kSampleBlock + 16 * lane;
+    const double L = wave_incl_scan(lane_prob_sum(re, im, N, first), lane);
+    const double Lprev = __shfl_up(L, 1, 64);
+    // first lane whose chunk ends above the target
+    const unsigned long long hit = __ballot(target < base + L);
+    const int l = hit ? __ffsll(hit) - 1 : 63;
+    if (lane == l) {
+        double c = base + (lane ? Lprev : 0.0);
+        uint64_t pick = first + 15 < N ? first + 15 : N - 1;
+        for (int j = 0; j < 16; ++j) {
+            const uint64_t i = first + j;
+            if (i >= N) break;
+            const double a = re[i], bb = im[i];
+            c += a * a + bb * bb;
+            if (target < c) {
+                pick = i;
+                break;
+            }
+        }
+        out[k] = (int64_t)pick;
+    }
+}
+
 __global__ __launch_bounds__(256) void fsv_norm_final(int parts, const double* __restrict__ part,
                                                      double* __restrict__ out) {
     __shared__ double red[256];
@@ -907,6 +1028,46 @@ qsim_status qsim_fsv_init_basis(qsim_ctx* ctx, int n_qubits, int64_t basis, void
                        static_cast<float4*>(d_psi));
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? ok() : device_fail("basis-state launch", e);
+}
+
+size_t qsim_fsv_sample_workspace_bytes(int n_qubits) {
+    if (n_qubits < 1 || n_qubits > QSIM_FSV_MAX_QUBITS) return 0;
+    const uint64_t N = (uint64_t)1 << n_qubits;
+    return (size_t)(((N + kSampleBlock - 1) / kSampleBlock) * sizeof(double));
+}
+
+qsim_status qsim_fsv_sample(qsim_ctx* ctx, int n_qubits, const void* d_psi, const double* d_uniform, int shots,
+                            int64_t* d_out, void* d_ws, size_t ws_bytes, void* stream) {
+    if (n_qubits < 1 || n_qubits > QSIM_FSV_MAX_QUBITS)
+        return fail(QSIM_E_RANGE, "n_qubits %d outside 1..%d", n_qubits, QSIM_FSV_MAX_QUBITS);
+    if (shots < 0) return fail(QSIM_E_INVALID, "negative shot count");
+    if (d_psi == nullptr || !aligned(d_psi)) return fail(QSIM_E_INVALID, "d_psi is NULL or not 256-byte aligned");
+    if (shots > 0 && (!d_uniform || !d_out || !aligned(d_uniform) || !aligned(d_out)))
+        return fail(QSIM_E_INVALID, "d_uniform / d_out is NULL or not 256-byte aligned");
+    const size_t need = qsim_fsv_sample_workspace_bytes(n_qubits);
+    if (d_ws == nullptr || !aligned(d_ws)) return fail(QSIM_E_INVALID, "d_ws is NULL or not 256-byte aligned");
+    if (ws_bytes < need) return fail(QSIM_E_RANGE, "workspace %zu bytes, need %zu", ws_bytes, need);
+    qsim_status s = check_ctx(ctx);
+    if (s != QSIM_OK) return s;
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return device_fail("hipSetDevice", g.err);
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const uint64_t N = (uint64_t)1 << n_qubits;
+    const uint64_t nb = (N + kSampleBlock - 1) / kSampleBlock;
+    const float* re = static_cast<const float*>(d_psi);
+    double* pre = static_cast<double*>(d_ws);
+    hipLaunchKernelGGL(fsv_block_sums, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, hs, N, nb, re, re + N, pre);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(fsv_block_prefix, dim3(1), dim3(1024), 0, hs, nb, pre);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && shots > 0) {
+        hipLaunchKernelGGL(fsv_sample_kernel, dim3((unsigned)((shots + 3) / 4)), dim3(256), 0, hs, N, nb, re, re + N,
+                           pre, d_uniform, shots, d_out);
+        e = hipGetLastError();
+    }
+    return e == hipSuccess ? ok() : device_fail("full-state sampling launch", e);
 }
 
 qsim_status qsim_fsv_norm2(qsim_ctx* ctx, int n_qubits, const void* d_psi, double* h_norm2, void* stream) {

@@ -124,3 +124,59 @@ def test_sampler_validation(ctx):
         B.qsim_sample(ctx, 3, p, None, 4, out)
     with pytest.raises(B.QsimError):
         B.qsim_sample(ctx, 17, p, u, 4, out)
+
+
+# --- full-state measurement (qsim_fsv_sample) -----------------------------------------------
+
+def fsv_sample(ctx, n, psi_dev, u):
+    shots = len(u)
+    d_u = torch.as_tensor(np.asarray(u, dtype=np.float64), device=DEV) if shots else None
+    d_out = torch.full((max(shots, 1),), -1, dtype=torch.int64, device=DEV)
+    ws = G.workspace(B.qsim_fsv_sample_workspace_bytes(n))
+    B.qsim_fsv_sample(ctx, n, psi_dev, d_u, shots, d_out if shots else None, ws)
+    G.sync()
+    return d_out[:shots].cpu().numpy()
+
+
+@pytest.mark.parametrize("n,shots", [(1, 9), (3, 500), (9, 0), (10, 4000), (12, 20000), (17, 50000)])
+def test_fsv_sample_matches_oracle(ctx, n, shots):
+    rng = np.random.default_rng(40 + n)
+    v = W.random_state(n, n) * rng.random(1 << n) ** 3
+    v[rng.random(1 << n) < 0.25] = 0.0
+    psi = G.planar_vec(v)
+    p = np.abs(G.vec_to_complex(psi)) ** 2  # the float32 state's own probabilities
+    u = rng.random(shots)
+    got = fsv_sample(ctx, n, psi, u)
+    assert got.shape == (shots,)
+    assert_same_outcomes(got, p, u)
+    if shots:
+        assert np.all(p[got] > 0)
+
+
+def test_fsv_sample_ghz_and_uniform_28(ctx):
+    n = 28
+    N = 1 << n
+    rng = np.random.default_rng(28)
+    u = rng.random(100000)
+    psi = torch.empty(2 * N, dtype=torch.float32, device=DEV)
+    B.qsim_fsv_init_basis(ctx, n, 0, psi)
+    with B.FsvPlan(ctx, n, W.gate_tuples(W.ghz_fanout(n))) as plan:
+        plan.run(psi)
+    shots = fsv_sample(ctx, n, psi, u)
+    assert set(np.unique(shots)) <= {0, N - 1}
+    assert 0.49 < np.mean(shots == 0) < 0.51
+    # H on every qubit: the uniform distribution, so shot = floor(u N) up to float32 rounding of 1/N
+    B.qsim_fsv_init_basis(ctx, n, 0, psi)
+    with B.FsvPlan(ctx, n, [("H", (q,), None) for q in range(n)]) as plan:
+        plan.run(psi)
+    shots = fsv_sample(ctx, n, psi, u)
+    assert np.max(np.abs(shots - np.floor(u * N).astype(np.int64))) <= 1
+
+
+def test_fsv_sample_validation(ctx):
+    psi = torch.zeros(64, dtype=torch.float32, device=DEV)
+    ws = G.workspace(B.qsim_fsv_sample_workspace_bytes(5))
+    with pytest.raises(B.QsimError, match="negative"):
+        B.qsim_fsv_sample(ctx, 5, psi, None, -1, None, ws)
+    with pytest.raises(B.QsimError, match="workspace"):
+        B.qsim_fsv_sample(ctx, 20, psi, None, 0, None, ws, 8)
