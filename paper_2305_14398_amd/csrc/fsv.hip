@@ -36,6 +36,7 @@
 // Gate entries are the float64 matrices of the unitary path rounded once to
 // float32; amplitude arithmetic is float32 with fused multiply-adds.
 #include <algorithm>
+#include <utility>
 #include <vector>
 
 #include "host.h"
@@ -49,6 +50,18 @@ constexpr int kFsvNormBlocks = 1024;
 constexpr int kFsvMaxOps = 256;   // operations per pass, staged in LDS (16 KiB)
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Calls f(std::integral_constant<int, r>) for r = 0..15: every register index
+// is a compile-time constant from the start, so the amplitude vectors never
+// need an addressable (scratch) copy.
+template <class F, int... Rs>
+__device__ __forceinline__ void fsv_for16_impl(F&& f, std::integer_sequence<int, Rs...>) {
+    (f(std::integral_constant<int, Rs>{}), ...);
+}
+template <class F>
+__device__ __forceinline__ void fsv_for16(F&& f) {
+    fsv_for16_impl(f, std::make_integer_sequence<int, 16>{});
+}
 
 enum : int32_t { FSV_GENERAL = 0, FSV_DIAG = 1, FSV_DENSE = 2, FSV_TABLE = 3 };
 
@@ -107,19 +120,26 @@ __device__ __forceinline__ void cmul_at(f32x16& ar, f32x16& ai, int r, float fr,
     ai[r] = fmaf(fr, xi, fi * xr);
 }
 
+// A 2x2 complex matrix in scalars (row-major (re, im)), so that it lives in
+// registers whatever the control flow around it.
+struct Mat2 {
+    float m0r, m0i, m1r, m1i, m2r, m2i, m3r, m3i;
+};
+
 // Non-diagonal 2x2 on register bit RB.  CP = register bit of the control
-// (compile time), or -1 (no control, or a control on a lane index bit,
-// applied by a whole-register select).  REAL:
+// (compile time), or -1 (no control, or a control on a lane index bit: lanes
+// whose control bit is 0 multiply by the identity).  REAL:
 // every entry is real (H, X, RY, CNOT), half the multiply-adds.
 template <int RB, int CP, bool REAL>
-__device__ __forceinline__ void fsv_general(f32x16& ar, f32x16& ai, const FsvGate& g) {
-    const float m0r = g.m[0], m0i = g.m[1], m1r = g.m[2], m1i = g.m[3];
-    const float m2r = g.m[4], m2i = g.m[5], m3r = g.m[6], m3i = g.m[7];
-#pragma clang loop unroll(full)
-    for (int r0 = 0; r0 < 16; ++r0) {
-        if ((r0 >> RB) & 1) continue;
+__device__ __forceinline__ void fsv_general(f32x16& ar_out, f32x16& ai_out, const Mat2 M) {
+    f32x16 ar = ar_out, ai = ai_out;  // value copies: the caller sees whole-vector accesses only
+    const float m0r = M.m0r, m0i = M.m0i, m1r = M.m1r, m1i = M.m1i;
+    const float m2r = M.m2r, m2i = M.m2i, m3r = M.m3r, m3i = M.m3i;
+    fsv_for16([&](auto I_) {
+        constexpr int r0 = decltype(I_)::value;
+        if ((r0 >> RB) & 1) return;
         if constexpr (CP >= 0) {
-            if (!((r0 >> CP) & 1)) continue;
+            if (!((r0 >> CP) & 1)) return;
         }
         const int r1 = r0 | (1 << RB);
         const float x0r = ar[r0], x0i = ai[r0], x1r = ar[r1], x1i = ai[r1];
@@ -139,78 +159,97 @@ __device__ __forceinline__ void fsv_general(f32x16& ar, f32x16& ai, const FsvGat
         ai[r0] = y0i;
         ar[r1] = y1r;
         ai[r1] = y1i;
-    }
+    });
+    ar_out = ar;
+    ai_out = ai;
 }
 
 template <int RB, bool REAL>
-__device__ __forceinline__ void fsv_general_cp(f32x16& ar, f32x16& ai, const FsvGate& g, int cp, bool lane_ctrl,
+__device__ __forceinline__ void fsv_general_cp(f32x16& ar, f32x16& ai, const Mat2 M, int cp, bool lane_ctrl,
                                                bool lane_on) {
     switch (cp) {
-        case 0: if constexpr (RB != 0) fsv_general<RB, 0, REAL>(ar, ai, g); break;
-        case 1: if constexpr (RB != 1) fsv_general<RB, 1, REAL>(ar, ai, g); break;
-        case 2: if constexpr (RB != 2) fsv_general<RB, 2, REAL>(ar, ai, g); break;
-        case 3: if constexpr (RB != 3) fsv_general<RB, 3, REAL>(ar, ai, g); break;
+        case 0: if constexpr (RB != 0) fsv_general<RB, 0, REAL>(ar, ai, M); break;
+        case 1: if constexpr (RB != 1) fsv_general<RB, 1, REAL>(ar, ai, M); break;
+        case 2: if constexpr (RB != 2) fsv_general<RB, 2, REAL>(ar, ai, M); break;
+        case 3: if constexpr (RB != 3) fsv_general<RB, 3, REAL>(ar, ai, M); break;
         default:
-            // a control on one of the lane's index bits selects per lane
             if (lane_ctrl) {
-                f32x16 br = ar, bi = ai;
-                fsv_general<RB, -1, REAL>(br, bi, g);
-                ar = lane_on ? br : ar;
-                ai = lane_on ? bi : ai;
+                // a control on one of the lane's index bits: lanes where it is 0
+                // apply the identity (exact: products with 1 and 0)
+                Mat2 L = M;
+                L.m0r = lane_on ? M.m0r : 1.f;
+                L.m0i = lane_on ? M.m0i : 0.f;
+                L.m1r = lane_on ? M.m1r : 0.f;
+                L.m1i = lane_on ? M.m1i : 0.f;
+                L.m2r = lane_on ? M.m2r : 0.f;
+                L.m2i = lane_on ? M.m2i : 0.f;
+                L.m3r = lane_on ? M.m3r : 1.f;
+                L.m3i = lane_on ? M.m3i : 0.f;
+                fsv_general<RB, -1, REAL>(ar, ai, L);
             } else {
-                fsv_general<RB, -1, REAL>(ar, ai, g);
+                fsv_general<RB, -1, REAL>(ar, ai, M);
             }
             break;
     }
 }
 
 template <int RB>
-__device__ __forceinline__ void fsv_general_rb(f32x16& ar, f32x16& ai, const FsvGate& g, int cp,
+__device__ __forceinline__ void fsv_general_rb(f32x16& ar, f32x16& ai, const Mat2 M, bool real, int cp,
                                                bool lane_ctrl, bool lane_on) {
-    if (g.real)
-        fsv_general_cp<RB, true>(ar, ai, g, cp, lane_ctrl, lane_on);
+    if (real)
+        fsv_general_cp<RB, true>(ar, ai, M, cp, lane_ctrl, lane_on);
     else
-        fsv_general_cp<RB, false>(ar, ai, g, cp, lane_ctrl, lane_on);
+        fsv_general_cp<RB, false>(ar, ai, M, cp, lane_ctrl, lane_on);
 }
 
 // A run of diagonal operations on local qubits, multiplied out on the host:
 // amplitude j (local index) times tab[j].
-__device__ __forceinline__ void fsv_table(f32x16& ar, f32x16& ai, const float* __restrict__ tab, int jt, int sh) {
-#pragma clang loop unroll(full)
-    for (int r = 0; r < 16; ++r) {
+__device__ __forceinline__ void fsv_table(f32x16& ar_out, f32x16& ai_out, const float* __restrict__ tab, int jt,
+                                          int sh) {
+    f32x16 ar = ar_out, ai = ai_out;  // value copies: the caller sees whole-vector accesses only
+    fsv_for16([&](auto I_) {
+        constexpr int r = decltype(I_)::value;
         const int j = jt | (r << sh);
         const float2 f = *reinterpret_cast<const float2*>(tab + 2 * j);
         cmul_at(ar, ai, r, f.x, f.y);
-    }
+    });
+    ar_out = ar;
+    ai_out = ai;
 }
 
 // Registers whose bit P is set (or all, P < 0) times the per-lane factor f.
 template <int P>
-__device__ __forceinline__ void fsv_scale(f32x16& ar, f32x16& ai, float fr, float fi) {
-#pragma clang loop unroll(full)
-    for (int r = 0; r < 16; ++r) {
+__device__ __forceinline__ void fsv_scale(f32x16& ar_out, f32x16& ai_out, float fr, float fi) {
+    f32x16 ar = ar_out, ai = ai_out;  // value copies: the caller sees whole-vector accesses only
+    fsv_for16([&](auto I_) {
+        constexpr int r = decltype(I_)::value;
         if constexpr (P >= 0) {
-            if (!((r >> P) & 1)) continue;
+            if (!((r >> P) & 1)) return;
         }
         cmul_at(ar, ai, r, fr, fi);
-    }
+    });
+    ar_out = ar;
+    ai_out = ai;
 }
 
 // Registers with bit CP set (all if CP < 0) times d1 where bit TP is set, else d0
 // (d0 skipped when it is exactly 1).
 template <int TP, int CP>
-__device__ __forceinline__ void fsv_diag_reg(f32x16& ar, f32x16& ai, float d0r, float d0i, float d1r,
+__device__ __forceinline__ void fsv_diag_reg(f32x16& ar_out, f32x16& ai_out, float d0r, float d0i, float d1r,
                                              float d1i, bool d0_one) {
-#pragma clang loop unroll(full)
-    for (int r = 0; r < 16; ++r) {
+    f32x16 ar = ar_out, ai = ai_out;  // value copies: the caller sees whole-vector accesses only
+    fsv_for16([&](auto I_) {
+        constexpr int r = decltype(I_)::value;
         if constexpr (CP >= 0) {
-            if (!((r >> CP) & 1)) continue;
+            if (!((r >> CP) & 1)) return;
         }
         if ((r >> TP) & 1)
             cmul_at(ar, ai, r, d1r, d1i);
         else if (!d0_one)
             cmul_at(ar, ai, r, d0r, d0i);
-    }
+    });
+    ar_out = ar;
+    ai_out = ai;
 }
 
 __device__ __forceinline__ void fsv_flush(f32x16& ar, f32x16& ai, float& lpr, float& lpi, bool& pending) {
@@ -236,22 +275,23 @@ __device__ __forceinline__ void fsv_diag_tp(f32x16& ar, f32x16& ai, int cp, floa
 
 // A dense operation on local bits lb .. lb+w-1: out[j] = sum_s M[row(j)][s] in[j with
 // those bits = s], through LDS; the register layout is unchanged.
-__device__ __forceinline__ void fsv_dense(f32x16& ar, f32x16& ai, int t, int cur, const FsvGate& g,
+__device__ __forceinline__ void fsv_dense(f32x16& ar_out, f32x16& ai_out, int t, int cur, const FsvGate& g,
                                           const float* __restrict__ pool, float* s_re, float* s_im) {
+    f32x16 ar = ar_out, ai = ai_out;  // value copies: the caller sees whole-vector accesses only
     __syncthreads();
     const int jt = fsv_thread_bits(t, cur), sh = 4 * cur;
-#pragma clang loop unroll(full)
-    for (int r = 0; r < 16; ++r) {
+    fsv_for16([&](auto I_) {
+        constexpr int r = decltype(I_)::value;
         const int a = fsv_swz(jt | (r << sh));
         s_re[a] = ar[r];
         s_im[a] = ai[r];
-    }
+    });
     __syncthreads();
     const int lb = g.tloc, W = 1 << g.width;
     const int field = (W - 1) << lb;
     const float* M = pool + g.moff;
-#pragma clang loop unroll(full)
-    for (int r = 0; r < 16; ++r) {
+    fsv_for16([&](auto I_) {
+        constexpr int r = decltype(I_)::value;
         const int j = jt | (r << sh);
         const int row = (j >> lb) & (W - 1);
         const int rest = j & ~field;
@@ -266,28 +306,33 @@ __device__ __forceinline__ void fsv_dense(f32x16& ar, f32x16& ai, int t, int cur
         }
         ar[r] = yr;
         ai[r] = yi;
-    }
+    });
+    ar_out = ar;
+    ai_out = ai;
 }
 
 // Layout change cur -> k through LDS.
-__device__ __forceinline__ void fsv_relayout(f32x16& ar, f32x16& ai, int t, int cur, int k, float* s_re,
+__device__ __forceinline__ void fsv_relayout(f32x16& ar_out, f32x16& ai_out, int t, int cur, int k, float* s_re,
                                              float* s_im) {
+    f32x16 ar = ar_out, ai = ai_out;  // value copies: the caller sees whole-vector accesses only
     __syncthreads();  // earlier readers of the buffer are done
     const int jt = fsv_thread_bits(t, cur), sh = 4 * cur;
-#pragma clang loop unroll(full)
-    for (int r = 0; r < 16; ++r) {
+    fsv_for16([&](auto I_) {
+        constexpr int r = decltype(I_)::value;
         const int a = fsv_swz(jt | (r << sh));
         s_re[a] = ar[r];
         s_im[a] = ai[r];
-    }
+    });
     __syncthreads();
     const int jn = fsv_thread_bits(t, k), shn = 4 * k;
-#pragma clang loop unroll(full)
-    for (int r = 0; r < 16; ++r) {
+    fsv_for16([&](auto I_) {
+        constexpr int r = decltype(I_)::value;
         const int a = fsv_swz(jn | (r << shn));
         ar[r] = s_re[a];
         ai[r] = s_im[a];
-    }
+    });
+    ar_out = ar;
+    ai_out = ai;
 }
 
 __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const FsvGate* __restrict__ gates,
@@ -322,21 +367,21 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
     const int nloc = full ? (1 << kFsvLocal) : (1 << n);
 
     f32x16 ar, ai;
-#pragma clang loop unroll(full)
-    for (int r = 0; r < 16; ++r) {
+    fsv_for16([&](auto I_) {
+        constexpr int r = decltype(I_)::value;
         const int j = t | (r << 8);
         uint64_t g = base | gt;
 #pragma unroll
         for (int b = 0; b < 4; ++b)
             if ((r >> b) & 1) g |= gh[b];
-        if (j < nloc) {
-            ar[r] = re[g];
-            ai[r] = im[g];
-        } else {
-            ar[r] = 0.f;
-            ai[r] = 0.f;
+        float vr = 0.f, vi = 0.f;  // loaded into scalars: a conditional vector-element write would go to scratch
+        if (full || j < nloc) {
+            vr = re[g];
+            vi = im[g];
         }
-    }
+        ar[r] = vr;
+        ai[r] = vi;
+    });
 
     // Diagonal factors that depend only on this lane's index bits (and the
     // workgroup's) are gathered into one per-lane phase and applied to all 16
@@ -402,11 +447,13 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
             }
         }
         if (g.kind == FSV_GENERAL) {
+            const Mat2 M = {g.m[0], g.m[1], g.m[2], g.m[3], g.m[4], g.m[5], g.m[6], g.m[7]};
+            const bool real = g.real != 0;
             switch (g.tloc & 3) {
-                case 0: fsv_general_rb<0>(ar, ai, g, cp, lane_ctrl, lane_on); break;
-                case 1: fsv_general_rb<1>(ar, ai, g, cp, lane_ctrl, lane_on); break;
-                case 2: fsv_general_rb<2>(ar, ai, g, cp, lane_ctrl, lane_on); break;
-                default: fsv_general_rb<3>(ar, ai, g, cp, lane_ctrl, lane_on); break;
+                case 0: fsv_general_rb<0>(ar, ai, M, real, cp, lane_ctrl, lane_on); break;
+                case 1: fsv_general_rb<1>(ar, ai, M, real, cp, lane_ctrl, lane_on); break;
+                case 2: fsv_general_rb<2>(ar, ai, M, real, cp, lane_ctrl, lane_on); break;
+                default: fsv_general_rb<3>(ar, ai, M, real, cp, lane_ctrl, lane_on); break;
             }
             continue;
         }
@@ -451,18 +498,19 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
     fsv_flush(ar, ai, lpr, lpi, lp_pending);
     if (cur != 2) fsv_relayout(ar, ai, t, cur, 2, s_re, s_im);
 
-#pragma clang loop unroll(full)
-    for (int r = 0; r < 16; ++r) {
+    fsv_for16([&](auto I_) {
+        constexpr int r = decltype(I_)::value;
         const int j = t | (r << 8);
         uint64_t g = base | gt;
 #pragma unroll
         for (int b = 0; b < 4; ++b)
             if ((r >> b) & 1) g |= gh[b];
-        if (j < nloc) {
-            re[g] = ar[r];
-            im[g] = ai[r];
+        const float vr = ar[r], vi = ai[r];
+        if (full || j < nloc) {
+            re[g] = vr;
+            im[g] = vi;
         }
-    }
+    });
 }
 
 // |basis> in planar complex64, written as float4 (2N floats, N >= 2).
