@@ -364,6 +364,18 @@ def cpu_baseline(n: int, budget_s: float):
             break
     dt = time.perf_counter() - t0
     threads = max([p.get("num_threads", 1) for p in threadpool_info() if p.get("internal_api") == "openblas"] or [1])
+    # one BLAS thread: the analogue of the paper's single-threaded baseline, on a few products
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        t1 = time.perf_counter()
+        r1 = np.eye(N, dtype=np.complex128)
+        single = 0
+        for st in steps:
+            r1 = UA.step_operator(n, st) @ r1
+            single += 1
+            if time.perf_counter() - t1 > budget_s / 3 and single >= 1:
+                break
+        dt1 = time.perf_counter() - t1
     return {
         "value": 8.0 * N ** 3 * products / dt / 1e12,
         "unit": "TFLOP/s",
@@ -371,6 +383,8 @@ def cpu_baseline(n: int, budget_s: float):
         "kind": "oracle",
         "sample": f"route A (dense step + complex128 matmul) over the first {products} of {len(steps)} steps of "
                   f"qft({n}); {dt:.1f} s; {os.cpu_count()} host CPUs visible",
+        "single_thread": {"value": 8.0 * N ** 3 * single / dt1 / 1e12, "unit": "TFLOP/s", "cores": 1,
+                          "sample": f"the first {single} steps of qft({n}) with one BLAS thread; {dt1:.1f} s"},
     }
 
 
@@ -551,6 +565,25 @@ def main() -> int:
                          "entangled), 493.10x (Deutsch-Jozsa) and 518.12x (QFT) at 11 qubits on a Quadro GP100; "
                          "different hardware, precision and baseline",
     }
+    # The same steps with every final state copied to pinned host memory (the paper's end-to-end timing includes
+    # the transfers; here gates travel as kernel arguments and the state is the only bulk transfer).
+    host_psi = torch.empty(2 * N, dtype=torch.float32, pin_memory=True)
+    prec_main = B.PRECISIONS[args.prec]
+    ws_main = torch.empty(B.qsim_chain_workspace_bytes(n, prec_main), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for gates in gate_lists:
+            B.qsim_unitary_chain(ctx, n, gates, prec_main, U, ws_main)
+            B.qsim_apply_state(ctx, n, U, None, psi, prob, want_norm2=False)
+            host_psi.copy_(psi, non_blocking=True)
+    torch.cuda.synchronize()
+    e2e = time.perf_counter() - t0
+    out["e2e_with_state_readback"] = {
+        "circuits_per_s": round(len(circuits) * args.steps / e2e, 3),
+        "ms_per_circuit": round(e2e * 1e3 / (len(circuits) * args.steps), 3),
+        "note": "expand + chain + apply + float64 norm, each state copied to pinned host memory (no drift check)"}
+    del ws_main
     progress(f"headline done: {tflops:.1f} TFLOP/s")
     if args.batched:
         out["batched"] = bench_batched(B, ctx, torch, args.batched, 0, "fp32_4m" if args.prec == "fp32_4m"
