@@ -31,6 +31,11 @@ __device__ __forceinline__ void step_entry(const DevStep& st, uint32_t r, uint32
                                            double& out_im) {
     double pr = 1.0, pi = 0.0;
     bool zero = ((r ^ s) & st.idle_mask) != 0;
+    if (zero) {  // most entries of a sparse step: no gate factor is needed
+        out_re = 0.0;
+        out_im = 0.0;
+        return;
+    }
     for (int g = 0; g < st.n_gates; ++g) {
         const int type = st.g[g].type;
         const int q0 = st.g[g].q0, q1 = st.g[g].q1;
