@@ -138,12 +138,16 @@ def replay_trace(B, ctx, torch, trace, prec: int, mode: int, arena, max_active: 
     th = threading.Thread(target=submitter)
     th.start()
     results = {}
+    last_note = time.monotonic()
     while len(results) < len(trace):
         for i in range(len(trace)):
             if ids[i] is not None and i not in results:
                 r = B.qsim_poll(ctx, ids[i])
                 if r is not None:
                     results[i] = r
+        if time.monotonic() - last_note > 30.0:
+            progress(f"  served {len(results)}/{len(trace)} requests")
+            last_note = time.monotonic()
         time.sleep(0.0005)
     th.join()
     stats = B.qsim_serve_get_stats(ctx)
