@@ -246,3 +246,27 @@ def test_fsv_custom_dft_on_high_qubits_equals_qft_gates(ctx):
     x, _ = run_fsv(ctx, n, lib_gates(pre + [("dft4_on_20", (20, 21, 22, 23), None, dft)]), psi0)
     y, _ = run_fsv(ctx, n, pre + qft_gates, psi0)
     assert np.linalg.norm(x - y) <= custom_bound(pre + [("d", (20, 21, 22, 23), None, dft)]) + bound(pre + qft_gates)
+
+
+def test_fsv_ghz_34_maximum_size(ctx):
+    """The largest register the full-state path takes: 34 qubits, a 128 GiB state (GHZ, Section 2.5), with
+    measurement by sampling on top (every shot is 0 or N-1)."""
+    n = B.QSIM_FSV_MAX_QUBITS
+    N = 1 << n
+    psi = torch.empty(2 * N, dtype=torch.float32, device=G.DEV)
+    B.qsim_fsv_init_basis(ctx, n, 0, psi)
+    with B.FsvPlan(ctx, n, W.gate_tuples(W.ghz_fanout(n))) as plan:
+        plan.run(psi)
+        G.sync()
+    r = 1 / math.sqrt(2)
+    ends = psi[torch.tensor([0, N - 1, N, 2 * N - 1], device=G.DEV)].cpu().numpy()
+    assert abs(ends[0] - r) <= 1e-7 and abs(ends[1] - r) <= 1e-7 and ends[2] == 0 and ends[3] == 0
+    assert abs(B.qsim_fsv_norm2(ctx, n, psi) - 2 * float(ends[0]) * float(ends[0])) <= 1e-6
+    u = torch.rand(4096, dtype=torch.float64, generator=torch.Generator().manual_seed(3)).to(G.DEV)
+    out = torch.empty(4096, dtype=torch.int64, device=G.DEV)
+    ws = G.workspace(B.qsim_fsv_sample_workspace_bytes(n))
+    B.qsim_fsv_sample(ctx, n, psi, u, 4096, out, ws)
+    shots = out.cpu().numpy()
+    assert set(np.unique(shots)) <= {0, N - 1}
+    del psi
+    torch.cuda.empty_cache()
