@@ -380,9 +380,19 @@ def cpu_baseline(n: int, budget_s: float):
             if time.perf_counter() - t1 > budget_s / 3 and single >= 1:
                 break
         dt1 = time.perf_counter() - t1
+    cpu_model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    blas = [f"{p.get('internal_api')} {p.get('version')}" for p in threadpool_info() if p.get("user_api") == "blas"]
     return {
         "value": 8.0 * N ** 3 * products / dt / 1e12,
         "unit": "TFLOP/s",
+        "host": {"cpu_model": cpu_model, "cpus_visible": os.cpu_count(), "blas": blas},
         "cores": int(threads),
         "kind": "oracle",
         "sample": f"route A (dense step + complex128 matmul) over the first {products} of {len(steps)} steps of "
