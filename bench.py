@@ -115,13 +115,13 @@ def bench_batched(B, ctx, torch, count: int, seed: int, prec_name: str, reps: in
 
 
 def replay_trace(B, ctx, torch, trace, prec: int, mode: int, arena, max_active: int, policy: int = 0,
-                 budget: float = 2.0):
+                 budget: float = 2.0, aging: float = 0.0):
     import threading
     dev = torch.device("cuda:0")
     psis = [torch.empty(2 << c.n, dtype=torch.float32, device=dev) for _, c in trace]
     torch.cuda.synchronize()
     B.qsim_serve_start(ctx, prec, arena, mode=mode, max_active=max_active, queue_capacity=len(trace) + 1,
-                       policy=policy, iter_budget_tflop=budget)
+                       policy=policy, iter_budget_tflop=budget, aging_tflop_per_s=aging)
     ids = [None] * len(trace)
     t0 = time.monotonic_ns()
 
@@ -165,7 +165,8 @@ def replay_trace(B, ctx, torch, trace, prec: int, mode: int, arena, max_active: 
             "peak_active": stats["peak_active"], "arena_high_water_gib": round(stats["arena_high_water"] / 2**30, 2)}
 
 
-def bench_served(B, ctx, torch, count: int, rate: float, seed: int, prec_name: str, arena_gib: int):
+def bench_served(B, ctx, torch, count: int, rate: float, seed: int, prec_name: str, arena_gib: int,
+                 aging: float = 100.0):
     from paper_2305_14398_amd import workloads as W
     prec = B.PRECISIONS[prec_name]
     trace = W.poisson_trace(count, rate, seed, n_lo=6, n_hi=13, d_lo=10, d_hi=40)
@@ -176,6 +177,10 @@ def bench_served(B, ctx, torch, count: int, rate: float, seed: int, prec_name: s
     progress(f"served continuous (arrival order): p50 {cont['p50_ms']} ms p99 {cont['p99_ms']} ms")
     srpt = replay_trace(B, ctx, torch, trace, prec, B.QSIM_SERVE_CONTINUOUS, arena, 64, B.QSIM_POLICY_SHORTEST, 2.0)
     progress(f"served continuous (least work first): p50 {srpt['p50_ms']} ms p99 {srpt['p99_ms']} ms")
+    aged = replay_trace(B, ctx, torch, trace, prec, B.QSIM_SERVE_CONTINUOUS, arena, 64, B.QSIM_POLICY_AGED, 2.0,
+                        aging)
+    progress(f"served continuous (least work first, aged {aging:g} TFLOP/s): p50 {aged['p50_ms']} ms "
+             f"p99 {aged['p99_ms']} ms")
     plain = replay_trace(B, ctx, torch, trace, prec, B.QSIM_SERVE_FIFO, arena, 1)
     del arena
     torch.cuda.empty_cache()
@@ -186,11 +191,14 @@ def bench_served(B, ctx, torch, count: int, rate: float, seed: int, prec_name: s
         "offered_tflops": round(offered / 1e12, 1),
         "continuous_arrival_order": cont,
         "continuous_least_work_first": srpt,
+        "continuous_least_work_first_aged": dict(aged, aging_tflop_per_s=aging),
         "plain_fifo": plain,
         "p50_speedup_vs_plain": {"arrival_order": round(plain["p50_ms"] / cont["p50_ms"], 3),
-                                 "least_work_first": round(plain["p50_ms"] / srpt["p50_ms"], 3)},
+                                 "least_work_first": round(plain["p50_ms"] / srpt["p50_ms"], 3),
+                                 "least_work_first_aged": round(plain["p50_ms"] / aged["p50_ms"], 3)},
         "p99_speedup_vs_plain": {"arrival_order": round(plain["p99_ms"] / cont["p99_ms"], 3),
-                                 "least_work_first": round(plain["p99_ms"] / srpt["p99_ms"], 3)},
+                                 "least_work_first": round(plain["p99_ms"] / srpt["p99_ms"], 3),
+                                 "least_work_first_aged": round(plain["p99_ms"] / aged["p99_ms"], 3)},
         "throughput_gain_vs_plain": {"arrival_order": round(cont["throughput_req_per_s"] / plain["throughput_req_per_s"], 3),
                                      "least_work_first": round(srpt["throughput_req_per_s"] / plain["throughput_req_per_s"], 3)},
     }
@@ -214,8 +222,11 @@ def bench_served_sweep(B, ctx, torch, rates, seconds: float, prec_name: str, are
         row = {"rate": rate, "requests": count, "offered_req_per_s": round(offered, 2),
                "offered_tflops": round(work / trace[-1][0] / 1e12, 1), "mean_tflop_per_request": round(work / count / 1e12, 2)}
         for name, mode, act, pol in (("continuous_least_work_first", B.QSIM_SERVE_CONTINUOUS, 64,
-                                      B.QSIM_POLICY_SHORTEST), ("plain_fifo", B.QSIM_SERVE_FIFO, 1, 0)):
-            r = replay_trace(B, ctx, torch, trace, prec, mode, arena, act, pol, 2.0)
+                                      B.QSIM_POLICY_SHORTEST),
+                                     ("continuous_least_work_first_aged", B.QSIM_SERVE_CONTINUOUS, 64,
+                                      B.QSIM_POLICY_AGED),
+                                     ("plain_fifo", B.QSIM_SERVE_FIFO, 1, 0)):
+            r = replay_trace(B, ctx, torch, trace, prec, mode, arena, act, pol, 2.0, 100.0)
             r["meets_slo"] = r["p99_ms"] <= slo_ms
             row[name] = r
             progress(f"sweep rate {rate}: {name} p50 {r['p50_ms']} ms p99 {r['p99_ms']} ms "
@@ -224,7 +235,7 @@ def bench_served_sweep(B, ctx, torch, rates, seconds: float, prec_name: str, are
     del arena
     torch.cuda.empty_cache()
     best = {m: max([r["rate"] for r in rows if r[m]["meets_slo"]] or [0])
-            for m in ("continuous_least_work_first", "plain_fifo")}
+            for m in ("continuous_least_work_first", "continuous_least_work_first_aged", "plain_fifo")}
     top = rows[-1]
     capacity = max(top["continuous_least_work_first"]["achieved_tflops"], top["plain_fifo"]["achieved_tflops"])
     mean_work = sum(r["mean_tflop_per_request"] * r["requests"] for r in rows) / sum(r["requests"] for r in rows)

@@ -310,9 +310,14 @@ qsim_status qsim_tune_set(qsim_ctx* ctx, int prec, int n_qubits, int tile);
  *   (8 N^3 per chain product) that fits the arena; every iteration advances the
  *   admitted requests in order of least remaining work until the iteration's
  *   work reaches iter_budget_tflop (at least one request per iteration), so
- *   short circuits are not held to the pace of large ones. */
+ *   short circuits are not held to the pace of large ones.
+ * QSIM_POLICY_AGED: as QSIM_POLICY_SHORTEST, ordered by remaining work minus
+ *   aging_tflop_per_s x seconds since submission, so a request that has waited
+ *   long enough overtakes newer small ones (bounds the tail that least work
+ *   first alone gives the largest requests). */
 #define QSIM_POLICY_ARRIVAL 0
 #define QSIM_POLICY_SHORTEST 1
+#define QSIM_POLICY_AGED 2
 
 typedef struct qsim_serve_config {
     int32_t prec;            /* qsim_precision of every served chain */
@@ -321,9 +326,10 @@ typedef struct qsim_serve_config {
     int32_t queue_capacity;  /* queued (not yet admitted) requests before qsim_submit returns QSIM_E_FULL */
     void* d_arena;           /* caller-owned device memory, 256-byte aligned, untouched by others while serving */
     size_t arena_bytes;
-    int32_t policy;          /* QSIM_POLICY_ARRIVAL or QSIM_POLICY_SHORTEST (continuous mode) */
+    int32_t policy;          /* QSIM_POLICY_ARRIVAL, _SHORTEST or _AGED (continuous mode) */
     int32_t reserved;        /* must be 0 */
-    double iter_budget_tflop;/* QSIM_POLICY_SHORTEST: product work per iteration (e.g. 2.0) */
+    double iter_budget_tflop;/* QSIM_POLICY_SHORTEST / _AGED: product work per iteration (e.g. 2.0) */
+    double aging_tflop_per_s;/* QSIM_POLICY_AGED: work credit per second of waiting (> 0); ignored otherwise */
 } qsim_serve_config;
 
 #define QSIM_REQ_DRIFT_PROBE 1u  /* also compute the probe drift (qsim_unitarity_drift_probe) */

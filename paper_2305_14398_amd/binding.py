@@ -70,13 +70,14 @@ QSIM_E_CANCELLED = -7
 STATUS_NAMES[-7] = "QSIM_E_CANCELLED"
 
 
-QSIM_POLICY_ARRIVAL, QSIM_POLICY_SHORTEST = 0, 1
+QSIM_POLICY_ARRIVAL, QSIM_POLICY_SHORTEST, QSIM_POLICY_AGED = 0, 1, 2
 
 
 class qsim_serve_config(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("mode", ctypes.c_int32), ("max_active", ctypes.c_int32),
                 ("queue_capacity", ctypes.c_int32), ("d_arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t),
-                ("policy", ctypes.c_int32), ("reserved", ctypes.c_int32), ("iter_budget_tflop", ctypes.c_double)]
+                ("policy", ctypes.c_int32), ("reserved", ctypes.c_int32), ("iter_budget_tflop", ctypes.c_double),
+                ("aging_tflop_per_s", ctypes.c_double)]
 
 
 class qsim_request(ctypes.Structure):
@@ -457,11 +458,11 @@ def qsim_unitarity_drift_probe(ctx, n_qubits: int, d_U, stream=None) -> tuple:
 
 def qsim_serve_start(ctx, prec: int, d_arena, arena_bytes: Optional[int] = None, mode: int = QSIM_SERVE_CONTINUOUS,
                      max_active: int = 64, queue_capacity: int = 4096, policy: int = QSIM_POLICY_ARRIVAL,
-                     iter_budget_tflop: float = 2.0) -> None:
+                     iter_budget_tflop: float = 2.0, aging_tflop_per_s: float = 0.0) -> None:
     if arena_bytes is None:
         arena_bytes = d_arena.numel() * d_arena.element_size() if hasattr(d_arena, "numel") else 0
     cfg = qsim_serve_config(prec, mode, max_active, queue_capacity, _ptr(d_arena), arena_bytes, policy, 0,
-                            iter_budget_tflop)
+                            iter_budget_tflop, aging_tflop_per_s)
     _check(lib().qsim_serve_start(_h(ctx), ctypes.byref(cfg)), "qsim_serve_start")
 
 

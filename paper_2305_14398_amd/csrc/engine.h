@@ -33,6 +33,9 @@ class Engine {
     void fail_all_locked(hipError_t err);
     hipError_t iterate(std::deque<Inflight>& inflight);
     hipError_t serve_fifo_one(Req* q);
+    // Scheduling key (smaller runs first): remaining work, less the aging credit
+    // under QSIM_POLICY_AGED.
+    double priority(const Req* q, uint64_t now) const;
     hipError_t finish_launches(Req* q);
     void complete(Inflight& f, hipError_t err);
     hipEvent_t event();

@@ -239,10 +239,20 @@ hipEvent_t Engine::event() {
     return e;
 }
 
+double Engine::priority(const Req* q, uint64_t now) const {
+    double k = q->remaining();
+    if (cfg_.policy == QSIM_POLICY_AGED && now > q->res.t_submit_ns)
+        k -= cfg_.aging_tflop_per_s * 1e12 * (double)(now - q->res.t_submit_ns) * 1e-9;
+    return k;
+}
+
 // Caller holds mu_.  Moves queued requests to the active set while they fit:
 // queue heads in arrival order, or the least estimated work first.
 void Engine::admit_locked() {
-    const bool shortest = cfg_.policy == QSIM_POLICY_SHORTEST && cfg_.mode == QSIM_SERVE_CONTINUOUS;
+    const bool shortest =
+        (cfg_.policy == QSIM_POLICY_SHORTEST || cfg_.policy == QSIM_POLICY_AGED) && cfg_.mode == QSIM_SERVE_CONTINUOUS;
+    const uint64_t now = now_ns();
+    auto key = [&](const Req* q) { return priority(q, now); };
     while (!queue_.empty() && (int)active_.size() < cfg_.max_active && !free_slots_.empty()) {
         auto pick = queue_.begin();
         size_t off = 0;
@@ -250,14 +260,13 @@ void Engine::admit_locked() {
             // the smallest request that fits; ties keep arrival order
             auto best = queue_.end();
             for (auto it = queue_.begin(); it != queue_.end(); ++it)
-                if (best == queue_.end() || (*it)->remaining() < (*best)->remaining()) best = it;
+                if (best == queue_.end() || key(*it) < key(*best)) best = it;
             pick = best;
             if (!arena_->alloc((*pick)->foot, off)) {
                 // try others in increasing work order until one fits
                 std::vector<std::deque<Req*>::iterator> order;
                 for (auto it = queue_.begin(); it != queue_.end(); ++it) order.push_back(it);
-                std::stable_sort(order.begin(), order.end(),
-                                 [](auto a, auto b) { return (*a)->remaining() < (*b)->remaining(); });
+                std::stable_sort(order.begin(), order.end(), [&](auto a, auto b) { return key(*a) < key(*b); });
                 pick = queue_.end();
                 for (auto it : order)
                     if (arena_->alloc((*it)->foot, off)) {
@@ -359,10 +368,11 @@ hipError_t Engine::iterate(std::deque<Inflight>& inflight) {
         std::lock_guard<std::mutex> lk(mu_);
         work = active_;
     }
-    if (cfg_.policy == QSIM_POLICY_SHORTEST) {
-        // least remaining work first, up to the iteration budget (at least one request)
+    if (cfg_.policy == QSIM_POLICY_SHORTEST || cfg_.policy == QSIM_POLICY_AGED) {
+        // least remaining (aged) work first, up to the iteration budget (at least one request)
+        const uint64_t now = now_ns();
         std::stable_sort(work.begin(), work.end(),
-                         [](const Req* a, const Req* b) { return a->remaining() < b->remaining(); });
+                         [&](const Req* a, const Req* b) { return priority(a, now) < priority(b, now); });
         const double budget = cfg_.iter_budget_tflop * 1e12;
         double used = 0.0;
         size_t keep = 0;
@@ -493,11 +503,13 @@ qsim_status qsim_serve_start(qsim_ctx* ctx, const qsim_serve_config* cfg) {
     if (cfg->queue_capacity < 1) return fail(QSIM_E_RANGE, "queue_capacity must be >= 1");
     if (cfg->d_arena == nullptr || !aligned(cfg->d_arena) || cfg->arena_bytes < 256)
         return fail(QSIM_E_INVALID, "arena is NULL, unaligned or empty");
-    if (cfg->policy != QSIM_POLICY_ARRIVAL && cfg->policy != QSIM_POLICY_SHORTEST)
+    if (cfg->policy != QSIM_POLICY_ARRIVAL && cfg->policy != QSIM_POLICY_SHORTEST && cfg->policy != QSIM_POLICY_AGED)
         return fail(QSIM_E_INVALID, "unknown policy %d", cfg->policy);
     if (cfg->reserved != 0) return fail(QSIM_E_INVALID, "reserved field must be 0");
-    if (cfg->policy == QSIM_POLICY_SHORTEST && !(cfg->iter_budget_tflop > 0.0))
+    if (cfg->policy != QSIM_POLICY_ARRIVAL && !(cfg->iter_budget_tflop > 0.0))
         return fail(QSIM_E_INVALID, "iter_budget_tflop must be positive");
+    if (cfg->policy == QSIM_POLICY_AGED && !(cfg->aging_tflop_per_s > 0.0))
+        return fail(QSIM_E_INVALID, "aging_tflop_per_s must be positive");
     qsim_status s = check_ctx(ctx);
     if (s != QSIM_OK) return s;
     if (ctx->engine) return fail(QSIM_E_INVALID, "a serving engine is already running on this context");

@@ -22,12 +22,13 @@ def ctx():
 
 
 def serve(ctx, circuits, prec, mode=B.QSIM_SERVE_CONTINUOUS, max_active=64, arena_mib=2048, want_U=False,
-          stagger=0.0, policy=B.QSIM_POLICY_ARRIVAL, budget=2.0):
+          stagger=0.0, policy=B.QSIM_POLICY_ARRIVAL, budget=2.0, aging=0.0):
     arena = torch.empty(arena_mib << 20, dtype=torch.uint8, device=G.DEV)
     psis = [torch.empty(2 << c.n, dtype=torch.float32, device=G.DEV) for c in circuits]
     Us = [G.planar(c.n) if want_U else None for c in circuits]
     G.sync()
-    B.qsim_serve_start(ctx, prec, arena, mode=mode, max_active=max_active, policy=policy, iter_budget_tflop=budget)
+    B.qsim_serve_start(ctx, prec, arena, mode=mode, max_active=max_active, policy=policy, iter_budget_tflop=budget,
+                       aging_tflop_per_s=aging)
     try:
         ids = []
         for c, p, U in zip(circuits, psis, Us):
@@ -173,12 +174,29 @@ def test_shortest_policy_gives_identical_results_and_finishes_small_first(ctx):
     assert last_small <= first_big
 
 
+def test_aged_policy_identical_results_and_oldest_first_with_large_credit(ctx):
+    """With an aging credit far above any request's work, the aged policy serves the oldest request first;
+    results are bit-identical to arrival order whatever the policy."""
+    big = [W.random_layers(12, 6, np.random.default_rng(s)) for s in range(2)]
+    small = W.batch_mixed(12, seed=14, n_lo=4, n_hi=8, d_lo=2, d_hi=10)
+    circuits = big + small
+    arrival, _ = serve(ctx, circuits, B.QSIM_SPLIT_BF16)
+    aged, _ = serve(ctx, circuits, B.QSIM_SPLIT_BF16, policy=B.QSIM_POLICY_AGED, budget=0.05, aging=1e9)
+    for (a, _, _), (b, rb, _) in zip(arrival, aged):
+        np.testing.assert_array_equal(a, b)
+        assert rb["status"] == B.QSIM_OK
+    first_big = min(r["t_done_ns"] for _, r, _ in aged[:2])
+    assert first_big <= min(r["t_done_ns"] for _, r, _ in aged[2:])
+
+
 def test_policy_validation(ctx):
     arena = torch.empty(1 << 20, dtype=torch.uint8, device=G.DEV)
     with pytest.raises(B.QsimError, match="policy"):
         B.qsim_serve_start(ctx, B.QSIM_FP32_4M, arena, policy=5)
     with pytest.raises(B.QsimError, match="budget"):
         B.qsim_serve_start(ctx, B.QSIM_FP32_4M, arena, policy=B.QSIM_POLICY_SHORTEST, iter_budget_tflop=0.0)
+    with pytest.raises(B.QsimError, match="aging"):
+        B.qsim_serve_start(ctx, B.QSIM_FP32_4M, arena, policy=B.QSIM_POLICY_AGED, aging_tflop_per_s=0.0)
 
 
 def test_served_custom_ops_match_oracle(ctx):

@@ -206,6 +206,8 @@ def test_serving_validation_without_device():
         B.qsim_serve_start(None, B.QSIM_FP32_4M, FAKE + 8, arena_bytes=1 << 20)
     with pytest.raises(B.QsimError, match="precision"):
         B.qsim_serve_start(None, 7, FAKE, arena_bytes=1 << 20)
+    with pytest.raises(B.QsimError, match="aging"):
+        B.qsim_serve_start(None, B.QSIM_FP32_4M, FAKE, arena_bytes=1 << 20, policy=B.QSIM_POLICY_AGED)
     with pytest.raises(B.QsimError, match="NULL"):
         B.qsim_submit(None, 3, [("H", (0,), None)], FAKE)
     with pytest.raises(B.QsimError, match="NULL"):
