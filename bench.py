@@ -250,7 +250,7 @@ def bench_precision_sweep(B, ctx, torch, sizes, depth: int):
     """Config 3: seeded random_layers(n, depth) chains at 12 and 13 qubits in every precision, timed, with the
     product's roofline fraction and the float64 drift of each result; and the QFT chain at the same n in every
     precision against its closed form U[j][k] = w^{jk}/sqrt(N) (max |dU| over sampled columns, and the fidelity of
-    U e_0 with the uniform state). No oracle is involved: random circuits are judged by drift, QFT by its formula."""
+    U e_0 with the uniform state). No oracle is involved: random circuits are assessed by drift, QFT by its formula."""
     import numpy as np
     from paper_2305_14398_amd import workloads as W
     dev = torch.device("cuda:0")
