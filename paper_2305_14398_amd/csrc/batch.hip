@@ -132,8 +132,6 @@ qsim_status qsim_batch_plan_create(qsim_ctx* ctx, const qsim_circuit_desc* circu
     DeviceGuard dg(ctx->device);
     if (dg.err != hipSuccess) return device_fail("hipSetDevice", dg.err);
 
-    const OpFormat fmt = format_of(prec);
-    const bool split = fmt != FMT_F32;
     // Host job tables, per iteration.
     int maxk = 1;
     for (int i = 0; i < count; ++i) maxk = std::max<int>(maxk, (int)offs[i].size() - 1);
@@ -187,8 +185,7 @@ qsim_status qsim_batch_plan_create(qsim_ctx* ctx, const qsim_circuit_desc* circu
     p->use_graph = (flags & QSIM_BATCH_GRAPH) != 0;
     const int cus = device_cus(ctx->device);
     p->grid_expand = cus * 8;
-    // float32 tiles fit two workgroups per CU (67.5 KB LDS), split tiles one (128 KB).
-    p->grid_gemm = split ? cus : 2 * cus;
+    p->grid_gemm = grouped_gemm_grid(prec, cus);
     std::vector<ExpandJob> all_e;
     std::vector<GemmJob> all_g;
     for (int j = 0; j < maxk; ++j) {
@@ -312,7 +309,7 @@ qsim_status qsim_autotune(qsim_ctx* ctx, int prec, int n_lo, int n_hi, double* m
     if (g.err != hipSuccess) return device_fail("hipSetDevice", g.err);
     const bool split = prec >= QSIM_SPLIT_BF16;
     const int cus = device_cus(ctx->device);
-    const int grid = split ? cus : 2 * cus;
+    const int grid = grouped_gemm_grid(prec, cus);
     hipStream_t st = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);

@@ -7,11 +7,9 @@
 namespace qsim {
 namespace {
 
-template <int WM, int WN, int BMB, int BNB, bool GAUSS>
-__global__ __launch_bounds__(64 * WM * WN) void cgemm_f32_kernel(int n, const float* __restrict__ A,
-                                                                   const float* __restrict__ B,
-                                                                   float* __restrict__ C) {
-    using Tile = F32Tile<WM, WN, BMB, BNB, GAUSS>;
+template <class Tile>
+__global__ __launch_bounds__(Tile::NT) void cgemm_f32_kernel(int n, const float* __restrict__ A,
+                                                             const float* __restrict__ B, float* __restrict__ C) {
     __shared__ __attribute__((aligned(16))) float smem[Tile::SMEM_FLOATS];
     const int N = 1 << n;
     int tm, tn;
@@ -25,20 +23,19 @@ __global__ void cgemm_f32_small(int n, const float* __restrict__ A, const float*
     f32_small_product<GAUSS>(n, A, B, C, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
-template <int WM, int WN, int BMB, int BNB, bool GAUSS>
+template <class Tile>
 hipError_t launch_tiled(int n, const float* A, const float* B, float* C, hipStream_t stream) {
     const int N = 1 << n;
-    const int tiles = (N / (32 * WM * BMB)) * (N / (32 * WN * BNB));
-    hipLaunchKernelGGL((cgemm_f32_kernel<WM, WN, BMB, BNB, GAUSS>), dim3(tiles), dim3(64 * WM * WN), 0, stream, n,
-                       A, B, C);
+    const int tiles = (N / Tile::TM) * (N / Tile::TN);
+    hipLaunchKernelGGL(cgemm_f32_kernel<Tile>, dim3(tiles), dim3(Tile::NT), 0, stream, n, A, B, C);
     return hipGetLastError();
 }
 
 template <bool GAUSS>
 hipError_t launch_f32(int n, int tile, const float* A, const float* B, float* C, hipStream_t stream) {
-    if (n >= 7 && tile == 128) return launch_tiled<2, 2, 2, 2, GAUSS>(n, A, B, C, stream);
-    if (n >= 6) return launch_tiled<2, 2, 1, 1, GAUSS>(n, A, B, C, stream);
-    if (n == 5) return launch_tiled<1, 1, 1, 1, GAUSS>(n, A, B, C, stream);
+    if (n >= 7 && tile == 128) return launch_tiled<typename F32Shapes<GAUSS>::T128>(n, A, B, C, stream);
+    if (n >= 6) return launch_tiled<typename F32Shapes<GAUSS>::T64>(n, A, B, C, stream);
+    if (n == 5) return launch_tiled<F32Tile<1, 1, 1, 1, GAUSS>>(n, A, B, C, stream);
     const int NN = 1 << (2 * n);
     hipLaunchKernelGGL(cgemm_f32_small<GAUSS>, dim3((NN + 255) / 256), dim3(256), 0, stream, n, A, B, C);
     return hipGetLastError();

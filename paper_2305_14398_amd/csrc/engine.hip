@@ -137,7 +137,7 @@ qsim_status Engine::init() {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx_->device) != hipSuccess || cus <= 0)
         cus = 256;
     grid_expand_ = 8 * cus;
-    grid_gemm_ = cfg_.prec >= QSIM_SPLIT_BF16 ? cus : 2 * cus;
+    grid_gemm_ = grouped_gemm_grid(cfg_.prec, cus);
     arena_.reset(new Arena(cfg_.arena_bytes));
     for (int s = nslots_ - 1; s >= 0; --s) free_slots_.push_back(s);
     thread_ = std::thread([this] { loop(); });

@@ -54,10 +54,11 @@ __global__ __launch_bounds__(256) void grouped_expand_kernel(const ExpandJob* __
 }
 
 template <bool GAUSS>
-__global__ __launch_bounds__(256) void grouped_f32_kernel(const GemmJob* __restrict__ jobs, int njobs, int total_tiles) {
-    using T128 = F32Tile<2, 2, 2, 2, GAUSS>;
-    using T64 = F32Tile<2, 2, 1, 1, GAUSS>;
-    __shared__ __attribute__((aligned(16))) float smem[T128::SMEM_FLOATS];
+__global__ __launch_bounds__(F32Shapes<GAUSS>::THREADS) void grouped_f32_kernel(const GemmJob* __restrict__ jobs,
+                                                                               int njobs, int total_tiles) {
+    using T128 = typename F32Shapes<GAUSS>::T128;
+    using T64 = typename F32Shapes<GAUSS>::T64;
+    __shared__ __attribute__((aligned(16))) float smem[F32Shapes<GAUSS>::SMEM_FLOATS];
     const int rounds = (total_tiles + gridDim.x - 1) / gridDim.x;
     for (int r = 0; r < rounds; ++r) {
         const int t = persistent_tile(r, blockIdx.x, gridDim.x);
@@ -77,7 +78,7 @@ __global__ __launch_bounds__(256) void grouped_f32_kernel(const GemmJob* __restr
             grouped_tile_order(local, N / 64, N / 64, tm, tn);
             T64::run(J.n, A, B, C, tm, tn, smem);
         } else {
-            f32_small_product<GAUSS>(J.n, A, B, C, threadIdx.x, 256);
+            f32_small_product<GAUSS>(J.n, A, B, C, threadIdx.x, F32Shapes<GAUSS>::THREADS);
         }
     }
 }
@@ -129,10 +130,12 @@ hipError_t launch_grouped_gemm(int prec, const GemmJob* jobs, int njobs, int tot
     if (njobs <= 0 || total_tiles <= 0) return hipSuccess;
     switch (prec) {
         case QSIM_FP32_4M:
-            hipLaunchKernelGGL(grouped_f32_kernel<false>, dim3(grid), dim3(256), 0, stream, jobs, njobs, total_tiles);
+            hipLaunchKernelGGL(grouped_f32_kernel<false>, dim3(grid), dim3(F32Shapes<false>::THREADS), 0, stream, jobs,
+                               njobs, total_tiles);
             break;
         case QSIM_FP32_3M:
-            hipLaunchKernelGGL(grouped_f32_kernel<true>, dim3(grid), dim3(256), 0, stream, jobs, njobs, total_tiles);
+            hipLaunchKernelGGL(grouped_f32_kernel<true>, dim3(grid), dim3(F32Shapes<true>::THREADS), 0, stream, jobs,
+                               njobs, total_tiles);
             break;
         case QSIM_SPLIT_BF16:
             hipLaunchKernelGGL(grouped_split_kernel<FMT_BF16>, dim3(grid), dim3(256), 0, stream, jobs, njobs,

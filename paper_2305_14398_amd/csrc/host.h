@@ -135,6 +135,11 @@ struct TuneTable {
 qsim_status chain_impl(int n, const qsim_gate* gates, int n_gates, const int32_t* off, int n_steps, int prec, void* d_U,
                        void* d_ws, hipStream_t stream, Profiler* prof, const TuneTable& tune);
 
+// Workgroups of a persistent grouped product launch on `cus` compute units:
+// 4M float32 tiles (256 threads, 67.5 KB LDS) fit two per CU; 3M tiles (512
+// threads, 240 registers) and split tiles (128 KB LDS) one.
+inline int grouped_gemm_grid(int prec, int cus) { return prec == QSIM_FP32_4M ? 2 * cus : cus; }
+
 // Context scratch layout (doubles): [0] norm2, [2..3] drift, [4..5] probe
 // drift, [8, 8 + 2*kDriftMaxPartials) drift partials, then the probe scratch.
 constexpr size_t kProbeScratchOffset = 8 + 2 * kDriftMaxPartials;

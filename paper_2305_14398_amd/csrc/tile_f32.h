@@ -17,11 +17,19 @@
 //   4M:  Cre += Ar.Br + (-Ai).Bi ;  Cim += Ar.Bi + Ai.Br        (4 MFMAs per k-pair)
 //   3M:  T1 += Ar.Br ; T2 += Ai.Bi ; T3 += (Ar+Ai).(Br+Bi)       (3 MFMAs per k-pair)
 //        Cre = T1 - T2 ;  Cim = T3 - T1 - T2
-// A workgroup of WM x WN waves computes a (32*WM*BMB) x (32*WN*BNB) tile of C;
-// each wave owns BMB x BNB blocks of 32x32.  K-tiles of 16 are double
-// buffered in LDS; the next tile's global loads are issued before the MFMAs
-// of the current one.  The tile ends with a barrier, so a persistent
+// A workgroup of KS x WM x WN waves computes a (32*WM*BMB) x (32*WN*BNB) tile
+// of C; each wave owns BMB x BNB blocks of 32x32.  K-tiles of BK rows are
+// double buffered in LDS; the next tile's global loads are issued before the
+// MFMAs of the current one.  The tile ends with a barrier, so a persistent
 // workgroup may start its next tile in the same LDS right away.
+//
+// KS = 2 splits every K-tile between two groups of WM x WN waves (in each
+// 16-row slice, group g takes rows 4g..4g+3 and 8+4g..8+4g+3), so two waves
+// share each SIMD and one hides the other's LDS and barrier stalls; each block
+// is then finished by one group, which adds the other group's partial sum
+// through LDS.  The 3M accumulators (192 registers a wave) leave room for only
+// one wave per SIMD otherwise.  The order of the additions into each element
+// depends on KS only, not on the tile size or BK.
 #pragma once
 
 #include "common.h"
@@ -49,21 +57,25 @@ __device__ __forceinline__ int xcd_contiguous_id(int bid, int nblk) {
     return ((nblk & 7) == 0) ? (bid & 7) * (nblk >> 3) + (bid >> 3) : bid;
 }
 
-template <int WM, int WN, int BMB, int BNB, bool GAUSS>
+template <int WM, int WN, int BMB, int BNB, bool GAUSS, int KS = 1, int BK = 16>
 struct F32Tile {
-    static constexpr int NT = 64 * WM * WN;
+    static_assert(KS == 1 || KS == 2, "the k range splits over one or two wave groups");
+    static_assert(BK % 16 == 0, "K-tiles are whole 16-row slices");
+    static constexpr int NT = 64 * WM * WN * KS;
     static constexpr int TM = 32 * WM * BMB;
     static constexpr int TN = 32 * WN * BNB;
-    static constexpr int BK = 16;
     static constexpr int LDA = TM + 4;
     static constexpr int LDB = TN + 4;
     static constexpr int A_V4 = BK * TM / 4 / NT;  // float4 loads per thread per plane
     static constexpr int B_V4 = BK * TN / 4 / NT;
     static_assert(A_V4 * NT * 4 == BK * TM && B_V4 * NT * 4 == BK * TN, "tile/thread mismatch");
     static constexpr int NACC = GAUSS ? 3 : 2;
-    static constexpr int SMEM_FLOATS = 2 * 2 * BK * (LDA + LDB);
+    static constexpr int STAGE_FLOATS = 2 * 2 * BK * (LDA + LDB);
+    static constexpr int XCHG_FLOATS = KS == 2 ? 2 * WM * WN * 2 * 64 * 16 : 0;  // [group][wave][re/im][lane][16]
+    static constexpr int SMEM_FLOATS = STAGE_FLOATS > XCHG_FLOATS ? STAGE_FLOATS : XCHG_FLOATS;
 
-    __device__ static void run(int n, const float* __restrict__ A, const float* __restrict__ B, float* __restrict__ C,
+    __device__ __forceinline__ static void run(int n, const float* __restrict__ A, const float* __restrict__ B,
+                                               float* __restrict__ C,
                                int tm, int tn, float* smem) {
         auto As = reinterpret_cast<float(*)[2][BK][LDA]>(smem);
         auto Bs = reinterpret_cast<float(*)[2][BK][LDB]>(smem + 2 * 2 * BK * LDA);
@@ -72,10 +84,11 @@ struct F32Tile {
         const int i0 = tm * TM, j0 = tn * TN;
         const int tid = threadIdx.x;
         const int lane = tid & 63;
-        const int wave = tid >> 6;
+        const int wave = (tid >> 6) % (WM * WN);
+        const int kgrp = (tid >> 6) / (WM * WN);
         const int wm = wave % WM, wn = wave / WM;
         const int lrow = lane & 31;
-        const int khalf = (lane >> 5) * (BK / 2);
+        const int khalf = (lane >> 5) * 8;
 
         floatx16 acc[BMB][BNB][NACC];
 #pragma unroll
@@ -124,8 +137,8 @@ struct F32Tile {
             const int cur = kt & 1;
             if (kt + 1 < KT) { QSIM_GLOAD((kt + 1) * BK); }
 #pragma unroll
-            for (int t = 0; t < BK / 2; ++t) {
-                const int kk = t + khalf;
+            for (int t = 0; t < BK / 2 / KS; ++t) {
+                const int kk = (t / (8 / KS)) * 16 + kgrp * (8 / KS) + t % (8 / KS) + khalf;
                 float ar[BMB], ai[BMB], br[BNB], bi[BNB];
 #pragma unroll
                 for (int x = 0; x < BMB; ++x) {
@@ -163,30 +176,88 @@ struct F32Tile {
 #undef QSIM_GLOAD
 #undef QSIM_LSTORE
 
+        // Complex value of each 32x32 block (over this wave's k rows) into
+        // accumulators 0 (real) and 1 (imaginary).
+        if constexpr (GAUSS) {
+#pragma unroll
+            for (int x = 0; x < BMB; ++x)
+#pragma unroll
+                for (int y = 0; y < BNB; ++y) {
+                    const floatx16 t1 = acc[x][y][0], t2 = acc[x][y][1];
+                    acc[x][y][0] = t1 - t2;
+                    acc[x][y][1] = acc[x][y][2] - t1 - t2;
+                }
+        }
+
+        // k split over two groups: block b (= x*BNB + y) is finished by group
+        // b & 1.  Blocks go in pairs, one each way per round; an odd last block
+        // goes from group 1 to group 0.  Block indices are compile-time after
+        // unrolling, so the accumulators stay in registers.
+        if constexpr (KS == 2) {
+            floatx16* xch = reinterpret_cast<floatx16*>(smem);
+            constexpr int NB = BMB * BNB;
+            auto slot = [&](int g, int z) { return ((g * (WM * WN) + wave) * 2 + z) * 64 + lane; };
+#pragma unroll
+            for (int b = 0; b < NB; b += 2) {
+                const int x0 = b / BNB, y0 = b % BNB;
+                if (b + 1 < NB) {
+                    const int x1 = (b + 1) / BNB, y1 = (b + 1) % BNB;
+#pragma unroll
+                    for (int z = 0; z < 2; ++z) xch[slot(kgrp, z)] = kgrp ? acc[x0][y0][z] : acc[x1][y1][z];
+                    __syncthreads();
+#pragma unroll
+                    for (int z = 0; z < 2; ++z) {
+                        const floatx16 r = xch[slot(kgrp ^ 1, z)];
+                        if (kgrp)
+                            acc[x1][y1][z] += r;
+                        else
+                            acc[x0][y0][z] += r;
+                    }
+                } else {
+                    if (kgrp) {
+#pragma unroll
+                        for (int z = 0; z < 2; ++z) xch[slot(1, z)] = acc[x0][y0][z];
+                    }
+                    __syncthreads();
+                    if (!kgrp) {
+#pragma unroll
+                        for (int z = 0; z < 2; ++z) acc[x0][y0][z] += xch[slot(1, z)];
+                    }
+                }
+                __syncthreads();
+            }
+        }
+
         // Accumulator layout of a 32x32 block: register e of lane l is
         // row 8*(e/4) + 4*(l/32) + e%4, column l%32.
 #pragma unroll
         for (int x = 0; x < BMB; ++x) {
 #pragma unroll
             for (int y = 0; y < BNB; ++y) {
+                if (KS == 2 && ((x * BNB + y) & 1) != kgrp) continue;
                 const int col = j0 + wn * (32 * BNB) + y * 32 + lrow;
 #pragma unroll
                 for (int e = 0; e < 16; ++e) {
                     const int row = i0 + wm * (32 * BMB) + x * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-                    float re, im;
-                    if constexpr (!GAUSS) {
-                        re = acc[x][y][0][e];
-                        im = acc[x][y][1][e];
-                    } else {
-                        re = acc[x][y][0][e] - acc[x][y][1][e];
-                        im = acc[x][y][2][e] - acc[x][y][0][e] - acc[x][y][1][e];
-                    }
-                    C[(size_t)row * N + col] = re;
-                    C[NN + (size_t)row * N + col] = im;
+                    C[(size_t)row * N + col] = acc[x][y][0][e];
+                    C[NN + (size_t)row * N + col] = acc[x][y][1][e];
                 }
             }
         }
     }
+};
+
+// Tile shapes of the single-problem and grouped products: 128 x 128 and
+// 64 x 64, with the k range split over two wave groups for 3M.  Both kernels
+// use these same shapes, so a product gives the same bits in either.
+template <bool GAUSS>
+struct F32Shapes {
+    using T128 = F32Tile<2, 2, 2, 2, GAUSS, GAUSS ? 2 : 1, 16>;
+    using T64 = F32Tile<2, 2, 1, 1, GAUSS, GAUSS ? 2 : 1, GAUSS ? 32 : 16>;
+    static constexpr int THREADS = T128::NT;
+    static_assert(T64::NT == THREADS, "both shapes run in workgroups of the same size");
+    static constexpr int SMEM_FLOATS =
+        T128::SMEM_FLOATS > T64::SMEM_FLOATS ? T128::SMEM_FLOATS : T64::SMEM_FLOATS;
 };
 
 // Whole product for N <= 32 by a workgroup of `nthreads` threads, one output
