@@ -190,6 +190,34 @@ qsim_status qsim_unitary_chain(qsim_ctx* ctx, int n_qubits, const qsim_gate* gat
                                const int32_t* step_offsets, int n_steps, int prec,
                                void* d_U, void* d_ws, size_t ws_bytes, void* stream);
 
+/* Stages 4 and 5 fused.  Section 5.3 lets a backend change how stages 4-6
+ * compute; here one product C = S . U takes the step operator S straight from
+ * the step's gates, entry by entry inside the product kernel, and never
+ * stores it.  S's entries are the ones qsim_build_step writes (float64
+ * product of the gate factors, rounded once), so d_Uout is bit-identical to
+ * qsim_build_step (column-major) followed by qsim_step_multiply with the same
+ * precision and tile table.
+ * prec: QSIM_FP32_4M or QSIM_FP32_3M (QSIM_E_INVALID otherwise).
+ * gates[0..n_gates): one step, pairwise disjoint spans (n_gates 0 = identity).
+ * d_Uin, d_Uout: planar complex64 row-major, 8*N*N bytes each, caller-owned,
+ *      256-byte aligned, not aliasing (QSIM_E_INVALID otherwise). */
+qsim_status qsim_step_multiply_fused(qsim_ctx* ctx, int n_qubits, int prec, const qsim_gate* gates,
+                                     int n_gates, const void* d_Uin, void* d_Uout, void* stream);
+
+/* Workspace of qsim_unitary_chain_fused: one matrix (8*N*N bytes) for the
+ * float32 precisions; 0 for split precisions or out-of-range arguments. */
+size_t qsim_chain_fused_workspace_bytes(int n_qubits, int prec);
+
+/* qsim_unitary_chain with stages 4 and 5 fused: the first step is expanded
+ * into the first partial product as before, and every later product computes
+ * its step operator inside the product (qsim_step_multiply_fused).  No step
+ * operator is stored, so d_ws holds only the second ping-pong matrix
+ * (ws_bytes >= qsim_chain_fused_workspace_bytes).  Same arguments, checks and
+ * bit-identical results as qsim_unitary_chain; float32 precisions only. */
+qsim_status qsim_unitary_chain_fused(qsim_ctx* ctx, int n_qubits, const qsim_gate* gates, int n_gates,
+                                     const int32_t* step_offsets, int n_steps, int prec,
+                                     void* d_U, void* d_ws, size_t ws_bytes, void* stream);
+
 /* Stage 6: d_psi = d_U . psi0 (complex64 matrix-vector product over the full
  * row-major U).  d_psi0: planar complex64 initial state, or NULL for |0...0>
  * (Eq. 9).  Then, in float64: norm2 = sum |psi_i|^2 and, if d_prob is not

@@ -128,6 +128,9 @@ def lib() -> ctypes.CDLL:
         "qsim_build_step": (i32, [vp, i32, gp, i32, i32, i32, vp, vp]),
         "qsim_step_multiply": (i32, [vp, i32, i32, vp, vp, vp, vp, vp]),
         "qsim_unitary_chain": (i32, [vp, i32, gp, i32, ip, i32, i32, vp, vp, sz, vp]),
+        "qsim_step_multiply_fused": (i32, [vp, i32, i32, gp, i32, vp, vp, vp]),
+        "qsim_chain_fused_workspace_bytes": (sz, [i32, i32]),
+        "qsim_unitary_chain_fused": (i32, [vp, i32, gp, i32, ip, i32, i32, vp, vp, sz, vp]),
         "qsim_apply_state": (i32, [vp, i32, vp, vp, vp, vp, ctypes.POINTER(dbl), vp]),
         "qsim_unitarity_drift": (i32, [vp, i32, vp, ctypes.POINTER(dbl), vp]),
         "qsim_profile_enable": (i32, [vp, i32]),
@@ -308,8 +311,24 @@ def qsim_step_multiply(ctx, n_qubits: int, prec: int, d_S, d_Uin, d_Uout, d_Uout
                                     _ptr(d_Uout_split), st), "qsim_step_multiply")
 
 
+def qsim_step_multiply_fused(ctx, n_qubits: int, prec: int, gates: Sequence, d_Uin, d_Uout, stream=None) -> None:
+    arr, ng = gate_array(gates)
+    st = _stream(stream, _dev(ctx)) if _h(ctx) else None
+    _check(lib().qsim_step_multiply_fused(_h(ctx), n_qubits, prec, arr, ng, _ptr(d_Uin), _ptr(d_Uout), st),
+           "qsim_step_multiply_fused")
+
+
+def qsim_chain_fused_workspace_bytes(n_qubits: int, prec: int) -> int:
+    return int(lib().qsim_chain_fused_workspace_bytes(n_qubits, prec))
+
+
+def qsim_unitary_chain_fused(ctx, n_qubits: int, gates: Sequence, prec: int, d_U, d_ws, ws_bytes: Optional[int] = None,
+                             step_offsets: Optional[Sequence[int]] = None, stream=None) -> None:
+    qsim_unitary_chain(ctx, n_qubits, gates, prec, d_U, d_ws, ws_bytes, step_offsets, stream, _fused=True)
+
+
 def qsim_unitary_chain(ctx, n_qubits: int, gates: Sequence, prec: int, d_U, d_ws, ws_bytes: Optional[int] = None,
-                       step_offsets: Optional[Sequence[int]] = None, stream=None) -> None:
+                       step_offsets: Optional[Sequence[int]] = None, stream=None, _fused: bool = False) -> None:
     arr, ng = gate_array(gates)
     if step_offsets is None:
         off_p, ns = None, 0
@@ -319,8 +338,8 @@ def qsim_unitary_chain(ctx, n_qubits: int, gates: Sequence, prec: int, d_U, d_ws
     if ws_bytes is None:
         ws_bytes = d_ws.numel() * d_ws.element_size() if hasattr(d_ws, "numel") else 0
     st = _stream(stream, _dev(ctx)) if _h(ctx) else None
-    _check(lib().qsim_unitary_chain(_h(ctx), n_qubits, arr, ng, off_p, ns, prec, _ptr(d_U), _ptr(d_ws), ws_bytes, st),
-           "qsim_unitary_chain")
+    name = "qsim_unitary_chain_fused" if _fused else "qsim_unitary_chain"
+    _check(getattr(lib(), name)(_h(ctx), n_qubits, arr, ng, off_p, ns, prec, _ptr(d_U), _ptr(d_ws), ws_bytes, st), name)
 
 
 def qsim_apply_state(ctx, n_qubits: int, d_U, d_psi0, d_psi, d_prob=None, want_norm2: bool = True,

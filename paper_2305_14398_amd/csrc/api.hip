@@ -1,6 +1,7 @@
 // C ABI of libqsim (declared in include/qsim.h): argument validation, the
 // float64 gate table (Section 2.3, Table 1; Section 5.2.2), step formation,
 // and the host side of stages 4-6 of the unitary method (Section 5.3).
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -160,12 +161,21 @@ qsim_status make_step(int n, const qsim_gate* gates, int count, DevStep& st) {
         return fail(QSIM_E_INVALID, "step has %d gates (max %d)", count, QSIM_MAX_GATES_PER_STEP);
     std::memset(&st, 0, sizeof st);
     uint32_t used_span = 0, touched = 0;
+    int order[QSIM_MAX_GATES_PER_STEP], top[QSIM_MAX_GATES_PER_STEP], bottom[QSIM_MAX_GATES_PER_STEP];
     for (int i = 0; i < count; ++i) {
-        const qsim_gate& g = gates[i];
-        const uint32_t sm = span_mask(g);
+        const uint32_t sm = span_mask(gates[i]);
         if (sm & used_span) return fail(QSIM_E_INVALID, "step gate %d overlaps the span of an earlier gate of the step", i);
         used_span |= sm;
-        DevGate& d = st.g[i];
+        span_of(gates[i], bottom[i], top[i]);
+        order[i] = i;
+    }
+    // Highest span first (spans are disjoint, so the order is total).
+    std::sort(order, order + count, [&](int a, int b) { return top[a] > top[b]; });
+    for (int slot = 0; slot < count; ++slot) {
+        const int i = order[slot];
+        const qsim_gate& g = gates[i];
+        if (bottom[i] >= 2) st.n_prefix = slot + 1;
+        DevGate& d = st.g[slot];
         if (g.kind == QSIM_CUSTOM) {
             d.type = GATE_CUSTOM;
             d.q0 = g.target;
@@ -175,7 +185,7 @@ qsim_status make_step(int n, const qsim_gate* gates, int count, DevStep& st) {
             if (e != hipSuccess) return device_fail("hipGetDevice", e);
             qsim_status cs = custom_device(g.op_id, dev, &d.ext);
             if (cs != QSIM_OK) return cs;
-            touched |= sm;
+            touched |= span_mask(g);
             continue;
         }
         if (g.kind == QSIM_SWAP) {
@@ -250,7 +260,7 @@ namespace qsim {
 
 // Shared by the synchronous entry points and the serving engine.
 qsim_status chain_impl(int n, const qsim_gate* gates, int n_gates, const int32_t* off, int n_steps, int prec, void* d_U,
-                       void* d_ws, hipStream_t stream, Profiler* prof, const TuneTable& tune) {
+                       void* d_ws, hipStream_t stream, Profiler* prof, const TuneTable& tune, bool fused) {
     const int tile = tune.get(prec, n);
     const size_t mb = mat_bytes(n);
     const OpFormat fmt = format_of(prec);
@@ -265,10 +275,11 @@ qsim_status chain_impl(int n, const qsim_gate* gates, int n_gates, const int32_t
     }
     char* ws = static_cast<char*>(d_ws);
     if (fmt == FMT_F32) {
-        // buffers: X0 = d_U, X1 = ws[1]; S = ws[0].  Product j (1..k-1) writes
-        // X[(k-1-j) % 2], so the last one lands in d_U.
-        void* X[2] = {d_U, ws + mb};
+        // buffers: X0 = d_U, X1 = ws[1]; S = ws[0] (fused: X1 = ws[0], no S).
+        // Product j (1..k-1) writes X[(k-1-j) % 2], so the last one lands in d_U.
+        void* X[2] = {d_U, fused ? ws : ws + mb};
         void* S = ws;
+        const bool gauss = prec == QSIM_FP32_3M;
         const int k = n_steps;
         void* cur = X[(k - 1) & 1];
         s = make_step(n, gates + off[0], off[1] - off[0], st);
@@ -278,13 +289,21 @@ qsim_status chain_impl(int n, const qsim_gate* gates, int n_gates, const int32_t
         for (int j = 1; j < k; ++j) {
             s = make_step(n, gates + off[j], off[j + 1] - off[j], st);
             if (s != QSIM_OK) return s;
-            e = timed(prof, QSIM_PROFILE_EXPAND, stream, [&] { return launch_expand_step(st, n, 1, FMT_F32, S, stream); });
-            if (e != hipSuccess) return device_fail("expand", e);
             void* nxt = X[(k - 1 - j) & 1];
-            e = timed(prof, QSIM_PROFILE_PRODUCT, stream, [&] {
-                return launch_cgemm_f32(n, prec == QSIM_FP32_3M, tile, static_cast<const float*>(S),
-                                        static_cast<const float*>(cur), static_cast<float*>(nxt), stream);
-            });
+            if (fused) {
+                e = timed(prof, QSIM_PROFILE_PRODUCT, stream, [&] {
+                    return launch_cgemm_f32_fused(n, gauss, tile, st, static_cast<const float*>(cur),
+                                                  static_cast<float*>(nxt), stream);
+                });
+            } else {
+                e = timed(prof, QSIM_PROFILE_EXPAND, stream,
+                          [&] { return launch_expand_step(st, n, 1, FMT_F32, S, stream); });
+                if (e != hipSuccess) return device_fail("expand", e);
+                e = timed(prof, QSIM_PROFILE_PRODUCT, stream, [&] {
+                    return launch_cgemm_f32(n, gauss, tile, static_cast<const float*>(S),
+                                            static_cast<const float*>(cur), static_cast<float*>(nxt), stream);
+                });
+            }
             if (e != hipSuccess) return device_fail("cgemm", e);
             cur = nxt;
         }
@@ -383,6 +402,11 @@ size_t qsim_chain_workspace_bytes(int n_qubits, int prec) {
     return (format_of(prec) == FMT_F32 ? 2 : 3) * mat_bytes(n_qubits);
 }
 
+size_t qsim_chain_fused_workspace_bytes(int n_qubits, int prec) {
+    if (!valid_n(n_qubits) || !valid_prec(prec) || format_of(prec) != FMT_F32) return 0;
+    return mat_bytes(n_qubits);
+}
+
 qsim_status qsim_build_step(qsim_ctx* ctx, int n_qubits, const qsim_gate* gates, int n_gates, int prec, int layout,
                             void* d_op, void* stream) {
     qsim_status s = QSIM_OK;
@@ -450,9 +474,39 @@ qsim_status qsim_step_multiply(qsim_ctx* ctx, int n_qubits, int prec, const void
     return e == hipSuccess ? ok() : device_fail("cgemm launch", e);
 }
 
-qsim_status qsim_unitary_chain(qsim_ctx* ctx, int n_qubits, const qsim_gate* gates, int n_gates,
-                               const int32_t* step_offsets, int n_steps, int prec, void* d_U, void* d_ws, size_t ws_bytes,
-                               void* stream) {
+qsim_status qsim_step_multiply_fused(qsim_ctx* ctx, int n_qubits, int prec, const qsim_gate* gates, int n_gates,
+                                     const void* d_Uin, void* d_Uout, void* stream) {
+    qsim_status s = QSIM_OK;
+    if (!valid_n(n_qubits)) return fail(QSIM_E_RANGE, "n_qubits %d outside 1..%d", n_qubits, QSIM_MAX_QUBITS);
+    if (!valid_prec(prec)) return fail(QSIM_E_INVALID, "unknown precision %d", prec);
+    if (format_of(prec) != FMT_F32) return fail(QSIM_E_INVALID, "fused products are float32 (4M or 3M) only");
+    if (!built_prec(prec)) return fail(QSIM_E_INVALID, "precision %d is not available in this build", prec);
+    if (!d_Uin || !d_Uout || !aligned(d_Uin) || !aligned(d_Uout))
+        return fail(QSIM_E_INVALID, "d_Uin / d_Uout is NULL or not 256-byte aligned");
+    if (d_Uin == d_Uout) return fail(QSIM_E_INVALID, "d_Uout aliases d_Uin");
+    s = check_gates(n_qubits, gates, n_gates);
+    if (s != QSIM_OK) return s;
+    DevStep st;
+    s = make_step(n_qubits, gates, n_gates, st);  // validation (the device pointers are rebuilt below)
+    if (s != QSIM_OK) return s;
+    s = check_ctx(ctx);
+    if (s != QSIM_OK) return s;
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return device_fail("hipSetDevice", g.err);
+    s = make_step(n_qubits, gates, n_gates, st);
+    if (s != QSIM_OK) return s;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const int tile = ctx->tune.get(prec, n_qubits);
+    hipError_t e = timed(ctx->prof, QSIM_PROFILE_PRODUCT, hs, [&] {
+        return launch_cgemm_f32_fused(n_qubits, prec == QSIM_FP32_3M, tile, st, static_cast<const float*>(d_Uin),
+                                      static_cast<float*>(d_Uout), hs);
+    });
+    return e == hipSuccess ? ok() : device_fail("fused cgemm launch", e);
+}
+
+static qsim_status unitary_chain_entry(qsim_ctx* ctx, int n_qubits, const qsim_gate* gates, int n_gates,
+                                       const int32_t* step_offsets, int n_steps, int prec, void* d_U, void* d_ws,
+                                       size_t ws_bytes, void* stream, bool fused) {
     qsim_status s = QSIM_OK;
     if (!valid_n(n_qubits)) return fail(QSIM_E_RANGE, "n_qubits %d outside 1..%d", n_qubits, QSIM_MAX_QUBITS);
     if (!valid_prec(prec)) return fail(QSIM_E_INVALID, "unknown precision %d", prec);
@@ -472,7 +526,8 @@ qsim_status qsim_unitary_chain(qsim_ctx* ctx, int n_qubits, const qsim_gate* gat
     const int k = (int)off.size() - 1;
     if (k > 0) {
         if (d_ws == nullptr || !aligned(d_ws)) return fail(QSIM_E_INVALID, "d_ws is NULL or not 256-byte aligned");
-        const size_t need = qsim_chain_workspace_bytes(n_qubits, prec);
+        const size_t need =
+            fused ? qsim_chain_fused_workspace_bytes(n_qubits, prec) : qsim_chain_workspace_bytes(n_qubits, prec);
         if (ws_bytes < need) return fail(QSIM_E_RANGE, "workspace %zu bytes, need %zu", ws_bytes, need);
         const char* w = static_cast<const char*>(d_ws);
         const char* u = static_cast<const char*>(d_U);
@@ -489,8 +544,24 @@ qsim_status qsim_unitary_chain(qsim_ctx* ctx, int n_qubits, const qsim_gate* gat
     DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return device_fail("hipSetDevice", g.err);
     s = chain_impl(n_qubits, gates, n_gates, off.data(), k, prec, d_U, d_ws, static_cast<hipStream_t>(stream), ctx->prof,
-                   ctx->tune);
+                   ctx->tune, fused);
     return s == QSIM_OK ? ok() : s;
+}
+
+qsim_status qsim_unitary_chain(qsim_ctx* ctx, int n_qubits, const qsim_gate* gates, int n_gates,
+                               const int32_t* step_offsets, int n_steps, int prec, void* d_U, void* d_ws, size_t ws_bytes,
+                               void* stream) {
+    return unitary_chain_entry(ctx, n_qubits, gates, n_gates, step_offsets, n_steps, prec, d_U, d_ws, ws_bytes, stream,
+                               false);
+}
+
+qsim_status qsim_unitary_chain_fused(qsim_ctx* ctx, int n_qubits, const qsim_gate* gates, int n_gates,
+                                     const int32_t* step_offsets, int n_steps, int prec, void* d_U, void* d_ws,
+                                     size_t ws_bytes, void* stream) {
+    if (valid_prec(prec) && format_of(prec) != FMT_F32)
+        return fail(QSIM_E_INVALID, "fused chains are float32 (4M or 3M) only");
+    return unitary_chain_entry(ctx, n_qubits, gates, n_gates, step_offsets, n_steps, prec, d_U, d_ws, ws_bytes, stream,
+                               true);
 }
 
 qsim_status qsim_apply_state(qsim_ctx* ctx, int n_qubits, const void* d_U, const void* d_psi0, void* d_psi,

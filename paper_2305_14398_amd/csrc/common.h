@@ -23,10 +23,14 @@ struct DevGate {
 };
 
 // A step descriptor small enough to travel as a kernel argument (by value).
+// Gates are stored in descending order of their span's top qubit, so the
+// n_prefix gates whose spans leave out qubits 0 and 1 come first (the others,
+// at most two, have the lowest spans).
 struct DevStep {
     int32_t n_gates;
     uint32_t idle_mask;  // bit q set: no gate of the step touches qubit q
-    int32_t pad[2];
+    int32_t n_prefix;
+    int32_t pad;
     DevGate g[QSIM_MAX_GATES_PER_STEP];
 };
 
@@ -78,6 +82,9 @@ hipError_t launch_expand_step(const DevStep& st, int n, int layout_col, OpFormat
                               hipStream_t stream);
 hipError_t launch_cgemm_f32(int n, bool gauss, int tile, const float* S_col, const float* U_row, float* C_row,
                             hipStream_t stream);
+// C = S . U with S (a step operator) computed inside the product, never stored.
+hipError_t launch_cgemm_f32_fused(int n, bool gauss, int tile, const DevStep& st, const float* U_row, float* C_row,
+                                  hipStream_t stream);
 // D = X Y^T over split operands (see cgemm_split.hip); D_split and/or D_f32 row-major.
 hipError_t launch_cgemm_split(int n, OpFormat fmt, int tile, const void* X, const void* Y, void* D_split,
                               float* D_f32, hipStream_t stream);

@@ -24,9 +24,53 @@ __device__ __forceinline__ double sel4(int idx, double a, double b, double c, do
     return idx == 0 ? a : idx == 1 ? b : idx == 2 ? c : d;
 }
 
-// Entry (r, s) of the step operator in float64.  All reads of `st` use a
-// wave-uniform gate index, so they stay scalar loads from the kernel argument
-// segment; the per-lane choice of matrix entry is a select.
+// Multiply the running entry (pr, pi) by gate G's factor at (r, s), or set
+// `zero` where the factor is a structural zero.  Reads of G use a wave-uniform
+// gate index, so they stay scalar loads from the kernel argument segment; the
+// per-lane choice of matrix entry is a select.
+__device__ __forceinline__ void gate_factor(const DevGate& G, uint32_t r, uint32_t s, double& pr, double& pi,
+                                            bool& zero) {
+    const int type = G.type;
+    const int q0 = G.q0, q1 = G.q1;
+    if (type == GATE_CUSTOM) {
+        const uint32_t mask = (1u << q1) - 1u;
+        const uint32_t e = (((r >> q0) & mask) << q1) | ((s >> q0) & mask);
+        const double ar = G.ext[2 * e], ai = G.ext[2 * e + 1];
+        const double t = pr * ar - pi * ai;
+        pi = pr * ai + pi * ar;
+        pr = t;
+        return;
+    }
+    int idx = 0;
+    bool use = true;
+    if (type == GATE_ONE) {
+        idx = (((r >> q0) & 1u) << 1) | ((s >> q0) & 1u);
+    } else if (type == GATE_CTRL) {
+        const uint32_t rc = (r >> q0) & 1u, sc = (s >> q0) & 1u;
+        const uint32_t rt = (r >> q1) & 1u, stt = (s >> q1) & 1u;
+        zero |= rc != sc;
+        if (sc == 0) {
+            zero |= rt != stt;
+            use = false;
+        }
+        idx = (int)((rt << 1) | stt);
+    } else {  // GATE_SWAP
+        zero |= ((r >> q0) & 1u) != ((s >> q1) & 1u);
+        zero |= ((r >> q1) & 1u) != ((s >> q0) & 1u);
+        use = false;
+    }
+    if (use) {
+        const double* m = G.m;
+        const double ar = sel4(idx, m[0], m[2], m[4], m[6]);
+        const double ai = sel4(idx, m[1], m[3], m[5], m[7]);
+        const double t = pr * ar - pi * ai;
+        pi = pr * ai + pi * ar;
+        pr = t;
+    }
+}
+
+// Entry (r, s) of the step operator in float64: the gate factors multiplied
+// in the descriptor's order, starting from 1.
 __device__ __forceinline__ void step_entry(const DevStep& st, uint32_t r, uint32_t s, double& out_re,
                                            double& out_im) {
     double pr = 1.0, pi = 0.0;
@@ -36,47 +80,32 @@ __device__ __forceinline__ void step_entry(const DevStep& st, uint32_t r, uint32
         out_im = 0.0;
         return;
     }
-    for (int g = 0; g < st.n_gates; ++g) {
-        const int type = st.g[g].type;
-        const int q0 = st.g[g].q0, q1 = st.g[g].q1;
-        int idx = 0;
-        bool use = true;
-        if (type == GATE_CUSTOM) {
-            const uint32_t mask = (1u << q1) - 1u;
-            const uint32_t e = (((r >> q0) & mask) << q1) | ((s >> q0) & mask);
-            const double ar = st.g[g].ext[2 * e], ai = st.g[g].ext[2 * e + 1];
-            const double t = pr * ar - pi * ai;
-            pi = pr * ai + pi * ar;
-            pr = t;
-            continue;
-        }
-        if (type == GATE_ONE) {
-            idx = (((r >> q0) & 1u) << 1) | ((s >> q0) & 1u);
-        } else if (type == GATE_CTRL) {
-            const uint32_t rc = (r >> q0) & 1u, sc = (s >> q0) & 1u;
-            const uint32_t rt = (r >> q1) & 1u, stt = (s >> q1) & 1u;
-            zero |= rc != sc;
-            if (sc == 0) {
-                zero |= rt != stt;
-                use = false;
-            }
-            idx = (int)((rt << 1) | stt);
-        } else {  // GATE_SWAP
-            zero |= ((r >> q0) & 1u) != ((s >> q1) & 1u);
-            zero |= ((r >> q1) & 1u) != ((s >> q0) & 1u);
-            use = false;
-        }
-        if (use) {
-            const double* m = st.g[g].m;
-            const double ar = sel4(idx, m[0], m[2], m[4], m[6]);
-            const double ai = sel4(idx, m[1], m[3], m[5], m[7]);
-            const double t = pr * ar - pi * ai;
-            pi = pr * ai + pi * ar;
-            pr = t;
-        }
-    }
+    for (int g = 0; g < st.n_gates; ++g) gate_factor(st.g[g], r, s, pr, pi, zero);
     out_re = zero ? 0.0 : pr;
     out_im = zero ? 0.0 : pi;
+}
+
+// Entries (r + c, s), c = 0..3, for r a multiple of 4: the same values as
+// step_entry, with the descriptor's leading gates (those whose spans leave out
+// qubits 0 and 1, so whose factors do not depend on c) multiplied once.
+__device__ __forceinline__ void step_entries4(const DevStep& st, uint32_t r, uint32_t s, double (&out_re)[4],
+                                              double (&out_im)[4]) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) out_re[c] = out_im[c] = 0.0;
+    bool zhi = ((r ^ s) & st.idle_mask & ~3u) != 0;
+    if (!zhi) {  // otherwise all four entries are structural zeros (most of a sparse step)
+        double pr = 1.0, pi = 0.0;
+        for (int g = 0; g < st.n_prefix; ++g) gate_factor(st.g[g], r, s, pr, pi, zhi);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            double qr = pr, qi = pi;
+            bool zero = zhi || ((((uint32_t)c ^ s) & st.idle_mask & 3u) != 0);
+            if (!zero)
+                for (int g = st.n_prefix; g < st.n_gates; ++g) gate_factor(st.g[g], r + c, s, qr, qi, zero);
+            out_re[c] = zero ? 0.0 : qr;
+            out_im[c] = zero ? 0.0 : qi;
+        }
+    }
 }
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }

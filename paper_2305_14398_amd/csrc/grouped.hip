@@ -78,7 +78,7 @@ __global__ __launch_bounds__(F32Shapes<GAUSS>::THREADS) void grouped_f32_kernel(
             grouped_tile_order(local, N / 64, N / 64, tm, tn);
             T64::run(J.n, A, B, C, tm, tn, smem);
         } else {
-            f32_small_product<GAUSS>(J.n, A, B, C, threadIdx.x, F32Shapes<GAUSS>::THREADS);
+            f32_small_product<GAUSS>(J.n, A, nullptr, B, C, threadIdx.x, F32Shapes<GAUSS>::THREADS);
         }
     }
 }

@@ -132,8 +132,10 @@ struct TuneTable {
 };
 
 // Shared by the synchronous entry points and the serving engine.
+// fused: float32 precisions only; every product after the first step computes
+// its step operator inside the product (no scratch operator in d_ws).
 qsim_status chain_impl(int n, const qsim_gate* gates, int n_gates, const int32_t* off, int n_steps, int prec, void* d_U,
-                       void* d_ws, hipStream_t stream, Profiler* prof, const TuneTable& tune);
+                       void* d_ws, hipStream_t stream, Profiler* prof, const TuneTable& tune, bool fused = false);
 
 // Workgroups of a persistent grouped product launch on `cus` compute units:
 // 4M float32 tiles (256 threads, 67.5 KB LDS) fit two per CU; 3M tiles (512

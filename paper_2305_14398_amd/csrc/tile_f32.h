@@ -30,9 +30,14 @@
 // through LDS.  The 3M accumulators (192 registers a wave) leave room for only
 // one wave per SIMD otherwise.  The order of the additions into each element
 // depends on KS only, not on the tile size or BK.
+//
+// run_fused() computes the same product without a stored A: each thread
+// evaluates its slice of every K-tile of the step operator from the step's
+// gates (fused stages 4 and 5), where run() loads it.
 #pragma once
 
 #include "common.h"
+#include "expand_entry.h"
 
 namespace qsim {
 
@@ -74,9 +79,36 @@ struct F32Tile {
     static constexpr int XCHG_FLOATS = KS == 2 ? 2 * WM * WN * 2 * 64 * 16 : 0;  // [group][wave][re/im][lane][16]
     static constexpr int SMEM_FLOATS = STAGE_FLOATS > XCHG_FLOATS ? STAGE_FLOATS : XCHG_FLOATS;
 
+    // Entries S[r + c][s], c = 0..3, of a step operator (column s of A).
+    __device__ __forceinline__ static void synth_a(const DevStep& st, uint32_t r, uint32_t s, floatx4& re,
+                                                   floatx4& im) {
+        double vr[4], vi[4];
+        step_entries4(st, r, s, vr, vi);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            re[c] = (float)vr[c];
+            im[c] = (float)vi[c];
+        }
+    }
+
     __device__ __forceinline__ static void run(int n, const float* __restrict__ A, const float* __restrict__ B,
-                                               float* __restrict__ C,
-                               int tm, int tn, float* smem) {
+                                               float* __restrict__ C, int tm, int tn, float* smem) {
+        run_impl<false>(n, A, nullptr, B, C, tm, tn, smem);
+    }
+
+    // Stages 4 and 5 fused: the A operand (the step operator) is never
+    // stored; each K-tile of it is computed from the step's gates by the same
+    // per-entry rule, in float64 rounded once, as the expansion kernel, so the
+    // product is bit-identical to expanding S and calling run().
+    __device__ __forceinline__ static void run_fused(int n, const DevStep& st, const float* __restrict__ B,
+                                                     float* __restrict__ C, int tm, int tn, float* smem) {
+        run_impl<true>(n, nullptr, &st, B, C, tm, tn, smem);
+    }
+
+    template <bool FUSED>
+    __device__ __forceinline__ static void run_impl(int n, const float* __restrict__ A, const DevStep* st,
+                                                    const float* __restrict__ B, float* __restrict__ C, int tm,
+                                                    int tn, float* smem) {
         auto As = reinterpret_cast<float(*)[2][BK][LDA]>(smem);
         auto Bs = reinterpret_cast<float(*)[2][BK][LDB]>(smem + 2 * 2 * BK * LDA);
         const int N = 1 << n;
@@ -104,11 +136,21 @@ struct F32Tile {
         // covers row f / (T/4) and columns 4*(f % (T/4)) .. +3 of that tile.
         floatx4 ra[2][A_V4], rb[2][B_V4];
 #define QSIM_GLOAD(k0)                                                                                   \
-    _Pragma("unroll") for (int p = 0; p < 2; ++p) {                                                      \
+    if constexpr (FUSED) {                                                                               \
         _Pragma("unroll") for (int u = 0; u < A_V4; ++u) {                                               \
             const int f = tid + NT * u;                                                                   \
-            ra[p][u] = *reinterpret_cast<const floatx4*>(A + p * NN + (size_t)((k0) + f / (TM / 4)) * N + \
-                                                         i0 + (f % (TM / 4)) * 4);                        \
+            synth_a(*st, (uint32_t)(i0 + (f % (TM / 4)) * 4), (uint32_t)((k0) + f / (TM / 4)), ra[0][u], \
+                    ra[1][u]);                                                                            \
+        }                                                                                                 \
+    }                                                                                                     \
+    _Pragma("unroll") for (int p = 0; p < 2; ++p) {                                                      \
+        if constexpr (!FUSED) {                                                                           \
+            _Pragma("unroll") for (int u = 0; u < A_V4; ++u) {                                           \
+                const int f = tid + NT * u;                                                               \
+                ra[p][u] = *reinterpret_cast<const floatx4*>(A + p * NN +                                \
+                                                             (size_t)((k0) + f / (TM / 4)) * N + i0 +    \
+                                                             (f % (TM / 4)) * 4);                         \
+            }                                                                                             \
         }                                                                                                 \
         _Pragma("unroll") for (int u = 0; u < B_V4; ++u) {                                               \
             const int f = tid + NT * u;                                                                   \
@@ -262,16 +304,28 @@ struct F32Shapes {
 
 // Whole product for N <= 32 by a workgroup of `nthreads` threads, one output
 // entry per thread and pass, plain float32 FMAs (same 4M / 3M arithmetic).
+// With `st` set, A is the step operator computed entry by entry (fused
+// stages 4 and 5, the same values the expansion kernel stores).
 template <bool GAUSS>
-__device__ __forceinline__ void f32_small_product(int n, const float* __restrict__ A, const float* __restrict__ B,
-                                                  float* __restrict__ C, int first, int stride) {
+__device__ __forceinline__ void f32_small_product(int n, const float* __restrict__ A, const DevStep* st,
+                                                  const float* __restrict__ B, float* __restrict__ C, int first,
+                                                  int stride) {
     const int N = 1 << n;
     const int NN = N * N;
     for (int idx = first; idx < NN; idx += stride) {
         const int i = idx / N, j = idx % N;
         float t1 = 0.f, t2 = 0.f, t3 = 0.f;
         for (int k = 0; k < N; ++k) {
-            const float ar = A[k * N + i], ai = A[NN + k * N + i];
+            float ar, ai;
+            if (st != nullptr) {
+                double vr, vi;
+                step_entry(*st, (uint32_t)i, (uint32_t)k, vr, vi);
+                ar = (float)vr;
+                ai = (float)vi;
+            } else {
+                ar = A[k * N + i];
+                ai = A[NN + k * N + i];
+            }
             const float br = B[k * N + j], bi = B[NN + k * N + j];
             if constexpr (!GAUSS) {
                 t1 = fmaf(ar, br, t1);

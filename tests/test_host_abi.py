@@ -144,6 +144,32 @@ def test_chain_validation_without_device():
     _expect(B.QSIM_E_INVALID, B.qsim_unitary_chain, None, 4, g, 0, FAKE, FAKE * 4, 2 * mb, match="context is NULL")
 
 
+def test_fused_chain_and_product_validation_without_device():
+    g = W.qft(4).gates
+    mb = 8 << 8
+    # one matrix of workspace: the fused chain stores no step operator
+    assert B.qsim_chain_fused_workspace_bytes(4, B.QSIM_FP32_3M) == mb
+    assert B.qsim_chain_fused_workspace_bytes(4, B.QSIM_FP32_4M) == mb
+    assert B.qsim_chain_workspace_bytes(4, B.QSIM_FP32_3M) == 2 * mb
+    assert B.qsim_chain_fused_workspace_bytes(4, B.QSIM_SPLIT_BF16) == 0
+    assert B.qsim_chain_fused_workspace_bytes(0, B.QSIM_FP32_4M) == 0
+    f = B.qsim_unitary_chain_fused
+    _expect(B.QSIM_E_INVALID, f, None, 4, g, B.QSIM_SPLIT_BF16, FAKE, FAKE * 4, 3 * mb, match="float32")
+    _expect(B.QSIM_E_RANGE, f, None, 4, g, 0, FAKE, FAKE * 4, mb - 8, match="workspace")
+    _expect(B.QSIM_E_INVALID, f, None, 4, g, 0, FAKE, FAKE, mb, match="overlaps")
+    _expect(B.QSIM_E_INVALID, f, None, 4, g, 0, FAKE, FAKE * 4, mb, [0, 2] + list(range(3, len(g) + 1)),
+            match="step 0")
+    _expect(B.QSIM_E_INVALID, f, None, 4, g, 0, FAKE, FAKE * 4, mb, match="context is NULL")
+    m = B.qsim_step_multiply_fused
+    step = [("H", (0,), None), ("CNOT", (1, 2), None)]
+    _expect(B.QSIM_E_INVALID, m, None, 4, B.QSIM_SPLIT_FP16, step, FAKE, FAKE * 2, match="float32")
+    _expect(B.QSIM_E_INVALID, m, None, 4, 0, step, FAKE, FAKE, match="aliases")
+    _expect(B.QSIM_E_INVALID, m, None, 4, 0, step, FAKE + 8, FAKE * 2, match="aligned")
+    _expect(B.QSIM_E_INVALID, m, None, 4, 0, [("H", (1,), None), ("CNOT", (0, 2), None)], FAKE, FAKE * 2)
+    _expect(B.QSIM_E_RANGE, m, None, 17, 0, step, FAKE, FAKE * 2)
+    _expect(B.QSIM_E_INVALID, m, None, 4, 0, step, FAKE, FAKE * 2, match="context is NULL")
+
+
 def test_multiply_apply_drift_validation_without_device():
     _expect(B.QSIM_E_INVALID, B.qsim_step_multiply, None, 5, 0, FAKE, FAKE * 2, FAKE, None, match="aliases")
     _expect(B.QSIM_E_INVALID, B.qsim_step_multiply, None, 5, 0, FAKE, FAKE * 2, FAKE * 3, FAKE * 4, match="split")
