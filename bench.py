@@ -421,6 +421,8 @@ def main() -> int:
     ap.add_argument("--prec", default="fp32_3m", choices=sorted(PEAK_TFLOPS))
     ap.add_argument("--variant", default="fp32_4m,split_fp16,split_bf16",
                     help="comma-separated further precisions timed on the same workload ('' to skip)")
+    ap.add_argument("--fused", default="fp32_3m",
+                    help="float32 precisions also timed with stages 4 and 5 fused ('' to skip)")
     ap.add_argument("--qubits", type=int, default=11)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -470,9 +472,11 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
 
-    def timed_run(prec_name: str, check: bool):
+    def timed_run(prec_name: str, check: bool, fused: bool = False):
         prec = B.PRECISIONS[prec_name]
-        ws = torch.empty(B.qsim_chain_workspace_bytes(n, prec), dtype=torch.uint8, device=dev)
+        ws_bytes = (B.qsim_chain_fused_workspace_bytes if fused else B.qsim_chain_workspace_bytes)(n, prec)
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+        chain = B.qsim_unitary_chain_fused if fused else B.qsim_unitary_chain
         results = {}
 
         drift_dev = torch.empty((len(circuits), 2), dtype=torch.float64, device=dev)
@@ -481,7 +485,7 @@ def main() -> int:
             # No host synchronisation inside a step: the float64 norm stays on the device and each drift result
             # goes to its own device slot; the checking step reads them back.
             for ci, (c, gates) in enumerate(zip(circuits, gate_lists)):
-                B.qsim_unitary_chain(ctx, n, gates, prec, U, ws)
+                chain(ctx, n, gates, prec, U, ws)
                 if not check:
                     B.qsim_apply_state(ctx, n, U, None, psi, prob, want_norm2=False)
                     B.qsim_unitarity_drift_async(ctx, n, U, drift_dev[ci])
@@ -515,12 +519,15 @@ def main() -> int:
         cnt, tot = stats["product"]
         avg_ms = tot / cnt if cnt else float("nan")
         return {"wall": wall, "gpu_ms": ev0.elapsed_time(ev1), "stats": stats, "checks": results,
-                "tflops": flops_per_step * args.steps / wall / 1e12, "avg_product_ms": avg_ms}
+                "tflops": flops_per_step * args.steps / wall / 1e12, "avg_product_ms": avg_ms, "ws_bytes": ws_bytes}
 
     main = timed_run(args.prec, check=True)
     wall, gpu_ms, stats, results = main["wall"], main["gpu_ms"], main["stats"], main["checks"]
     variant_names = [v for v in args.variant.split(",") if v and v != args.prec]
     variant_runs = [(v, timed_run(v, check=False)) for v in variant_names]
+    fused_names = [v for v in args.fused.split(",") if v]
+    fused_runs = [(v, timed_run(v, check=False, fused=True)) for v in fused_names]
+    unfused = dict(variant_runs + [(args.prec, main)])
 
     ms_per_step = wall * 1e3 / args.steps
     tflops = flops_per_step * args.steps / wall / 1e12
@@ -586,6 +593,18 @@ def main() -> int:
             "product_frac_of_ceiling": round(8.0 * N ** 3 / (r["avg_product_ms"] * 1e-3) / 1e12 /
                                              (PEAK_TFLOPS[v] / ISSUED_PER_COUNTED[v]), 4),
         } for v, r in variant_runs],
+        "fused": [{
+            "precision": v,
+            "workload": "the same steps with stages 4 and 5 fused (qsim_unitary_chain_fused: each step operator "
+                        "computed inside the product, never stored)",
+            "value": round(r["tflops"], 3),
+            "ms_per_step": round(r["wall"] * 1e3 / args.steps, 3),
+            "avg_product_ms": round(r["avg_product_ms"], 5),
+            "expand_launches": r["stats"]["expand"][0],
+            "workspace_bytes": r["ws_bytes"],
+            "unfused_workspace_bytes": B.qsim_chain_workspace_bytes(n, B.PRECISIONS[v]),
+            "speed_vs_unfused": round(r["tflops"] / unfused[v]["tflops"], 4) if v in unfused else None,
+        } for v, r in fused_runs],
         "paper_context": "TornadoQSim reports end-to-end speedups over single-threaded Java of 506.5x (fully "
                          "entangled), 493.10x (Deutsch-Jozsa) and 518.12x (QFT) at 11 qubits on a Quadro GP100; "
                          "different hardware, precision and baseline",
