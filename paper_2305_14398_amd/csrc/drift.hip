@@ -17,9 +17,7 @@ namespace {
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int DT = 64;     // tile edge
-constexpr int DBK = 16;    // k rows per LDS tile
-constexpr int DLD = DT + 16;  // padded row stride (floats): the 4 k-rows of one MFMA land on distinct banks
+constexpr int DBK = 16;  // k rows per LDS tile
 
 __device__ __forceinline__ void tile_of(int t, int T, int& tm, int& tn) {
     // t-th upper-triangular tile in row order: row tm holds T - tm tiles.
@@ -31,7 +29,16 @@ __device__ __forceinline__ void tile_of(int t, int T, int& tm, int& tn) {
     tn = tm + t;
 }
 
-__global__ __launch_bounds__(256, 3) void drift_mfma_kernel(int n, const float* __restrict__ U, double* __restrict__ partials) {
+// A workgroup of 2 x 2 waves computes a DT x DT tile of G, DT = 32 * BX; each
+// wave owns BX x BX blocks of 16 x 16.  The tile edge sets the granularity of
+// the work split: at 11 qubits 64-wide tiles give 528 tiles for 256 CUs (16 CUs
+// take a third tile while the rest idle), 32-wide ones 2080.
+template <int BX>
+__global__ __launch_bounds__(256, 3) void drift_mfma_kernel(int n, const float* __restrict__ U,
+                                                            double* __restrict__ partials) {
+    constexpr int DT = 32 * BX;
+    constexpr int DLD = DT + 16;  // padded row stride (floats): the 4 k-rows of one MFMA land on distinct banks
+    constexpr int LOADS = DBK * DT / 4;  // float4 per plane per operand and K-tile: 256 (BX 2) or 128 (BX 1)
     const int N = 1 << n;
     const size_t NN = (size_t)N * N;
     const int T = N / DT;
@@ -44,8 +51,11 @@ __global__ __launch_bounds__(256, 3) void drift_mfma_kernel(int n, const float* 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
     const int l16 = lane & 15, kq = lane >> 4;
-    // loader: one float4 per plane per operand: row tid/16, columns 4*(tid%16)
-    const int lrow = tid >> 4, lcol = (tid & 15) * 4;
+    // loader: float4 number f of a plane covers row f / (DT/4), columns 4*(f % (DT/4)); with 128 per operand,
+    // threads 0..127 load A and 128..255 load B
+    const int f = tid % LOADS;
+    const int lrow = f / (DT / 4), lcol = (f % (DT / 4)) * 4;
+    const bool load_a = LOADS == 256 || tid < 128, load_b = LOADS == 256 || tid >= 128;
 
     double tmax = 0.0, tsum = 0.0;
 
@@ -53,24 +63,24 @@ __global__ __launch_bounds__(256, 3) void drift_mfma_kernel(int n, const float* 
         int tm, tn;
         tile_of(t, T, tm, tn);
         const int i0 = tm * DT, j0 = tn * DT;
-        doublex4 acc[2][2][2];
+        doublex4 acc[BX][BX][2];
 #pragma unroll
-        for (int x = 0; x < 2; ++x)
+        for (int x = 0; x < BX; ++x)
 #pragma unroll
-            for (int y = 0; y < 2; ++y)
+            for (int y = 0; y < BX; ++y)
 #pragma unroll
                 for (int z = 0; z < 2; ++z) acc[x][y][z] = doublex4{0.0, 0.0, 0.0, 0.0};
 
         floatx4 ra[2], rb[2];
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
-            ra[p] = *reinterpret_cast<const floatx4*>(U + p * NN + (size_t)lrow * N + i0 + lcol);
-            rb[p] = *reinterpret_cast<const floatx4*>(U + p * NN + (size_t)lrow * N + j0 + lcol);
+            if (load_a) ra[p] = *reinterpret_cast<const floatx4*>(U + p * NN + (size_t)lrow * N + i0 + lcol);
+            if (load_b) rb[p] = *reinterpret_cast<const floatx4*>(U + p * NN + (size_t)lrow * N + j0 + lcol);
         }
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
-            *reinterpret_cast<floatx4*>(&As[0][p][lrow][lcol]) = ra[p];
-            *reinterpret_cast<floatx4*>(&Bs[0][p][lrow][lcol]) = rb[p];
+            if (load_a) *reinterpret_cast<floatx4*>(&As[0][p][lrow][lcol]) = ra[p];
+            if (load_b) *reinterpret_cast<floatx4*>(&Bs[0][p][lrow][lcol]) = rb[p];
         }
         __syncthreads();
 
@@ -81,25 +91,25 @@ __global__ __launch_bounds__(256, 3) void drift_mfma_kernel(int n, const float* 
                 const size_t r = (size_t)((kt + 1) * DBK + lrow) * N;
 #pragma unroll
                 for (int p = 0; p < 2; ++p) {
-                    ra[p] = *reinterpret_cast<const floatx4*>(U + p * NN + r + i0 + lcol);
-                    rb[p] = *reinterpret_cast<const floatx4*>(U + p * NN + r + j0 + lcol);
+                    if (load_a) ra[p] = *reinterpret_cast<const floatx4*>(U + p * NN + r + i0 + lcol);
+                    if (load_b) rb[p] = *reinterpret_cast<const floatx4*>(U + p * NN + r + j0 + lcol);
                 }
             }
 #pragma unroll
             for (int s = 0; s < DBK / 4; ++s) {
                 const int k = 4 * s + kq;
-                double ar[2], ai[2], br[2], bi[2];
+                double ar[BX], ai[BX], br[BX], bi[BX];
 #pragma unroll
-                for (int x = 0; x < 2; ++x) {
-                    ar[x] = (double)As[cur][0][k][wm * 32 + x * 16 + l16];
-                    ai[x] = (double)As[cur][1][k][wm * 32 + x * 16 + l16];
-                    br[x] = (double)Bs[cur][0][k][wn * 32 + x * 16 + l16];
-                    bi[x] = (double)Bs[cur][1][k][wn * 32 + x * 16 + l16];
+                for (int x = 0; x < BX; ++x) {
+                    ar[x] = (double)As[cur][0][k][wm * 16 * BX + x * 16 + l16];
+                    ai[x] = (double)As[cur][1][k][wm * 16 * BX + x * 16 + l16];
+                    br[x] = (double)Bs[cur][0][k][wn * 16 * BX + x * 16 + l16];
+                    bi[x] = (double)Bs[cur][1][k][wn * 16 * BX + x * 16 + l16];
                 }
 #pragma unroll
-                for (int x = 0; x < 2; ++x) {
+                for (int x = 0; x < BX; ++x) {
 #pragma unroll
-                    for (int y = 0; y < 2; ++y) {
+                    for (int y = 0; y < BX; ++y) {
                         acc[x][y][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[x], br[y], acc[x][y][0], 0, 0, 0);
                         acc[x][y][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[x], bi[y], acc[x][y][0], 0, 0, 0);
                         acc[x][y][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[x], bi[y], acc[x][y][1], 0, 0, 0);
@@ -110,8 +120,8 @@ __global__ __launch_bounds__(256, 3) void drift_mfma_kernel(int n, const float* 
             if (kt + 1 < KT) {
 #pragma unroll
                 for (int p = 0; p < 2; ++p) {
-                    *reinterpret_cast<floatx4*>(&As[cur ^ 1][p][lrow][lcol]) = ra[p];
-                    *reinterpret_cast<floatx4*>(&Bs[cur ^ 1][p][lrow][lcol]) = rb[p];
+                    if (load_a) *reinterpret_cast<floatx4*>(&As[cur ^ 1][p][lrow][lcol]) = ra[p];
+                    if (load_b) *reinterpret_cast<floatx4*>(&Bs[cur ^ 1][p][lrow][lcol]) = rb[p];
                 }
             }
             __syncthreads();
@@ -120,13 +130,13 @@ __global__ __launch_bounds__(256, 3) void drift_mfma_kernel(int n, const float* 
         // 16x16 float64 accumulator layout: register r of lane l is row l/16 + 4*r, column l%16.
         const double w = (tm == tn) ? 1.0 : 2.0;
 #pragma unroll
-        for (int x = 0; x < 2; ++x) {
+        for (int x = 0; x < BX; ++x) {
 #pragma unroll
-            for (int y = 0; y < 2; ++y) {
-                const int j = j0 + wn * 32 + y * 16 + l16;
+            for (int y = 0; y < BX; ++y) {
+                const int j = j0 + wn * 16 * BX + y * 16 + l16;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int i = i0 + wm * 32 + x * 16 + kq + 4 * r;
+                    const int i = i0 + wm * 16 * BX + x * 16 + kq + 4 * r;
                     const double dr = acc[x][y][0][r] - (i == j ? 1.0 : 0.0);
                     const double di = acc[x][y][1][r];
                     const double m2 = dr * dr + di * di;
@@ -153,7 +163,7 @@ __global__ __launch_bounds__(256, 3) void drift_mfma_kernel(int n, const float* 
     }
 }
 
-// N < 64: one block, one thread per entry of G, plain float64 arithmetic.
+// N < 32: one block, one thread per entry of G, plain float64 arithmetic.
 __global__ __launch_bounds__(256) void drift_small_kernel(int n, const float* __restrict__ U, double* __restrict__ partials) {
     const int N = 1 << n;
     const size_t NN = (size_t)N * N;
@@ -337,13 +347,18 @@ hipError_t launch_drift(int n, const float* U_row, double* partials, int max_par
                         hipStream_t stream) {
     const int N = 1 << n;
     int count = 1;
-    if (N < DT) {
+    if (N < 32) {
         hipLaunchKernelGGL(drift_small_kernel, dim3(1), dim3(256), 0, stream, n, U_row, partials);
     } else {
-        const int T = N / DT;
+        // 64-wide tiles once there are enough of them to spread evenly over the CUs (n >= 12: 2080 tiles)
+        const bool wide = n >= 12;
+        const int T = N / (wide ? 64 : 32);
         const int ntiles = T * (T + 1) / 2;
         count = ntiles < max_partials ? ntiles : max_partials;
-        hipLaunchKernelGGL(drift_mfma_kernel, dim3(count), dim3(256), 0, stream, n, U_row, partials);
+        if (wide)
+            hipLaunchKernelGGL(drift_mfma_kernel<2>, dim3(count), dim3(256), 0, stream, n, U_row, partials);
+        else
+            hipLaunchKernelGGL(drift_mfma_kernel<1>, dim3(count), dim3(256), 0, stream, n, U_row, partials);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
