@@ -85,9 +85,11 @@ __device__ __forceinline__ void step_entry(const DevStep& st, uint32_t r, uint32
     out_im = zero ? 0.0 : pi;
 }
 
-// Entries (r + c, s), c = 0..3, for r a multiple of 4: the same values as
-// step_entry, with the descriptor's leading gates (those whose spans leave out
-// qubits 0 and 1, so whose factors do not depend on c) multiplied once.
+// Entries (r + c, s), c = 0..3, for r a multiple of 4 (ALONG_S: (r, s + c),
+// s a multiple of 4): the same values as step_entry, with the descriptor's
+// leading gates (those whose spans leave out qubits 0 and 1, so whose factors
+// do not depend on c) multiplied once.
+template <bool ALONG_S = false>
 __device__ __forceinline__ void step_entries4(const DevStep& st, uint32_t r, uint32_t s, double (&out_re)[4],
                                               double (&out_im)[4]) {
 #pragma unroll
@@ -96,12 +98,14 @@ __device__ __forceinline__ void step_entries4(const DevStep& st, uint32_t r, uin
     if (!zhi) {  // otherwise all four entries are structural zeros (most of a sparse step)
         double pr = 1.0, pi = 0.0;
         for (int g = 0; g < st.n_prefix; ++g) gate_factor(st.g[g], r, s, pr, pi, zhi);
+        const uint32_t low = (ALONG_S ? r : s) & 3u;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             double qr = pr, qi = pi;
-            bool zero = zhi || ((((uint32_t)c ^ s) & st.idle_mask & 3u) != 0);
+            bool zero = zhi || ((((uint32_t)c ^ low) & st.idle_mask & 3u) != 0);
+            const uint32_t rc = ALONG_S ? r : r + c, sc = ALONG_S ? s + c : s;
             if (!zero)
-                for (int g = st.n_prefix; g < st.n_gates; ++g) gate_factor(st.g[g], r + c, s, qr, qi, zero);
+                for (int g = st.n_prefix; g < st.n_gates; ++g) gate_factor(st.g[g], rc, sc, qr, qi, zero);
             out_re[c] = zero ? 0.0 : qr;
             out_im[c] = zero ? 0.0 : qi;
         }
@@ -132,13 +136,22 @@ __device__ __forceinline__ void expand_four(const DevStep& st, int n, int layout
     const uint64_t N = 1ull << n;
     const uint64_t NN = N * N;
     double vr[4], vi[4];
+    if (n >= 2) {  // the four entries share a storage row
+        const uint32_t a = (uint32_t)(e0 >> n);
+        const uint32_t b = (uint32_t)(e0 & (N - 1));
+        if (layout_col)
+            step_entries4<false>(st, b, a, vr, vi);
+        else
+            step_entries4<true>(st, a, b, vr, vi);
+    } else {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        const uint32_t a = (uint32_t)((e0 + c) >> n);
-        const uint32_t b = (uint32_t)((e0 + c) & (N - 1));
-        const uint32_t r = layout_col ? b : a;
-        const uint32_t s = layout_col ? a : b;
-        step_entry(st, r, s, vr[c], vi[c]);
+        for (int c = 0; c < 4; ++c) {
+            const uint32_t a = (uint32_t)((e0 + c) >> n);
+            const uint32_t b = (uint32_t)((e0 + c) & (N - 1));
+            const uint32_t r = layout_col ? b : a;
+            const uint32_t s = layout_col ? a : b;
+            step_entry(st, r, s, vr[c], vi[c]);
+        }
     }
     if (FMT == FMT_F32) {
         float* o = reinterpret_cast<float*>(out);
