@@ -72,7 +72,7 @@ struct SplitTile {
     static constexpr int TN = 32 * WN * BNB;
     static constexpr int SMEM_CHUNKS = 2 * 4 * (TM + TN) * 4;  // 16-byte chunks
 
-    __device__ static void run(int n, const uint16_t* __restrict__ X, const uint16_t* __restrict__ Y,
+    __device__ __forceinline__ static void run(int n, const uint16_t* __restrict__ X, const uint16_t* __restrict__ Y,
                                uint16_t* __restrict__ Dsplit, float* __restrict__ Df32, int tm, int tn,
                                u32x4* smem) {
         constexpr int XCH = 4 * TM * 4;  // 16-byte chunks per X stage (4 planes, TM rows, 4 chunks)

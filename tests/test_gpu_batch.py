@@ -165,3 +165,38 @@ def test_batch_with_custom_ops_matches_single_and_oracle(ctx):
         cols = W.random_columns(c.n, 8, 3)
         assert np.abs(U[:, cols] - fsv.unitary_columns(c.n, g, cols)).max() <= 1e-5
         np.testing.assert_array_equal(U, single(ctx, c, B.QSIM_FP32_4M))
+
+
+def test_full_batched_config_sampled_against_oracle(ctx):
+    """The batched configuration at full size, in the launch configuration the benchmark times: 512 seeded
+    circuits (n ~ U{4..11}, families ghz_chain/dj/qft/random, depth ~ U{5..30}, seed 0), 3M, autotuned tiles,
+    one graph-captured plan launched twice.  Every result is checked by a property that holds at any size
+    (float64 probe drift); the largest circuits and a regular sample are checked against the oracle (route B)
+    on sampled columns; the replay equals the first launch bit for bit."""
+    prec = B.QSIM_FP32_3M
+    circuits = W.batch_mixed(512, seed=0, n_lo=4, n_hi=11, d_lo=5, d_hi=30)
+    B.qsim_autotune(ctx, prec, 7, 11)
+    outs = [G.planar(c.n) for c in circuits]
+    ws = G.workspace(B.qsim_batch_workspace_bytes(circuits, prec))
+    plan = B.BatchPlan(ctx, circuits, outs, prec, ws, graph=True)
+    plan.launch()
+    G.sync()
+    first = [o.clone() for o in outs[:24]]
+    plan.launch()
+    G.sync()
+    plan.close()
+    del ws
+    for a, o in zip(first, outs[:24]):
+        assert torch.equal(a, o)
+    for c, o in zip(circuits, outs):
+        mx, _ = B.qsim_unitarity_drift_probe(ctx, c.n, o)
+        assert mx <= 1e-5, (c.family, c.n, mx)
+    largest = sorted(range(len(circuits)), key=lambda i: -circuits[i].n)[:6]
+    for i in sorted(set(largest + list(range(0, len(circuits), 48)))):
+        c = circuits[i]
+        cols = W.random_columns(c.n, 4, i)
+        got = G.to_complex(outs[i][:, :, torch.as_tensor(cols, device=G.DEV)])
+        ref = fsv.unitary_columns(c.n, W.gate_tuples(c), cols)
+        assert np.abs(got - ref).max() <= 1e-5, (i, c.family, c.n)
+    del outs, first
+    torch.cuda.empty_cache()

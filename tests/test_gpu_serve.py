@@ -211,3 +211,24 @@ def test_served_custom_ops_match_oracle(ctx):
     for c, g, (psi, res, _) in zip(circuits, refs, out):
         assert res["status"] == B.QSIM_OK
         assert np.abs(psi - fsv.final_state(c.n, g)).max() <= 1e-5
+
+
+def test_full_served_config_sampled_against_oracle(ctx):
+    """The served configuration at full size: 200 Poisson arrivals at 200 req/s (seed 0), n ~ U{6..13}, depth
+    ~ U{10..40}, split-bf16, least-work-first continuous batching, submitted at the trace's mean spacing.  Every
+    request completes with its float64 norm and probe drift; the largest requests and a regular sample match
+    the oracle's final state (route B) with fidelity >= 1 - 1e-6."""
+    trace = W.poisson_trace(200, 200.0, 0, n_lo=6, n_hi=13, d_lo=10, d_hi=40)
+    circuits = [c for _, c in trace]
+    out, stats = serve(ctx, circuits, B.QSIM_SPLIT_BF16, arena_mib=32 << 10, policy=B.QSIM_POLICY_SHORTEST,
+                       budget=2.0, stagger=0.005)
+    assert stats["completed"] == len(circuits)
+    for c, (psi, res, _) in zip(circuits, out):
+        assert res["status"] == B.QSIM_OK
+        assert 0 <= res["drift_max"] <= 1e-3, (c.family, c.n, res["drift_max"])
+        assert res["norm2"] == pytest.approx(float(np.sum(np.abs(psi) ** 2)), rel=1e-12)
+    largest = sorted(range(len(circuits)), key=lambda i: -circuits[i].n)[:5]
+    for i in sorted(set(largest + list(range(0, len(circuits), 25)))):
+        c = circuits[i]
+        ref = fsv.final_state(c.n, W.gate_tuples(c))
+        assert metrics.fidelity(out[i][0], ref) >= 1 - 1e-6, (i, c.family, c.n)
