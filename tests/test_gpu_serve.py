@@ -220,7 +220,7 @@ def test_full_served_config_sampled_against_oracle(ctx):
     the oracle's final state (route B) with fidelity >= 1 - 1e-6."""
     trace = W.poisson_trace(200, 200.0, 0, n_lo=6, n_hi=13, d_lo=10, d_hi=40)
     circuits = [c for _, c in trace]
-    out, stats = serve(ctx, circuits, B.QSIM_SPLIT_BF16, arena_mib=32 << 10, policy=B.QSIM_POLICY_SHORTEST,
+    out, stats = serve(ctx, circuits, B.QSIM_SPLIT_BF16, arena_mib=48 << 10, policy=B.QSIM_POLICY_SHORTEST,
                        budget=2.0, stagger=0.005)
     assert stats["completed"] == len(circuits)
     for c, (psi, res, _) in zip(circuits, out):
