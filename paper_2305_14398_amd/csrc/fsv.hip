@@ -63,16 +63,17 @@ __device__ __forceinline__ void fsv_for16(F&& f) {
     fsv_for16_impl(f, std::make_integer_sequence<int, 16>{});
 }
 
-enum : int32_t { FSV_GENERAL = 0, FSV_DIAG = 1, FSV_DENSE = 2, FSV_TABLE = 3 };
+enum : int32_t { FSV_GENERAL = 0, FSV_DIAG = 1, FSV_DENSE = 2, FSV_TABLE = 3, FSV_PHASE = 4 };
+constexpr int kFsvPhaseBits = 5;  // non-local qubits per FSV_PHASE table (2^5 entries)
 
 struct FsvGate {
     int32_t kind;
     int32_t tloc;   // local bit of the target (dense: of the range's lowest qubit), or -1 (diagonal only)
-    int32_t tglob;  // the target qubit when it is not local
+    int32_t tglob;  // the target qubit when it is not local (phase: up to 5 non-local qubits, 6 bits each)
     int32_t cloc;   // local bit of the control, or -1
     int32_t cglob;  // a non-local control qubit, or -1
-    int32_t width;  // dense: qubits in the range
-    int32_t moff;   // dense / table: offset of its float32 (re, im) data in the plan's pool
+    int32_t width;  // dense: qubits in the range; phase: non-local qubits of its table
+    int32_t moff;   // dense / table / phase: offset of its float32 data in the plan's pool
     int32_t real;   // general: 1 if every matrix entry is real
     float m[8];  // row-major 2x2 (re, im); a diagonal gate uses m[0..1] and m[6..7]
 };
@@ -366,6 +367,32 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
     const bool full = n >= kFsvLocal;
     const int nloc = full ? (1 << kFsvLocal) : (1 << n);
 
+    // Stage the pass's operation records in LDS once per workgroup: every
+    // thread then reads each record at LDS latency instead of a scalar-cache miss.
+    // A grouped-diagonal record holds a table over some non-local qubits: this
+    // workgroup's entry turns it into a plain diagonal record on its local bit
+    // (no local bit: d0 = d1, the same factor whatever bit it reads).
+    const int nops = p.g1 - p.g0;
+    const uint32_t base_lo = (uint32_t)base, base_hi = (uint32_t)(base >> 32);
+    for (int r = t; r < nops; r += 256) {
+        FsvGate o = gates[p.g0 + r];
+        if (o.kind == FSV_PHASE) {
+            int idx = 0;
+            for (int b = 0; b < o.width; ++b) {
+                const int q = (o.tglob >> (6 * b)) & 63;
+                idx |= (int)(((q < 32 ? base_lo >> q : base_hi >> (q - 32))) & 1u) << b;
+            }
+            const float4 e = *reinterpret_cast<const float4*>(pool + o.moff + 4 * idx);
+            o.m[0] = e.x;
+            o.m[1] = e.y;
+            o.m[6] = e.z;
+            o.m[7] = e.w;
+            o.kind = FSV_DIAG;
+            if (o.tloc < 0) o.tglob = 0;
+        }
+        s_ops[r] = o;
+    }
+    __syncthreads();
     f32x16 ar, ai;
     fsv_for16([&](auto I_) {
         constexpr int r = decltype(I_)::value;
@@ -391,16 +418,6 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
     bool lp_pending = false;
 
     int cur = 2;
-    // Stage the pass's operation records in LDS once per workgroup: every
-    // thread then reads each record at LDS latency instead of a scalar-cache miss.
-    const int nops = p.g1 - p.g0;
-    {
-        const int* src = reinterpret_cast<const int*>(gates + p.g0);
-        int* dst = reinterpret_cast<int*>(s_ops);
-        const int words = nops * (int)(sizeof(FsvGate) / sizeof(int));
-        for (int w = t; w < words; w += 256) dst[w] = src[w];
-    }
-    __syncthreads();
     // The next record is read from LDS while the current one executes.
     FsvGate nxt = nops > 0 ? s_ops[0] : FsvGate{};
     for (int gi = 0; gi < nops; ++gi) {
@@ -498,10 +515,19 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
     fsv_flush(ar, ai, lpr, lpi, lp_pending);
     if (cur != 2) fsv_relayout(ar, ai, t, cur, 2, s_re, s_im);
 
+    // The thread's offset again (recomputed rather than kept in two registers
+    // through the operation loop; the empty asm keeps the compiler from reusing
+    // the first computation).
+    int t2 = t;
+    asm volatile("" : "+v"(t2));
+    uint64_t gt2 = 0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+        if ((t2 >> b) & 1) gt2 |= (uint64_t)1 << fsv_pos(p, b);
     fsv_for16([&](auto I_) {
         constexpr int r = decltype(I_)::value;
         const int j = t | (r << 8);
-        uint64_t g = base | gt;
+        uint64_t g = base | gt2;
 #pragma unroll
         for (int b = 0; b < 4; ++b)
             if ((r >> b) & 1) g |= gh[b];
@@ -915,7 +941,96 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
             } else {
                 for (size_t q : local_ops) other_ops.push_back(q);
             }
-            for (size_t q : other_ops) table.push_back(record(gs[q]));
+            // In a workgroup the non-local qubits are fixed, so each remaining operation is a diagonal on one
+            // local bit (one local and one non-local qubit) or a single factor (no local qubit).  They are
+            // grouped by that local bit and multiplied out on the host in float64 for every combination of up
+            // to 5 of their non-local qubits: one table lookup replaces a record per operation.
+            std::vector<std::pair<int, std::vector<size_t>>> groups;  // local bit (-1: none), operations
+            for (size_t q : other_ops) {
+                const LoweredGate& l = gs[q];
+                const int tb = local_bit(l.tq), cb = l.cq >= 0 ? local_bit(l.cq) : -1;
+                int a;
+                if (tb >= 0 && l.cq >= 0 && cb < 0)
+                    a = tb;  // local target, non-local control
+                else if (tb < 0 && cb >= 0)
+                    a = cb;  // local control, non-local target
+                else if (tb < 0)
+                    a = -1;  // no local qubit
+                else {
+                    table.push_back(record(l));  // both local (a run with a single such operation)
+                    continue;
+                }
+                size_t gi = 0;
+                while (gi < groups.size() && groups[gi].first != a) ++gi;
+                if (gi == groups.size()) groups.push_back({a, {}});
+                groups[gi].second.push_back(q);
+            }
+            for (auto& grp : groups) {
+                const int a = grp.first;
+                size_t x = 0;
+                while (x < grp.second.size()) {
+                    // the next chunk: operations in order while their non-local qubits number <= 5
+                    std::vector<int> qs;
+                    size_t y = x;
+                    for (; y < grp.second.size(); ++y) {
+                        const LoweredGate& l = gs[grp.second[y]];
+                        std::vector<int> need;
+                        if (local_bit(l.tq) < 0) need.push_back(l.tq);
+                        if (l.cq >= 0 && local_bit(l.cq) < 0) need.push_back(l.cq);
+                        std::vector<int> merged = qs;
+                        for (int qq : need)
+                            if (std::find(merged.begin(), merged.end(), qq) == merged.end()) merged.push_back(qq);
+                        if ((int)merged.size() > kFsvPhaseBits) break;
+                        qs = merged;
+                    }
+                    FsvGate d{};
+                    d.kind = FSV_PHASE;
+                    d.tloc = a;
+                    d.tglob = 0;
+                    for (size_t b = 0; b < qs.size(); ++b) d.tglob |= qs[b] << (6 * b);
+                    d.cloc = d.cglob = -1;
+                    d.width = (int)qs.size();
+                    d.moff = (int)pool.size();
+                    for (int idx = 0; idx < (1 << qs.size()); ++idx) {
+                        auto bit_of = [&](int q) {
+                            const size_t b = std::find(qs.begin(), qs.end(), q) - qs.begin();
+                            return (idx >> b) & 1;
+                        };
+                        double u0r = 1.0, u0i = 0.0, u1r = 1.0, u1i = 0.0;  // diag(u0, u1) on bit a
+                        auto mul = [](double& xr, double& xi, double fr, double fi) {
+                            const double t = xr * fr - xi * fi;
+                            xi = xr * fi + xi * fr;
+                            xr = t;
+                        };
+                        for (size_t z = x; z < y; ++z) {
+                            const LoweredGate& l = gs[grp.second[z]];
+                            const double d0r = l.md[0], d0i = l.md[1], d1r = l.md[6], d1i = l.md[7];
+                            const bool tl = local_bit(l.tq) >= 0;
+                            if (tl) {  // local target, non-local control: diag(d0, d1) where the control is 1
+                                if (bit_of(l.cq)) {
+                                    mul(u0r, u0i, d0r, d0i);
+                                    mul(u1r, u1i, d1r, d1i);
+                                }
+                            } else {
+                                const int tv = bit_of(l.tq);
+                                const double fr = tv ? d1r : d0r, fi = tv ? d1i : d0i;
+                                if (l.cq >= 0 && local_bit(l.cq) >= 0) {  // local control: factor where it is 1
+                                    mul(u1r, u1i, fr, fi);
+                                } else if (l.cq < 0 || bit_of(l.cq)) {  // no local qubit: one factor
+                                    mul(u0r, u0i, fr, fi);
+                                    mul(u1r, u1i, fr, fi);
+                                }
+                            }
+                        }
+                        pool.push_back((float)u0r);
+                        pool.push_back((float)u0i);
+                        pool.push_back((float)u1r);
+                        pool.push_back((float)u1i);
+                    }
+                    table.push_back(d);
+                    x = y;
+                }
+            }
             k = e;
         }
         p.g1 = (int)table.size();
