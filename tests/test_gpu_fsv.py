@@ -270,3 +270,32 @@ def test_fsv_ghz_34_maximum_size(ctx):
     assert set(np.unique(shots)) <= {0, N - 1}
     del psi
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("n", [16, 19])
+def test_fsv_diagonal_runs_across_local_and_non_local_qubits(ctx, n):
+    """Runs of diagonal operations between Hadamard layers, built to hit every way the planner multiplies them
+    out: both qubits local (one table), a local target with a non-local control and the reverse (grouped by
+    the local bit, more than five non-local partners per bit so a group spans several tables), one-qubit phases
+    and CZ/CR pairs on non-local qubits only (a single factor per workgroup), and a lone diagonal."""
+    rng = np.random.default_rng(900 + n)
+    g = []
+    for layer in range(3):
+        g += [("H", (q,), None) for q in range(n)]
+        local_t = int(rng.integers(0, 6))
+        for c in rng.permutation(np.arange(8, n))[:9]:
+            g.append(("CR", (int(c), local_t), float(rng.uniform(0, 2 * math.pi))))  # non-local control
+            g.append(("CZ", (local_t + 1, int(c)), None))  # local control, non-local target
+        for q in rng.permutation(np.arange(0, 6))[:4]:
+            g.append(("RZ", (int(q),), float(rng.uniform(0, 2 * math.pi))))
+        for _ in range(6):
+            a, b = (int(x) for x in rng.choice(np.arange(12, n), 2, replace=False))
+            g.append(("CR", (a, b), float(rng.uniform(0, 2 * math.pi))))
+            g.append(("T", (a,), None))
+        g.append(("CZ", (0, 1), None))
+        g.append(("X", (layer,), None))
+        g.append(("S", (n - 1,), None))
+    psi0 = W.random_state(n, n + 1)
+    got, info = run_fsv(ctx, n, g, psi0)
+    ref = fsv.final_state(n, g, psi0)
+    assert np.linalg.norm(got - ref) <= bound(g), (np.linalg.norm(got - ref), bound(g), info)
