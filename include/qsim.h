@@ -436,12 +436,13 @@ qsim_status qsim_profile_read(qsim_ctx* ctx, qsim_kernel_stats* out);
  * planar complex64: 2^n float re values then 2^n float im values (8 * 2^n
  * bytes, 256-byte aligned, caller-owned); up to QSIM_FSV_MAX_QUBITS qubits.
  *
- * The library lowers each SWAP to three CNOTs and groups consecutive gates
- * into passes over the state.  A pass names 12 local qubits: qubits
- * 0..low_qubits-1 and n_high others; it holds only gates whose target is
- * local, or that are diagonal (Z, S, T, R, RZ and their controlled forms,
- * which need no local qubit); controls may be any qubit; a custom operation
- * needs its whole range local (its matrix is rounded to float32).  Each pass reads and
+ * The library groups consecutive gates into passes over the state.  A pass
+ * names 12 local qubits: qubits 0..low_qubits-1 and n_high others; it holds
+ * only gates whose target is local, or that are diagonal (Z, S, T, R, RZ and
+ * their controlled forms, which need no local qubit); controls may be any
+ * qubit; a SWAP needs both qubits local (it permutes amplitudes exactly); a
+ * custom operation needs its whole range local (its matrix is rounded to
+ * float32).  Each pass reads and
  * writes the whole state once (16 bytes per amplitude), whatever its gate
  * count.  For n <= 12 one pass holds every gate.  Gate matrices are the
  * float64 ones of the unitary path rounded once to float32; amplitude
@@ -453,7 +454,7 @@ typedef struct qsim_fsv_pass_info {
     int32_t low_qubits;             /* qubits 0..low_qubits-1 are local */
     int32_t n_high;                 /* further local qubits, ascending in high[] */
     int32_t high[QSIM_FSV_MAX_HIGH]; /* -1 past n_high */
-    int32_t first_op;               /* the pass's operations (a SWAP counts three) */
+    int32_t first_op;               /* the pass's gates: first_op .. first_op + n_ops - 1 */
     int32_t n_ops;
 } qsim_fsv_pass_info;
 

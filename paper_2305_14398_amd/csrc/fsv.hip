@@ -28,7 +28,8 @@
 // amplitudes, so they need no local target at all; when neither of their
 // qubits is a register bit, their factor is the same for a thread's 16
 // amplitudes and is folded into one per-thread phase that is applied once.
-// SWAP runs as three CNOTs, which permute amplitudes exactly.  A custom
+// SWAP needs both qubits local and is one LDS round trip that reads every
+// amplitude back from the index with the two bits exchanged (exact).  A custom
 // operation on m qubits (Section 5.2.2) needs its whole range local; it is
 // applied through LDS: every amplitude is written out, then each thread forms
 // its 16 outputs as sums of 2^m products with the operation's float32 matrix.
@@ -63,7 +64,7 @@ __device__ __forceinline__ void fsv_for16(F&& f) {
     fsv_for16_impl(f, std::make_integer_sequence<int, 16>{});
 }
 
-enum : int32_t { FSV_GENERAL = 0, FSV_DIAG = 1, FSV_DENSE = 2, FSV_TABLE = 3, FSV_PHASE = 4 };
+enum : int32_t { FSV_GENERAL = 0, FSV_DIAG = 1, FSV_DENSE = 2, FSV_TABLE = 3, FSV_PHASE = 4, FSV_SWAP = 5 };
 constexpr int kFsvPhaseBits = 5;  // non-local qubits per FSV_PHASE table (2^5 entries)
 
 struct FsvGate {
@@ -83,7 +84,7 @@ struct FsvPass {
     int32_t nh;  // local bits L..L+nh-1 are qubits high[0..nh-1], ascending
     int32_t high[kFsvMaxHigh];
     int32_t g0, g1;  // the pass's records in the plan's table
-    int32_t op0, op1;  // the operations (SWAP = three) the pass covers
+    int32_t op0, op1;  // the operations the pass covers
 };
 
 namespace {
@@ -336,6 +337,33 @@ __device__ __forceinline__ void fsv_relayout(f32x16& ar_out, f32x16& ai_out, int
     ai_out = ai;
 }
 
+// SWAP of local bits a and b: one LDS round trip in the current layout, each
+// amplitude read back from the index with those two bits exchanged.
+__device__ __forceinline__ void fsv_swap_bits(f32x16& ar_out, f32x16& ai_out, int t, int cur, int a, int b,
+                                              float* s_re, float* s_im) {
+    f32x16 ar = ar_out, ai = ai_out;  // value copies: the caller sees whole-vector accesses only
+    __syncthreads();  // earlier readers of the buffer are done
+    const int jt = fsv_thread_bits(t, cur), sh = 4 * cur;
+    fsv_for16([&](auto I_) {
+        constexpr int r = decltype(I_)::value;
+        const int a_ = fsv_swz(jt | (r << sh));
+        s_re[a_] = ar[r];
+        s_im[a_] = ai[r];
+    });
+    __syncthreads();
+    const int both = (1 << a) | (1 << b);
+    fsv_for16([&](auto I_) {
+        constexpr int r = decltype(I_)::value;
+        int j = jt | (r << sh);
+        if (((j >> a) ^ (j >> b)) & 1) j ^= both;
+        const int a_ = fsv_swz(j);
+        ar[r] = s_re[a_];
+        ai[r] = s_im[a_];
+    });
+    ar_out = ar;
+    ai_out = ai;
+}
+
 __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const FsvGate* __restrict__ gates,
                                                       const float* __restrict__ pool, float* __restrict__ re,
                                                       float* __restrict__ im) {
@@ -441,6 +469,11 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
         if (g.kind == FSV_DENSE) {
             fsv_flush(ar, ai, lpr, lpi, lp_pending);
             fsv_dense(ar, ai, t, cur, g, pool, s_re, s_im);
+            continue;
+        }
+        if (g.kind == FSV_SWAP) {
+            fsv_flush(ar, ai, lpr, lpi, lp_pending);
+            fsv_swap_bits(ar, ai, t, cur, g.tloc, g.cloc, s_re, s_im);
             continue;
         }
         if (g.kind == FSV_GENERAL) {
@@ -732,18 +765,12 @@ void lower(const qsim_gate* gates, int n_gates, std::vector<LoweredGate>& out) {
             out.push_back(l);
             continue;
         }
-        if (g.kind == QSIM_SWAP) {
-            const float x[8] = {0, 0, 1, 0, 1, 0, 0, 0};
-            const int a = g.target, b = g.control;
-            for (int rep = 0; rep < 3; ++rep) {
-                LoweredGate l{};
-                l.kind = FSV_GENERAL;
-                l.tq = rep == 1 ? a : b;
-                l.cq = rep == 1 ? b : a;
-                std::copy(x, x + 8, l.m);
-                std::copy(x, x + 8, l.md);
-                out.push_back(l);
-            }
+        if (g.kind == QSIM_SWAP) {  // a permutation of two local bits
+            LoweredGate l{};
+            l.kind = FSV_SWAP;
+            l.tq = g.target;
+            l.cq = g.control;
+            out.push_back(l);
             continue;
         }
         double m[8];
@@ -770,9 +797,11 @@ int fit_low(uint64_t targets) {
     return -1;
 }
 
-// Qubits a gate needs local: the target of a non-diagonal 2x2, the whole range of a dense operation.
+// Qubits a gate needs local: the target of a non-diagonal 2x2, both qubits of a SWAP, the whole range of a
+// dense operation.
 uint64_t local_need(const LoweredGate& l) {
     if (l.kind == FSV_GENERAL) return (uint64_t)1 << l.tq;
+    if (l.kind == FSV_SWAP) return ((uint64_t)1 << l.tq) | ((uint64_t)1 << l.cq);
     if (l.kind == FSV_DENSE) return (((uint64_t)1 << l.width) - 1) << l.tq;
     return 0;
 }

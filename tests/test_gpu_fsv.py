@@ -32,7 +32,7 @@ def ctx():
 
 
 def n_ops(gates):
-    return sum(3 if g[0] == "SWAP" else 1 for g in gates)
+    return len(gates)
 
 
 def bound(gates):
@@ -217,7 +217,7 @@ def custom_bound(gates):
             D = 1 << len(g[1])
             total += 2 * (D + 2) * math.sqrt(D)
         else:
-            total += 8 * (3 if g[0] == "SWAP" else 1)
+            total += 8
     return total * U32
 
 

@@ -247,12 +247,12 @@ def _check_schedule(n, gates):
     sched = B.qsim_fsv_schedule(n, gates)
     ops = []
     for nm, qs, th in gates:
-        if nm == "SWAP":
-            ops += [("X", qs[0]), ("X", qs[1]), ("X", qs[0])]
-        elif len(qs) == 1:
-            ops.append((nm, qs[0]))
-        else:
-            ops.append((nm, qs[1]))
+        if len(qs) == 1:
+            ops.append((nm, qs))
+        elif nm == "SWAP":  # a permutation of two bits: both local
+            ops.append((nm, qs))
+        else:  # controlled: the target must be local, the control may be anywhere
+            ops.append((nm, qs[1:]))
     nxt = 0
     for low, highs, first, cnt in sched:
         assert first == nxt and cnt >= 1
@@ -263,9 +263,9 @@ def _check_schedule(n, gates):
             assert 6 <= low <= 12 and len(highs) == 12 - low
             assert list(highs) == sorted(set(highs)) and all(low <= q < n for q in highs)
         local = set(range(low)) | set(highs)
-        for nm, t in ops[first:first + cnt]:
+        for nm, need in ops[first:first + cnt]:
             diagonal = nm in ("Z", "S", "T", "R", "RZ", "CZ", "CR")
-            assert diagonal or t in local, (nm, t, low, highs)
+            assert diagonal or set(need) <= local, (nm, need, low, highs)
     assert nxt == len(ops)
     return sched
 
@@ -334,7 +334,7 @@ def test_fsv_schedule_keeps_custom_ranges_local():
     sched = B.qsim_fsv_schedule(n, lg)
     ops = []
     for x in lg:
-        ops += [x] * (3 if x[0] == "SWAP" else 1)
+        ops.append(x)
     for low, highs, first, cnt in sched:
         local = set(range(low)) | set(highs)
         for x in ops[first:first + cnt]:
