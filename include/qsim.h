@@ -454,15 +454,20 @@ typedef struct qsim_fsv_pass_info {
     int32_t low_qubits;             /* qubits 0..low_qubits-1 are local */
     int32_t n_high;                 /* further local qubits, ascending in high[] */
     int32_t high[QSIM_FSV_MAX_HIGH]; /* -1 past n_high */
-    int32_t first_op;               /* the pass's gates: first_op .. first_op + n_ops - 1 */
+    int32_t first_op;               /* the pass's gates: order[first_op .. first_op + n_ops) */
     int32_t n_ops;
 } qsim_fsv_pass_info;
 
 /* Host only (no device, no context): the pass schedule of a gate list.
  * Writes min(capacity, passes) records and *n_passes; QSIM_E_RANGE if
- * capacity > 0 and the schedule needs more records (capacity 0 just counts). */
+ * capacity > 0 and the schedule needs more records (capacity 0 just counts).
+ * A gate must run after every earlier gate that shares a qubit with it unless
+ * both are diagonal; within that rule a pass may take gates from further on in
+ * the circuit, so passes hold ranges of an execution order rather than of the
+ * gate list.  order (NULL, or n_gates entries) receives that order: gate
+ * indices, pass by pass. */
 qsim_status qsim_fsv_schedule(int n_qubits, const qsim_gate* gates, int n_gates, qsim_fsv_pass_info* passes,
-                              int capacity, int* n_passes);
+                              int capacity, int* n_passes, int32_t* order);
 /* Validates the gates, schedules them and uploads the operation table to the
  * context's device (a synchronous copy; the plan owns that memory).  The gate
  * array may be freed on return. */

@@ -148,7 +148,7 @@ def lib() -> ctypes.CDLL:
         "qsim_register_unitary": (i32, [ctypes.c_char_p, i32, ctypes.POINTER(dbl), ctypes.POINTER(i32)]),
         "qsim_find_unitary": (i32, [ctypes.c_char_p, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "qsim_fsv_schedule": (i32, [i32, vp, i32, ctypes.POINTER(qsim_fsv_pass_info), i32,
-                                    ctypes.POINTER(i32)]),
+                                    ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "qsim_fsv_plan_create": (i32, [vp, i32, vp, i32, ctypes.POINTER(vp)]),
         "qsim_fsv_plan_info": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "qsim_fsv_plan_destroy": (i32, [vp]),
@@ -521,14 +521,17 @@ def qsim_sample(ctx, n_qubits: int, d_prob, d_uniform, shots: int, d_out, stream
 
 # --- full-state-vector simulation ---
 
-def qsim_fsv_schedule(n_qubits: int, gates) -> list:
-    """Pass schedule of a gate list (host only): [(low_qubits, high_qubits, first_op, n_ops), ...]."""
+def qsim_fsv_schedule(n_qubits: int, gates, with_order: bool = False):
+    """Pass schedule of a gate list (host only): [(low_qubits, high_qubits, first_op, n_ops), ...], and with
+    with_order the execution order (gate indices; pass p runs order[first_op:first_op + n_ops])."""
     arr, count = gate_array(gates)
     n = ctypes.c_int32(0)
-    _check(lib().qsim_fsv_schedule(n_qubits, arr, count, None, 0, ctypes.byref(n)), "qsim_fsv_schedule")
+    _check(lib().qsim_fsv_schedule(n_qubits, arr, count, None, 0, ctypes.byref(n), None), "qsim_fsv_schedule")
     buf = (qsim_fsv_pass_info * max(n.value, 1))()
-    _check(lib().qsim_fsv_schedule(n_qubits, arr, count, buf, n.value, ctypes.byref(n)), "qsim_fsv_schedule")
-    return [(p.low_qubits, tuple(p.high[:p.n_high]), p.first_op, p.n_ops) for p in buf[:n.value]]
+    order = (ctypes.c_int32 * max(count, 1))()
+    _check(lib().qsim_fsv_schedule(n_qubits, arr, count, buf, n.value, ctypes.byref(n), order), "qsim_fsv_schedule")
+    passes = [(p.low_qubits, tuple(p.high[:p.n_high]), p.first_op, p.n_ops) for p in buf[:n.value]]
+    return (passes, [int(order[i]) for i in range(count)]) if with_order else passes
 
 
 class FsvPlan:

@@ -37,6 +37,7 @@
 // Gate entries are the float64 matrices of the unitary path rounded once to
 // float32; amplitude arithmetic is float32 with fused multiply-adds.
 #include <algorithm>
+#include <set>
 #include <utility>
 #include <vector>
 
@@ -818,30 +819,91 @@ int pool_offset(int32_t op, int width, std::vector<float>& pool, std::vector<std
     return off;
 }
 
+// Qubits an operation touches (its whole span for a dense operation).
+uint64_t op_qubits(const LoweredGate& l) {
+    if (l.kind == FSV_DENSE) return (((uint64_t)1 << l.width) - 1) << l.tq;
+    return ((uint64_t)1 << l.tq) | (l.cq >= 0 ? (uint64_t)1 << l.cq : 0);
+}
+
+// Passes over a gate list.  An operation must follow every earlier one that
+// shares a qubit with it, unless both are diagonal (they commute).  A pass is
+// filled by one sweep over the operations whose predecessors are all done, in
+// circuit order, taking each one whose local qubits still fit; operations that
+// become ready during the sweep are considered in the same sweep.  So a pass may
+// take gates from later layers on its local qubits while a gate on a qubit that
+// is not local waits for a later pass.  exec_order (optional) receives the
+// operations pass by pass.
 void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass>& passes,
-                  std::vector<FsvGate>& table, std::vector<float>& pool) {
+                  std::vector<FsvGate>& table, std::vector<float>& pool, std::vector<int>* exec_order = nullptr) {
     passes.clear();
     table.clear();
     pool.clear();
+    if (exec_order) exec_order->clear();
     std::vector<std::pair<int32_t, int>> seen;
-    size_t i = 0;
-    while (i < gs.size()) {
+    const int m_all = (int)gs.size();
+    std::vector<std::vector<int>> succ_all(m_all);
+    std::vector<int> indeg_all(m_all, 0);
+    {
+        std::vector<int> last_nd(64, -1), mark(m_all, -1);
+        std::vector<std::vector<int>> diag_since(64);
+        for (int b = 0; b < m_all; ++b) {
+            const uint64_t qb = op_qubits(gs[b]);
+            const bool dg = gs[b].kind == FSV_DIAG;
+            auto dep = [&](int a) {
+                if (a >= 0 && mark[a] != b) {
+                    mark[a] = b;
+                    succ_all[a].push_back(b);
+                    ++indeg_all[b];
+                }
+            };
+            for (int x = 0; x < n; ++x) {
+                if (!((qb >> x) & 1)) continue;
+                dep(last_nd[x]);
+                if (!dg)
+                    for (int a : diag_since[x]) dep(a);
+            }
+            for (int x = 0; x < n; ++x) {
+                if (!((qb >> x) & 1)) continue;
+                if (dg) {
+                    diag_since[x].push_back(b);
+                } else {
+                    last_nd[x] = b;
+                    diag_since[x].clear();
+                }
+            }
+        }
+    }
+    std::set<int> ready;
+    for (int b = 0; b < m_all; ++b)
+        if (indeg_all[b] == 0) ready.insert(b);
+    int executed = 0;
+    while (!ready.empty()) {
         FsvPass p{};
         uint64_t T = 0;
-        size_t j = i;
+        int L = n <= kFsvLocal ? n : kFsvLocal;
+        std::vector<int> pass_ops;
+        for (auto it = ready.begin(); it != ready.end() && (int)pass_ops.size() < kFsvMaxOps;) {
+            const int b = *it;
+            const uint64_t T2 = T | local_need(gs[b]);
+            if (n > kFsvLocal) {
+                const int L2 = fit_low(T2);
+                if (L2 < 0) {
+                    ++it;
+                    continue;
+                }
+                L = L2;
+            }
+            T = T2;
+            pass_ops.push_back(b);
+            ready.erase(it);
+            for (int c : succ_all[b])
+                if (--indeg_all[c] == 0) ready.insert(c);
+            it = ready.upper_bound(b);  // successors (larger indices) join this sweep
+        }
         if (n <= kFsvLocal) {
             p.L = n;
             p.nh = 0;
-            j = std::min(gs.size(), i + kFsvMaxOps);
         } else {
-            int L = kFsvLocal;
-            for (; j < gs.size() && j - i < (size_t)kFsvMaxOps; ++j) {
-                const uint64_t T2 = T | local_need(gs[j]);
-                const int L2 = fit_low(T2);
-                if (L2 < 0) break;
-                T = T2;
-                L = L2;
-            }
             p.L = L;
             p.nh = kFsvLocal - L;
             std::vector<int> hs;
@@ -852,6 +914,10 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
             std::sort(hs.begin(), hs.end());
             for (int h = 0; h < p.nh; ++h) p.high[h] = hs[h];
         }
+        p.op0 = executed;
+        executed += (int)pass_ops.size();
+        p.op1 = executed;
+        if (exec_order) exec_order->insert(exec_order->end(), pass_ops.begin(), pass_ops.end());
         auto local_bit = [&](int q) {
             if (q < 0) return -1;
             if (q < p.L) return q;
@@ -860,8 +926,6 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
             return -1;
         };
         p.g0 = (int)table.size();
-        p.op0 = (int)i;
-        p.op1 = (int)j;
         auto record = [&](const LoweredGate& l) {
             FsvGate d{};
             d.kind = l.kind;
@@ -883,13 +947,12 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
         // current register layout, else the earliest ready one.
         std::vector<size_t> order;
         {
-            const size_t m = j - i;
+            const size_t m = pass_ops.size();
             std::vector<uint64_t> qm(m);
             std::vector<char> dg(m);
             for (size_t a = 0; a < m; ++a) {
-                const LoweredGate& l = gs[i + a];
-                qm[a] = l.kind == FSV_DENSE ? (((uint64_t)1 << l.width) - 1) << l.tq
-                                            : ((uint64_t)1 << l.tq) | (l.cq >= 0 ? (uint64_t)1 << l.cq : 0);
+                const LoweredGate& l = gs[pass_ops[a]];
+                qm[a] = op_qubits(l);
                 dg[a] = l.kind == FSV_DIAG;
             }
             std::vector<std::vector<int>> succ(m);
@@ -906,7 +969,7 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
                 int pick = -1, pick_general = -1;
                 for (size_t a = 0; a < m; ++a) {
                     if (done[a] || indeg[a] != 0) continue;
-                    const LoweredGate& l = gs[i + a];
+                    const LoweredGate& l = gs[pass_ops[a]];
                     if (l.kind != FSV_GENERAL) {
                         pick = (int)a;
                         break;
@@ -919,10 +982,10 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
                 }
                 if (pick < 0) {
                     pick = pick_general;
-                    cur = local_bit(gs[i + pick].tq) >> 2;
+                    cur = local_bit(gs[pass_ops[pick]].tq) >> 2;
                 }
                 done[pick] = 1;
-                order.push_back(i + pick);
+                order.push_back((size_t)pass_ops[pick]);
                 for (int b : succ[pick]) --indeg[b];
             }
         }
@@ -1064,7 +1127,6 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
         }
         p.g1 = (int)table.size();
         passes.push_back(p);
-        i = j;
     }
 }
 
@@ -1095,7 +1157,7 @@ qsim_status fsv_check(int n_qubits, const qsim_gate* gates, int n_gates) {
 extern "C" {
 
 qsim_status qsim_fsv_schedule(int n_qubits, const qsim_gate* gates, int n_gates, qsim_fsv_pass_info* passes,
-                              int capacity, int* n_passes) {
+                              int capacity, int* n_passes, int32_t* order) {
     qsim_status s = fsv_check(n_qubits, gates, n_gates);
     if (s != QSIM_OK) return s;
     if (n_passes == nullptr) return fail(QSIM_E_INVALID, "n_passes is NULL");
@@ -1105,8 +1167,11 @@ qsim_status qsim_fsv_schedule(int n_qubits, const qsim_gate* gates, int n_gates,
     std::vector<FsvPass> ps;
     std::vector<FsvGate> table;
     std::vector<float> pool;
-    fsv_schedule(n_qubits, gs, ps, table, pool);
+    std::vector<int> exec;
+    fsv_schedule(n_qubits, gs, ps, table, pool, &exec);
     *n_passes = (int)ps.size();
+    if (order)
+        for (size_t i = 0; i < exec.size(); ++i) order[i] = exec[i];
     if ((int)ps.size() > capacity && capacity > 0)
         return fail(QSIM_E_RANGE, "%d passes do not fit the buffer of %d", (int)ps.size(), capacity);
     for (int i = 0; i < (int)ps.size() && i < capacity; ++i) {

@@ -242,17 +242,20 @@ def test_serving_validation_without_device():
 
 # --- full-state-vector pass schedule (host only) ---------------------------------------------
 
+DIAGONAL = ("Z", "S", "T", "R", "RZ", "CZ", "CR")
+
+
 def _check_schedule(n, gates):
-    from oracle import gates as OG
-    sched = B.qsim_fsv_schedule(n, gates)
-    ops = []
-    for nm, qs, th in gates:
-        if len(qs) == 1:
-            ops.append((nm, qs))
-        elif nm == "SWAP":  # a permutation of two bits: both local
-            ops.append((nm, qs))
-        else:  # controlled: the target must be local, the control may be anywhere
-            ops.append((nm, qs[1:]))
+    """Passes cover the gates once, in an order where every gate follows each earlier gate sharing a qubit
+    with it (unless both are diagonal), and every gate's target (both qubits of a SWAP) is local to its pass."""
+    sched, order = B.qsim_fsv_schedule(n, gates, with_order=True)
+    assert sorted(order) == list(range(len(gates)))
+    pos = {g: i for i, g in enumerate(order)}
+    for b, (nb, qb, _) in enumerate(gates):
+        for a in range(b):
+            na, qa, _ = gates[a]
+            if set(qa) & set(qb) and not (na in DIAGONAL and nb in DIAGONAL):
+                assert pos[a] < pos[b], (a, b, gates[a], gates[b])
     nxt = 0
     for low, highs, first, cnt in sched:
         assert first == nxt and cnt >= 1
@@ -263,10 +266,11 @@ def _check_schedule(n, gates):
             assert 6 <= low <= 12 and len(highs) == 12 - low
             assert list(highs) == sorted(set(highs)) and all(low <= q < n for q in highs)
         local = set(range(low)) | set(highs)
-        for nm, need in ops[first:first + cnt]:
-            diagonal = nm in ("Z", "S", "T", "R", "RZ", "CZ", "CR")
-            assert diagonal or set(need) <= local, (nm, need, low, highs)
-    assert nxt == len(ops)
+        for gi in order[first:first + cnt]:
+            nm, qs, _ = gates[gi]
+            need = () if nm in DIAGONAL else (qs if nm == "SWAP" or len(qs) == 1 else qs[1:])
+            assert set(need) <= local, (nm, qs, low, highs)
+    assert nxt == len(gates)
     return sched
 
 
@@ -278,6 +282,20 @@ def test_fsv_schedule_invariants(n):
     sched = _check_schedule(n, gates)
     if n <= 12:
         assert len(sched) == 1
+
+
+def test_fsv_schedule_runs_ahead_on_local_qubits():
+    # after H on 13 qubits (12 fit one pass), an X on qubit 0 does not wait for the 13th H
+    n = 20
+    gates = [("H", (q,), None) for q in range(13)] + [("X", (0,), None)]
+    sched, order = B.qsim_fsv_schedule(n, gates, with_order=True)
+    assert len(sched) == 2
+    assert 13 in order[:sched[0][3]] and 12 not in order[:sched[0][3]]
+    # a gate that shares a qubit with a waiting one waits too
+    gates = [("H", (q,), None) for q in range(13)] + [("CNOT", (12, 0), None), ("X", (0,), None)]
+    sched, order = B.qsim_fsv_schedule(n, gates, with_order=True)
+    assert order.index(12) < order.index(13) < order.index(14)
+    _check_schedule(n, gates)
 
 
 def test_fsv_schedule_counts():
@@ -331,12 +349,9 @@ def test_fsv_schedule_keeps_custom_ranges_local():
     n = 24
     g = W.with_custom_ops(W.gate_tuples(W.random_layers(n, 2, np.random.default_rng(3))), n, [2, 3, 6, 6, 1], 77)
     lg = lib_gates(g)
-    sched = B.qsim_fsv_schedule(n, lg)
-    ops = []
-    for x in lg:
-        ops.append(x)
+    sched, order = B.qsim_fsv_schedule(n, lg, with_order=True)
     for low, highs, first, cnt in sched:
         local = set(range(low)) | set(highs)
-        for x in ops[first:first + cnt]:
+        for x in (lg[i] for i in order[first:first + cnt]):
             if x[0] == "CUSTOM":
                 assert set(x[1]) <= local, (x[1], low, highs)
