@@ -361,6 +361,7 @@ typedef struct qsim_serve_config {
 } qsim_serve_config;
 
 #define QSIM_REQ_DRIFT_PROBE 1u  /* also compute the probe drift (qsim_unitarity_drift_probe) */
+#define QSIM_REQ_DRIFT_FULL 2u   /* instead, the full float64 check (qsim_unitarity_drift): 8 N^3 / 2 flops */
 
 typedef struct qsim_request {
     int32_t n_qubits;
@@ -369,7 +370,7 @@ typedef struct qsim_request {
     void* d_psi;             /* out: final state, planar complex64 (2N floats); required */
     const void* d_psi0;      /* initial state (planar complex64) or NULL for |0...0> */
     void* d_U;               /* out: circuit unitary, row-major planar complex64, or NULL (kept in the arena) */
-    uint32_t flags;          /* QSIM_REQ_DRIFT_PROBE */
+    uint32_t flags;          /* QSIM_REQ_DRIFT_PROBE or QSIM_REQ_DRIFT_FULL (not both), or 0 */
     uint32_t reserved;       /* must be 0 */
 } qsim_request;              /* d_psi, d_psi0 and d_U must stay valid until the request is polled done */
 
@@ -377,8 +378,8 @@ typedef struct qsim_result {
     int32_t status;          /* QSIM_PENDING, QSIM_OK, QSIM_E_DEVICE or QSIM_E_CANCELLED */
     int32_t n_steps;
     double norm2;            /* float64 sum |psi_i|^2 */
-    double drift_max;        /* probe drift max |d_j| (-1 if not requested) */
-    double drift_l2;         /* probe drift |d|_2 (-1 if not requested) */
+    double drift_max;        /* probe: max |d_j|; full: max |D_ij| (-1 if not requested) */
+    double drift_l2;         /* probe: |d|_2; full: ||D||_F / sqrt(N) (-1 if not requested) */
     uint64_t t_submit_ns;    /* steady clock: submitted, admitted, results observed by the engine */
     uint64_t t_start_ns;
     uint64_t t_done_ns;

@@ -66,6 +66,7 @@ class qsim_circuit_desc(ctypes.Structure):
 QSIM_BATCH_GRAPH = 1
 QSIM_SERVE_CONTINUOUS, QSIM_SERVE_FIFO = 0, 1
 QSIM_REQ_DRIFT_PROBE = 1
+QSIM_REQ_DRIFT_FULL = 2
 QSIM_E_CANCELLED = -7
 STATUS_NAMES[-7] = "QSIM_E_CANCELLED"
 
@@ -489,10 +490,14 @@ def qsim_serve_stop(ctx) -> None:
     _check(lib().qsim_serve_stop(_h(ctx)), "qsim_serve_stop")
 
 
-def qsim_submit(ctx, n_qubits: int, gates: Sequence, d_psi, d_psi0=None, d_U=None, probe: bool = True) -> int:
+def qsim_submit(ctx, n_qubits: int, gates: Sequence, d_psi, d_psi0=None, d_U=None, probe: bool = True,
+                full_drift: bool = False, flags: Optional[int] = None) -> int:
+    """probe: the probe drift check; full_drift: the full float64 check instead; flags: raw request flags."""
     arr, ng = gate_array(gates)
+    if flags is None:
+        flags = QSIM_REQ_DRIFT_FULL if full_drift else (QSIM_REQ_DRIFT_PROBE if probe else 0)
     req = qsim_request(n_qubits, ng, ctypes.cast(arr, ctypes.POINTER(qsim_gate)), _ptr(d_psi), _ptr(d_psi0),
-                       _ptr(d_U), QSIM_REQ_DRIFT_PROBE if probe else 0, 0)
+                       _ptr(d_U), flags, 0)
     rid = ctypes.c_uint64()
     _check(lib().qsim_submit(_h(ctx), ctypes.byref(req), ctypes.byref(rid)), "qsim_submit")
     return int(rid.value)

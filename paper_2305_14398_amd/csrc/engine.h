@@ -51,6 +51,7 @@ class Engine {
     double* d_results_ = nullptr;  // 4 doubles per slot: norm2, probe max, probe l2, pad
     double* h_results_ = nullptr;
     double* d_probe_ = nullptr;
+    double* d_drift_part_ = nullptr;  // partial sums of the full drift check (its own: the context's are the caller's)
     int nslots_ = 0;
     int grid_expand_ = 0, grid_gemm_ = 0;
     int table_ = 0;

@@ -132,6 +132,7 @@ qsim_status Engine::init() {
     if (e == hipSuccess) e = hipMalloc(&d_results_, nslots_ * 4 * sizeof(double));
     if (e == hipSuccess) e = hipHostMalloc(&h_results_, nslots_ * 4 * sizeof(double), hipHostMallocDefault);
     if (e == hipSuccess) e = hipMalloc(&d_probe_, kProbeScratchDoubles * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&d_drift_part_, 2 * kDriftMaxPartials * sizeof(double));
     if (e != hipSuccess) return device_fail("serving engine setup", e);
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx_->device) != hipSuccess || cus <= 0)
@@ -162,6 +163,7 @@ Engine::~Engine() {
     if (d_results_) (void)hipFree(d_results_);
     if (h_results_) (void)hipHostFree(h_results_);
     if (d_probe_) (void)hipFree(d_probe_);
+    if (d_drift_part_) (void)hipFree(d_drift_part_);
     for (hipEvent_t ev : event_pool_) (void)hipEventDestroy(ev);
     if (stream_) (void)hipStreamDestroy(stream_);
     for (auto& kv : reqs_) delete kv.second;
@@ -169,7 +171,10 @@ Engine::~Engine() {
 
 qsim_status Engine::submit(const qsim_request& r, uint64_t* id_out) {
     if (!valid_n(r.n_qubits)) return fail(QSIM_E_RANGE, "n_qubits %d outside 1..%d", r.n_qubits, QSIM_MAX_QUBITS);
-    if (r.reserved != 0 || (r.flags & ~QSIM_REQ_DRIFT_PROBE)) return fail(QSIM_E_INVALID, "unknown request flags");
+    if (r.reserved != 0 || (r.flags & ~(QSIM_REQ_DRIFT_PROBE | QSIM_REQ_DRIFT_FULL)))
+        return fail(QSIM_E_INVALID, "unknown request flags");
+    if ((r.flags & QSIM_REQ_DRIFT_PROBE) && (r.flags & QSIM_REQ_DRIFT_FULL))
+        return fail(QSIM_E_INVALID, "request flags: the probe and the full drift check are exclusive");
     if (r.d_psi == nullptr || !aligned(r.d_psi)) return fail(QSIM_E_INVALID, "d_psi is NULL or not 256-byte aligned");
     if ((r.d_psi0 && !aligned(r.d_psi0)) || (r.d_U && !aligned(r.d_U)))
         return fail(QSIM_E_INVALID, "d_psi0 / d_U not 256-byte aligned");
@@ -303,13 +308,15 @@ void Engine::admit_locked() {
     }
 }
 
-// Stage 6 and the probe for a finished chain, then the copy of its results.
+// Stage 6 and the drift check (probe or full) for a finished chain, then the copy of its results.
 hipError_t Engine::finish_launches(Req* q) {
     double* dres = d_results_ + 4 * q->slot;
     hipError_t e = launch_apply_state(q->n, static_cast<const float*>(q->cc.U), static_cast<const float*>(q->d_psi0),
                                       static_cast<float*>(q->d_psi), nullptr, dres, stream_);
     if (e == hipSuccess && (q->flags & QSIM_REQ_DRIFT_PROBE))
         e = launch_drift_probe(q->n, static_cast<const float*>(q->cc.U), d_probe_, dres + 1, stream_);
+    if (e == hipSuccess && (q->flags & QSIM_REQ_DRIFT_FULL))
+        e = launch_drift(q->n, static_cast<const float*>(q->cc.U), d_drift_part_, kDriftMaxPartials, dres + 1, stream_);
     if (e == hipSuccess)
         e = hipMemcpyAsync(h_results_ + 4 * q->slot, dres, 4 * sizeof(double), hipMemcpyDeviceToHost, stream_);
     return e;
@@ -322,7 +329,7 @@ void Engine::complete(Inflight& f, hipError_t err) {
         if (err == hipSuccess) {
             const double* r = h_results_ + 4 * q->slot;
             q->res.norm2 = r[0];
-            if (q->flags & QSIM_REQ_DRIFT_PROBE) {
+            if (q->flags & (QSIM_REQ_DRIFT_PROBE | QSIM_REQ_DRIFT_FULL)) {
                 q->res.drift_max = r[1];
                 q->res.drift_l2 = r[2];
             }

@@ -232,3 +232,38 @@ def test_full_served_config_sampled_against_oracle(ctx):
         c = circuits[i]
         ref = fsv.final_state(c.n, W.gate_tuples(c))
         assert metrics.fidelity(out[i][0], ref) >= 1 - 1e-6, (i, c.family, c.n)
+
+
+def test_served_full_drift_equals_the_synchronous_check(ctx):
+    """QSIM_REQ_DRIFT_FULL: the engine runs the full float64 check on each finished unitary; its values equal
+    qsim_unitarity_drift of the same returned U (the same kernels and partial counts, so bit for bit), and the
+    probe and full flags are exclusive."""
+    circuits = W.batch_mixed(12, seed=31, n_lo=4, n_hi=11, d_lo=3, d_hi=10)
+    arena = torch.empty(2 << 30, dtype=torch.uint8, device=G.DEV)
+    psis = [torch.empty(2 << c.n, dtype=torch.float32, device=G.DEV) for c in circuits]
+    Us = [G.planar(c.n) for c in circuits]
+    B.qsim_serve_start(ctx, B.QSIM_FP32_3M, arena)
+    try:
+        with pytest.raises(B.QsimError, match="exclusive"):
+            B.qsim_submit(ctx, circuits[0].n, circuits[0].gates, psis[0],
+                          flags=B.QSIM_REQ_DRIFT_PROBE | B.QSIM_REQ_DRIFT_FULL)
+        ids = [B.qsim_submit(ctx, c.n, c.gates, p, d_U=U, full_drift=True) for c, p, U in zip(circuits, psis, Us)]
+        results = {}
+        t0 = time.time()
+        while len(results) < len(ids):
+            for i in ids:
+                if i not in results:
+                    r = B.qsim_poll(ctx, i)
+                    if r is not None:
+                        results[i] = r
+            assert time.time() - t0 < 120, "serving did not finish"
+            time.sleep(0.001)
+    finally:
+        B.qsim_serve_stop(ctx)
+    G.sync()
+    for c, i, U in zip(circuits, ids, Us):
+        r = results[i]
+        assert r["status"] == B.QSIM_OK
+        mx, fro = B.qsim_unitarity_drift(ctx, c.n, U)
+        assert (r["drift_max"], r["drift_l2"]) == (mx, fro), (c.family, c.n)
+        assert mx <= 1e-5
