@@ -114,8 +114,13 @@ def bench_batched(B, ctx, torch, count: int, seed: int, prec_name: str, reps: in
     }
 
 
+# Drift checks a served request can ask for.
+DRIFT_TEXT = {"full": "drift ||U^H U - I|| (max and Frobenius / sqrt(N))",
+              "probe": "probe drift ||U^H (U x) - x|| for a fixed unit-modulus x"}
+
+
 def replay_trace(B, ctx, torch, trace, prec: int, mode: int, arena, max_active: int, policy: int = 0,
-                 budget: float = 2.0, aging: float = 0.0):
+                 budget: float = 2.0, aging: float = 0.0, drift: str = "full"):
     import threading
     dev = torch.device("cuda:0")
     psis = [torch.empty(2 << c.n, dtype=torch.float32, device=dev) for _, c in trace]
@@ -133,7 +138,7 @@ def replay_trace(B, ctx, torch, trace, prec: int, mode: int, arena, max_active: 
                 if now >= target:
                     break
                 time.sleep(min(0.002, (target - now) / 1e9))
-            ids[i] = B.qsim_submit(ctx, c.n, c.gates, psis[i], probe=True)
+            ids[i] = B.qsim_submit(ctx, c.n, c.gates, psis[i], probe=drift == "probe", full_drift=drift == "full")
 
     th = threading.Thread(target=submitter)
     th.start()
@@ -157,37 +162,38 @@ def replay_trace(B, ctx, torch, trace, prec: int, mode: int, arena, max_active: 
     span = (end - t0) / 1e9
     flops = sum(flops_of(B, c) for _, c in trace)
     bad = sum(1 for r in results.values() if r["status"] != 0)
-    drift = max(r["drift_max"] for r in results.values())
+    max_drift = max(r["drift_max"] for r in results.values())
     q = lambda p: lat[min(len(lat) - 1, int(round(p * (len(lat) - 1))))]
     return {"p50_ms": round(q(0.50), 2), "p99_ms": round(q(0.99), 2), "max_ms": round(lat[-1], 2),
             "throughput_req_per_s": round(len(trace) / span, 2), "achieved_tflops": round(flops / span / 1e12, 2),
-            "makespan_s": round(span, 3), "failed": bad, "max_probe_drift": drift,
+            "makespan_s": round(span, 3), "failed": bad, "drift_check": drift, "max_drift": max_drift,
             "peak_active": stats["peak_active"], "arena_high_water_gib": round(stats["arena_high_water"] / 2**30, 2)}
 
 
 def bench_served(B, ctx, torch, count: int, rate: float, seed: int, prec_name: str, arena_gib: int,
-                 aging: float = 100.0):
+                 aging: float = 100.0, drift: str = "full"):
     from paper_2305_14398_amd import workloads as W
     prec = B.PRECISIONS[prec_name]
     trace = W.poisson_trace(count, rate, seed, n_lo=6, n_hi=13, d_lo=10, d_hi=40)
     arena = torch.empty(arena_gib << 30, dtype=torch.uint8, device=torch.device("cuda:0"))
     B.qsim_autotune(ctx, prec, 7, 13)
     offered = sum(flops_of(B, c) for _, c in trace) / trace[-1][0]
-    cont = replay_trace(B, ctx, torch, trace, prec, B.QSIM_SERVE_CONTINUOUS, arena, 64)
+    cont = replay_trace(B, ctx, torch, trace, prec, B.QSIM_SERVE_CONTINUOUS, arena, 64, drift=drift)
     progress(f"served continuous (arrival order): p50 {cont['p50_ms']} ms p99 {cont['p99_ms']} ms")
-    srpt = replay_trace(B, ctx, torch, trace, prec, B.QSIM_SERVE_CONTINUOUS, arena, 64, B.QSIM_POLICY_SHORTEST, 2.0)
+    srpt = replay_trace(B, ctx, torch, trace, prec, B.QSIM_SERVE_CONTINUOUS, arena, 64, B.QSIM_POLICY_SHORTEST, 2.0,
+                        drift=drift)
     progress(f"served continuous (least work first): p50 {srpt['p50_ms']} ms p99 {srpt['p99_ms']} ms")
     aged = replay_trace(B, ctx, torch, trace, prec, B.QSIM_SERVE_CONTINUOUS, arena, 64, B.QSIM_POLICY_AGED, 2.0,
-                        aging)
+                        aging, drift=drift)
     progress(f"served continuous (least work first, aged {aging:g} TFLOP/s): p50 {aged['p50_ms']} ms "
              f"p99 {aged['p99_ms']} ms")
-    plain = replay_trace(B, ctx, torch, trace, prec, B.QSIM_SERVE_FIFO, arena, 1)
+    plain = replay_trace(B, ctx, torch, trace, prec, B.QSIM_SERVE_FIFO, arena, 1, drift=drift)
     del arena
     torch.cuda.empty_cache()
     return {
         "workload": f"{count} Poisson arrivals at {rate:g} req/s (seed {seed}), n ~ U{{6..13}}, depth ~ U{{10..40}}, "
-                    f"families ghz_chain/dj/qft/random; {prec_name} chains, float64 probe drift and norm per "
-                    f"request; arena {arena_gib} GiB",
+                    f"families ghz_chain/dj/qft/random; {prec_name} chains, float64 "
+                    f"{DRIFT_TEXT[drift]} and norm per request; arena {arena_gib} GiB",
         "offered_tflops": round(offered / 1e12, 1),
         "continuous_arrival_order": cont,
         "continuous_least_work_first": srpt,
@@ -204,7 +210,8 @@ def bench_served(B, ctx, torch, count: int, rate: float, seed: int, prec_name: s
     }
 
 
-def bench_served_sweep(B, ctx, torch, rates, seconds: float, prec_name: str, arena_gib: int, slo_ms: float):
+def bench_served_sweep(B, ctx, torch, rates, seconds: float, prec_name: str, arena_gib: int, slo_ms: float,
+                       drift: str = "full"):
     """Offered-rate sweep of the served workload: for each Poisson rate, a trace of about `seconds` of arrivals
     run to completion under continuous batching (least work first) and under plain FIFO. A rate counts as
     sustained when the p99 latency meets the SLO; the highest rate's achieved TFLOP/s (saturated) gives the
@@ -226,7 +233,7 @@ def bench_served_sweep(B, ctx, torch, rates, seconds: float, prec_name: str, are
                                      ("continuous_least_work_first_aged", B.QSIM_SERVE_CONTINUOUS, 64,
                                       B.QSIM_POLICY_AGED),
                                      ("plain_fifo", B.QSIM_SERVE_FIFO, 1, 0)):
-            r = replay_trace(B, ctx, torch, trace, prec, mode, arena, act, pol, 2.0, 100.0)
+            r = replay_trace(B, ctx, torch, trace, prec, mode, arena, act, pol, 2.0, 100.0, drift)
             r["meets_slo"] = r["p99_ms"] <= slo_ms
             row[name] = r
             progress(f"sweep rate {rate}: {name} p50 {r['p50_ms']} ms p99 {r['p99_ms']} ms "
@@ -240,7 +247,7 @@ def bench_served_sweep(B, ctx, torch, rates, seconds: float, prec_name: str, are
     capacity = max(top["continuous_least_work_first"]["achieved_tflops"], top["plain_fifo"]["achieved_tflops"])
     mean_work = sum(r["mean_tflop_per_request"] * r["requests"] for r in rows) / sum(r["requests"] for r in rows)
     return {"workload": f"Poisson arrivals (seed 1) at each rate for ~{seconds:g} s, n ~ U{{6..13}}, depth ~ "
-                        f"U{{10..40}}, {prec_name}, float64 probe drift per request",
+                        f"U{{10..40}}, {prec_name}, float64 {DRIFT_TEXT[drift]} per request",
             "rates": rows, "slo_p99_ms": slo_ms, "max_rate_meeting_slo": best,
             "capacity_tflops_at_highest_rate": capacity,
             "throughput_bound_rate": round(capacity / mean_work, 2)}
@@ -430,6 +437,8 @@ def main() -> int:
     ap.add_argument("--served", type=int, default=200, help="requests in the served trace (0: skip)")
     ap.add_argument("--served-rate", type=float, default=200.0)
     ap.add_argument("--served-prec", default="split_bf16", choices=sorted(PEAK_TFLOPS))
+    ap.add_argument("--served-drift", default="full", choices=sorted(DRIFT_TEXT),
+                    help="drift check per served request: the full ||U^H U - I|| or the two-pass probe")
     ap.add_argument("--fsv", type=int, default=30, help="qubits of the full-state-vector workload (0: skip)")
     ap.add_argument("--sweep-qubits", default="12,13", help="qubit counts of the precision sweep ('' to skip)")
     ap.add_argument("--served-sweep", default="", help="comma-separated Poisson rates for an offered-rate sweep")
@@ -634,7 +643,8 @@ def main() -> int:
                                        else args.prec, reps=2)
         progress("batched done")
     if args.served:
-        out["served"] = bench_served(B, ctx, torch, args.served, args.served_rate, 0, args.served_prec, 96)
+        out["served"] = bench_served(B, ctx, torch, args.served, args.served_rate, 0, args.served_prec, 96,
+                                     drift=args.served_drift)
         progress("served done")
     if args.sweep_qubits:
         out["precision_sweep"] = bench_precision_sweep(B, ctx, torch, [int(x) for x in args.sweep_qubits.split(",")], 20)
@@ -642,7 +652,7 @@ def main() -> int:
     if args.served_sweep:
         rates = [float(x) for x in args.served_sweep.split(",") if x]
         out["served_sweep"] = bench_served_sweep(B, ctx, torch, rates, args.served_sweep_seconds, args.served_prec, 96,
-                                                 args.served_slo_ms)
+                                                 args.served_slo_ms, args.served_drift)
         progress("served sweep done")
     if args.fsv:
         out["full_state"] = bench_fsv(B, ctx, torch, args.fsv, reps=3)
