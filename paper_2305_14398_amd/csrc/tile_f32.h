@@ -178,22 +178,36 @@ struct F32Tile {
         for (int kt = 0; kt < KT; ++kt) {
             const int cur = kt & 1;
             if (kt + 1 < KT) { QSIM_GLOAD((kt + 1) * BK); }
-#pragma unroll
-            for (int t = 0; t < BK / 2 / KS; ++t) {
+            // Fragments of k-step t+1 are read from LDS before the MFMAs of
+            // step t are issued, so their latency hides behind those MFMAs.
+            constexpr int TS = BK / 2 / KS;
+            float fr[2][4][BMB > BNB ? BMB : BNB];  // [buffer][ar, ai, br, bi][block]
+            auto read_frags = [&](int t, int buf) {
                 const int kk = (t / (8 / KS)) * 16 + kgrp * (8 / KS) + t % (8 / KS) + khalf;
-                float ar[BMB], ai[BMB], br[BNB], bi[BNB];
 #pragma unroll
                 for (int x = 0; x < BMB; ++x) {
                     const int m = wm * (32 * BMB) + x * 32 + lrow;
-                    ar[x] = As[cur][0][kk][m];
-                    ai[x] = As[cur][1][kk][m];
+                    fr[buf][0][x] = As[cur][0][kk][m];
+                    fr[buf][1][x] = As[cur][1][kk][m];
                 }
 #pragma unroll
                 for (int y = 0; y < BNB; ++y) {
                     const int c = wn * (32 * BNB) + y * 32 + lrow;
-                    br[y] = Bs[cur][0][kk][c];
-                    bi[y] = Bs[cur][1][kk][c];
+                    fr[buf][2][y] = Bs[cur][0][kk][c];
+                    fr[buf][3][y] = Bs[cur][1][kk][c];
                 }
+            };
+            read_frags(0, 0);
+#pragma unroll
+            for (int t = 0; t < TS; ++t) {
+                // issue those reads at the start of step t, ahead of its MFMAs
+                __builtin_amdgcn_sched_barrier(0);
+                if (t + 1 < TS) read_frags(t + 1, (t + 1) & 1);
+                __builtin_amdgcn_sched_barrier(0);
+                const float* ar = fr[t & 1][0];
+                const float* ai = fr[t & 1][1];
+                const float* br = fr[t & 1][2];
+                const float* bi = fr[t & 1][3];
 #pragma unroll
                 for (int x = 0; x < BMB; ++x) {
 #pragma unroll
