@@ -170,40 +170,56 @@ struct F32Tile {
         }                                                                                        \
     }
 
+        // Fragments of k-step t+1 are read from LDS before the MFMAs of step t
+        // are issued, so their latency hides behind those MFMAs.  The next
+        // K-tile is staged before the last k-step of the current one: after
+        // the barrier, its first fragments are read while that step's MFMAs
+        // run, so no wave waits on LDS at a K-tile boundary.  Scheduling
+        // barriers hold that order against the compiler, which otherwise sinks
+        // the reads below the MFMAs; the fused tile, whose entry synthesis
+        // shares the K-tile's instruction stream, keeps the compiler's order.
+        constexpr int TS = BK / 2 / KS;
+        static_assert(TS % 2 == 0, "step t uses fragment buffer t & 1 in every K-tile");
+        float fr[2][4][BMB > BNB ? BMB : BNB];  // [buffer][ar, ai, br, bi][block]
+        auto read_frags = [&](int stage, int t, int buf) {
+            const int kk = (t / (8 / KS)) * 16 + kgrp * (8 / KS) + t % (8 / KS) + khalf;
+#pragma unroll
+            for (int x = 0; x < BMB; ++x) {
+                const int m = wm * (32 * BMB) + x * 32 + lrow;
+                fr[buf][0][x] = As[stage][0][kk][m];
+                fr[buf][1][x] = As[stage][1][kk][m];
+            }
+#pragma unroll
+            for (int y = 0; y < BNB; ++y) {
+                const int c = wn * (32 * BNB) + y * 32 + lrow;
+                fr[buf][2][y] = Bs[stage][0][kk][c];
+                fr[buf][3][y] = Bs[stage][1][kk][c];
+            }
+        };
+
         const int KT = N / BK;
         QSIM_GLOAD(0);
         QSIM_LSTORE(0);
         __syncthreads();
+        read_frags(0, 0, 0);
 
         for (int kt = 0; kt < KT; ++kt) {
             const int cur = kt & 1;
-            if (kt + 1 < KT) { QSIM_GLOAD((kt + 1) * BK); }
-            // Fragments of k-step t+1 are read from LDS before the MFMAs of
-            // step t are issued, so their latency hides behind those MFMAs.
-            constexpr int TS = BK / 2 / KS;
-            float fr[2][4][BMB > BNB ? BMB : BNB];  // [buffer][ar, ai, br, bi][block]
-            auto read_frags = [&](int t, int buf) {
-                const int kk = (t / (8 / KS)) * 16 + kgrp * (8 / KS) + t % (8 / KS) + khalf;
-#pragma unroll
-                for (int x = 0; x < BMB; ++x) {
-                    const int m = wm * (32 * BMB) + x * 32 + lrow;
-                    fr[buf][0][x] = As[cur][0][kk][m];
-                    fr[buf][1][x] = As[cur][1][kk][m];
-                }
-#pragma unroll
-                for (int y = 0; y < BNB; ++y) {
-                    const int c = wn * (32 * BNB) + y * 32 + lrow;
-                    fr[buf][2][y] = Bs[cur][0][kk][c];
-                    fr[buf][3][y] = Bs[cur][1][kk][c];
-                }
-            };
-            read_frags(0, 0);
+            const bool more = kt + 1 < KT;
+            if (more) { QSIM_GLOAD((kt + 1) * BK); }
 #pragma unroll
             for (int t = 0; t < TS; ++t) {
-                // issue those reads at the start of step t, ahead of its MFMAs
-                __builtin_amdgcn_sched_barrier(0);
-                if (t + 1 < TS) read_frags(t + 1, (t + 1) & 1);
-                __builtin_amdgcn_sched_barrier(0);
+                if constexpr (!FUSED) __builtin_amdgcn_sched_barrier(0);
+                if (t + 1 < TS) {
+                    read_frags(cur, t + 1, (t + 1) & 1);
+                } else {
+                    // every read of stage cur ^ 1 (the previous K-tile) was
+                    // issued before the previous barrier
+                    if (more) { QSIM_LSTORE(cur ^ 1); }
+                    __syncthreads();
+                    if (more) read_frags(cur ^ 1, 0, 0);
+                }
+                if constexpr (!FUSED) __builtin_amdgcn_sched_barrier(0);
                 const float* ar = fr[t & 1][0];
                 const float* ai = fr[t & 1][1];
                 const float* br = fr[t & 1][2];
@@ -226,8 +242,6 @@ struct F32Tile {
                     }
                 }
             }
-            if (kt + 1 < KT) { QSIM_LSTORE(cur ^ 1); }
-            __syncthreads();
         }
 #undef QSIM_GLOAD
 #undef QSIM_LSTORE
