@@ -73,10 +73,10 @@ __global__ __launch_bounds__(F32Shapes<GAUSS>::THREADS) void grouped_f32_kernel(
         int tm, tn;
         if (J.cfg == 128) {
             grouped_tile_order(local, N / 128, N / 128, tm, tn);
-            T128::run(J.n, A, B, C, tm, tn, smem);
+            T128::template run<false>(J.n, A, B, C, tm, tn, smem);
         } else if (J.cfg == 64) {
             grouped_tile_order(local, N / 64, N / 64, tm, tn);
-            T64::run(J.n, A, B, C, tm, tn, smem);
+            T64::template run<false>(J.n, A, B, C, tm, tn, smem);
         } else {
             f32_small_product<GAUSS>(J.n, A, nullptr, B, C, threadIdx.x, F32Shapes<GAUSS>::THREADS);
         }

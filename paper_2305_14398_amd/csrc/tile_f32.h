@@ -91,9 +91,13 @@ struct F32Tile {
         }
     }
 
+    // PIN: hold the LDS read order below with scheduling barriers (the
+    // grouped kernel, whose job lookup keeps more registers live, leaves the
+    // order to the compiler to stay within 256 registers).
+    template <bool PIN = true>
     __device__ __forceinline__ static void run(int n, const float* __restrict__ A, const float* __restrict__ B,
                                                float* __restrict__ C, int tm, int tn, float* smem) {
-        run_impl<false>(n, A, nullptr, B, C, tm, tn, smem);
+        run_impl<false, PIN>(n, A, nullptr, B, C, tm, tn, smem);
     }
 
     // Stages 4 and 5 fused: the A operand (the step operator) is never
@@ -102,10 +106,10 @@ struct F32Tile {
     // product is bit-identical to expanding S and calling run().
     __device__ __forceinline__ static void run_fused(int n, const DevStep& st, const float* __restrict__ B,
                                                      float* __restrict__ C, int tm, int tn, float* smem) {
-        run_impl<true>(n, nullptr, &st, B, C, tm, tn, smem);
+        run_impl<true, false>(n, nullptr, &st, B, C, tm, tn, smem);
     }
 
-    template <bool FUSED>
+    template <bool FUSED, bool PIN>
     __device__ __forceinline__ static void run_impl(int n, const float* __restrict__ A, const DevStep* st,
                                                     const float* __restrict__ B, float* __restrict__ C, int tm,
                                                     int tn, float* smem) {
@@ -176,8 +180,10 @@ struct F32Tile {
         // the barrier, its first fragments are read while that step's MFMAs
         // run, so no wave waits on LDS at a K-tile boundary.  Scheduling
         // barriers hold that order against the compiler, which otherwise sinks
-        // the reads below the MFMAs; the fused tile, whose entry synthesis
-        // shares the K-tile's instruction stream, keeps the compiler's order.
+        // the reads below the MFMAs.  Without PIN (the fused tile, whose entry
+        // synthesis shares the K-tile's instruction stream, and the grouped
+        // kernel, which would exceed 256 registers) the plain order is kept:
+        // each k-step reads its fragments, the next K-tile is stored last.
         constexpr int TS = BK / 2 / KS;
         static_assert(TS % 2 == 0, "step t uses fragment buffer t & 1 in every K-tile");
         float fr[2][4][BMB > BNB ? BMB : BNB];  // [buffer][ar, ai, br, bi][block]
@@ -197,50 +203,66 @@ struct F32Tile {
             }
         };
 
+        // The MFMAs of one k-step on fragments (ar, ai, br, bi) of each block.
+        auto mma_step = [&](const float* ar, const float* ai, const float* br, const float* bi) {
+#pragma unroll
+            for (int x = 0; x < BMB; ++x) {
+#pragma unroll
+                for (int y = 0; y < BNB; ++y) {
+                    if constexpr (!GAUSS) {
+                        acc[x][y][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[x], br[y], acc[x][y][0], 0, 0, 0);
+                        acc[x][y][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai[x], bi[y], acc[x][y][0], 0, 0, 0);
+                        acc[x][y][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[x], bi[y], acc[x][y][1], 0, 0, 0);
+                        acc[x][y][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[x], br[y], acc[x][y][1], 0, 0, 0);
+                    } else {
+                        acc[x][y][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[x], br[y], acc[x][y][0], 0, 0, 0);
+                        acc[x][y][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[x], bi[y], acc[x][y][1], 0, 0, 0);
+                        acc[x][y][2] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[x] + ai[x], br[y] + bi[y],
+                                                                            acc[x][y][2], 0, 0, 0);
+                    }
+                }
+            }
+        };
+
         const int KT = N / BK;
         QSIM_GLOAD(0);
         QSIM_LSTORE(0);
         __syncthreads();
-        read_frags(0, 0, 0);
-
-        for (int kt = 0; kt < KT; ++kt) {
-            const int cur = kt & 1;
-            const bool more = kt + 1 < KT;
-            if (more) { QSIM_GLOAD((kt + 1) * BK); }
+        if constexpr (PIN) {
+            read_frags(0, 0, 0);
+            for (int kt = 0; kt < KT; ++kt) {
+                const int cur = kt & 1;
+                const bool more = kt + 1 < KT;
+                if (more) { QSIM_GLOAD((kt + 1) * BK); }
 #pragma unroll
-            for (int t = 0; t < TS; ++t) {
-                if constexpr (!FUSED) __builtin_amdgcn_sched_barrier(0);
-                if (t + 1 < TS) {
-                    read_frags(cur, t + 1, (t + 1) & 1);
-                } else {
-                    // every read of stage cur ^ 1 (the previous K-tile) was
-                    // issued before the previous barrier
-                    if (more) { QSIM_LSTORE(cur ^ 1); }
-                    __syncthreads();
-                    if (more) read_frags(cur ^ 1, 0, 0);
-                }
-                if constexpr (!FUSED) __builtin_amdgcn_sched_barrier(0);
-                const float* ar = fr[t & 1][0];
-                const float* ai = fr[t & 1][1];
-                const float* br = fr[t & 1][2];
-                const float* bi = fr[t & 1][3];
-#pragma unroll
-                for (int x = 0; x < BMB; ++x) {
-#pragma unroll
-                    for (int y = 0; y < BNB; ++y) {
-                        if constexpr (!GAUSS) {
-                            acc[x][y][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[x], br[y], acc[x][y][0], 0, 0, 0);
-                            acc[x][y][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai[x], bi[y], acc[x][y][0], 0, 0, 0);
-                            acc[x][y][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[x], bi[y], acc[x][y][1], 0, 0, 0);
-                            acc[x][y][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[x], br[y], acc[x][y][1], 0, 0, 0);
-                        } else {
-                            acc[x][y][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[x], br[y], acc[x][y][0], 0, 0, 0);
-                            acc[x][y][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[x], bi[y], acc[x][y][1], 0, 0, 0);
-                            acc[x][y][2] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[x] + ai[x], br[y] + bi[y],
-                                                                                acc[x][y][2], 0, 0, 0);
-                        }
+                for (int t = 0; t < TS; ++t) {
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (t + 1 < TS) {
+                        read_frags(cur, t + 1, (t + 1) & 1);
+                    } else {
+                        // every read of stage cur ^ 1 (the previous K-tile)
+                        // was issued before the previous barrier
+                        if (more) { QSIM_LSTORE(cur ^ 1); }
+                        __syncthreads();
+                        if (more) read_frags(cur ^ 1, 0, 0);
                     }
+                    __builtin_amdgcn_sched_barrier(0);
+                    mma_step(fr[t & 1][0], fr[t & 1][1], fr[t & 1][2], fr[t & 1][3]);
                 }
+            }
+        } else {
+            // Each k-step reads its own fragments; the next K-tile is stored
+            // after the current one's MFMAs.
+            for (int kt = 0; kt < KT; ++kt) {
+                const int cur = kt & 1;
+                if (kt + 1 < KT) { QSIM_GLOAD((kt + 1) * BK); }
+#pragma unroll
+                for (int t = 0; t < TS; ++t) {
+                    read_frags(cur, t, 0);
+                    mma_step(fr[0][0], fr[0][1], fr[0][2], fr[0][3]);
+                }
+                if (kt + 1 < KT) { QSIM_LSTORE(cur ^ 1); }
+                __syncthreads();
             }
         }
 #undef QSIM_GLOAD
