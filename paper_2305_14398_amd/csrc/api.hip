@@ -47,7 +47,7 @@ bool valid_n(int n) { return n >= 1 && n <= QSIM_MAX_QUBITS; }
 
 bool valid_prec(int p) { return p >= QSIM_FP32_4M && p <= QSIM_SPLIT_FP16; }
 
-// Precisions with a kernel in this build.
+// Precisions with a kernel in this library.
 static bool built_prec(int p) { return valid_prec(p); }
 
 static qsim_status check_gate(int n, const qsim_gate& g, int idx) {
@@ -436,7 +436,7 @@ qsim_status qsim_step_multiply(qsim_ctx* ctx, int n_qubits, int prec, const void
     qsim_status s = QSIM_OK;
     if (!valid_n(n_qubits)) return fail(QSIM_E_RANGE, "n_qubits %d outside 1..%d", n_qubits, QSIM_MAX_QUBITS);
     if (!valid_prec(prec)) return fail(QSIM_E_INVALID, "unknown precision %d", prec);
-    if (!built_prec(prec)) return fail(QSIM_E_INVALID, "precision %d is not available in this build", prec);
+    if (!built_prec(prec)) return fail(QSIM_E_INVALID, "precision %d is not available in this library", prec);
     const OpFormat fmt = format_of(prec);
     if (!d_S || !d_Uin || !aligned(d_S) || !aligned(d_Uin))
         return fail(QSIM_E_INVALID, "d_S / d_Uin is NULL or not 256-byte aligned");
@@ -480,7 +480,7 @@ qsim_status qsim_step_multiply_fused(qsim_ctx* ctx, int n_qubits, int prec, cons
     if (!valid_n(n_qubits)) return fail(QSIM_E_RANGE, "n_qubits %d outside 1..%d", n_qubits, QSIM_MAX_QUBITS);
     if (!valid_prec(prec)) return fail(QSIM_E_INVALID, "unknown precision %d", prec);
     if (format_of(prec) != FMT_F32) return fail(QSIM_E_INVALID, "fused products are float32 (4M or 3M) only");
-    if (!built_prec(prec)) return fail(QSIM_E_INVALID, "precision %d is not available in this build", prec);
+    if (!built_prec(prec)) return fail(QSIM_E_INVALID, "precision %d is not available in this library", prec);
     if (!d_Uin || !d_Uout || !aligned(d_Uin) || !aligned(d_Uout))
         return fail(QSIM_E_INVALID, "d_Uin / d_Uout is NULL or not 256-byte aligned");
     if (d_Uin == d_Uout) return fail(QSIM_E_INVALID, "d_Uout aliases d_Uin");
@@ -510,7 +510,7 @@ static qsim_status unitary_chain_entry(qsim_ctx* ctx, int n_qubits, const qsim_g
     qsim_status s = QSIM_OK;
     if (!valid_n(n_qubits)) return fail(QSIM_E_RANGE, "n_qubits %d outside 1..%d", n_qubits, QSIM_MAX_QUBITS);
     if (!valid_prec(prec)) return fail(QSIM_E_INVALID, "unknown precision %d", prec);
-    if (!built_prec(prec)) return fail(QSIM_E_INVALID, "precision %d is not available in this build", prec);
+    if (!built_prec(prec)) return fail(QSIM_E_INVALID, "precision %d is not available in this library", prec);
     if (d_U == nullptr || !aligned(d_U)) return fail(QSIM_E_INVALID, "d_U is NULL or not 256-byte aligned");
     s = check_gates(n_qubits, gates, n_gates);
     if (s != QSIM_OK) return s;
