@@ -241,7 +241,8 @@ qsim_status qsim_sample(qsim_ctx* ctx, int n_qubits, const double* d_prob, const
 /* Unitarity drift of a row-major planar complex64 U (Section 2.3: a gate
  * matrix is unitary iff U^H = U^-1): computes D = U^H U - I in float64 and
  * returns h_out[0] = max |D_ij| and h_out[1] = ||D||_F / sqrt(N).  No N x N
- * float64 matrix is stored.  Synchronises the stream. */
+ * float64 matrix is stored; the upper triangle of U^H U is formed with three
+ * real float64 products (3 N^3 flops).  Synchronises the stream. */
 qsim_status qsim_unitarity_drift(qsim_ctx* ctx, int n_qubits, const void* d_U, double* h_out,
                                  void* stream);
 /* The same check without waiting: d_out (device memory, 2 doubles, 8-byte
@@ -361,7 +362,7 @@ typedef struct qsim_serve_config {
 } qsim_serve_config;
 
 #define QSIM_REQ_DRIFT_PROBE 1u  /* also compute the probe drift (qsim_unitarity_drift_probe) */
-#define QSIM_REQ_DRIFT_FULL 2u   /* instead, the full float64 check (qsim_unitarity_drift): 8 N^3 / 2 flops */
+#define QSIM_REQ_DRIFT_FULL 2u   /* instead, the full float64 check (qsim_unitarity_drift): 3 N^3 flops */
 
 typedef struct qsim_request {
     int32_t n_qubits;

@@ -8,6 +8,12 @@
 // above the diagonal are computed; off-diagonal tiles count twice in the sum.
 //   Re G_ij = sum_k Ur_ki Ur_kj + Ui_ki Ui_kj
 //   Im G_ij = sum_k Ur_ki Ui_kj - Ui_ki Ur_kj
+// taken in Gauss's three-product form (as the 3M chain products), with
+// a = Ur_ki, b = Ui_ki, c = Ur_kj, d = Ui_kj:
+//   K1 = sum (a - b) c,  K2 = sum a (d - c),  K3 = sum (-b)(c + d),
+//   Re G = K1 - K3,      Im G = K1 + K2,
+// three float64 MFMA products instead of four.  The operand sums of float32
+// values are exact in float64; only the accumulation order differs.
 // Both operands are rows k of U, read as contiguous 16-byte vectors.
 #include "common.h"
 
@@ -63,13 +69,13 @@ __global__ __launch_bounds__(256, 3) void drift_mfma_kernel(int n, const float* 
         int tm, tn;
         tile_of(t, T, tm, tn);
         const int i0 = tm * DT, j0 = tn * DT;
-        doublex4 acc[BX][BX][2];
+        doublex4 acc[BX][BX][3];
 #pragma unroll
         for (int x = 0; x < BX; ++x)
 #pragma unroll
             for (int y = 0; y < BX; ++y)
 #pragma unroll
-                for (int z = 0; z < 2; ++z) acc[x][y][z] = doublex4{0.0, 0.0, 0.0, 0.0};
+                for (int z = 0; z < 3; ++z) acc[x][y][z] = doublex4{0.0, 0.0, 0.0, 0.0};
 
         floatx4 ra[2], rb[2];
 #pragma unroll
@@ -108,12 +114,13 @@ __global__ __launch_bounds__(256, 3) void drift_mfma_kernel(int n, const float* 
                 }
 #pragma unroll
                 for (int x = 0; x < BX; ++x) {
+                    const double amb = ar[x] - ai[x];  // exact: float32 operands
 #pragma unroll
                     for (int y = 0; y < BX; ++y) {
-                        acc[x][y][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[x], br[y], acc[x][y][0], 0, 0, 0);
-                        acc[x][y][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[x], bi[y], acc[x][y][0], 0, 0, 0);
-                        acc[x][y][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[x], bi[y], acc[x][y][1], 0, 0, 0);
-                        acc[x][y][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[x], br[y], acc[x][y][1], 0, 0, 0);
+                        const double dmc = bi[y] - br[y], cpd = br[y] + bi[y];
+                        acc[x][y][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(amb, br[y], acc[x][y][0], 0, 0, 0);
+                        acc[x][y][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[x], dmc, acc[x][y][1], 0, 0, 0);
+                        acc[x][y][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[x], cpd, acc[x][y][2], 0, 0, 0);
                     }
                 }
             }
@@ -137,8 +144,8 @@ __global__ __launch_bounds__(256, 3) void drift_mfma_kernel(int n, const float* 
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int i = i0 + wm * 16 * BX + x * 16 + kq + 4 * r;
-                    const double dr = acc[x][y][0][r] - (i == j ? 1.0 : 0.0);
-                    const double di = acc[x][y][1][r];
+                    const double dr = (acc[x][y][0][r] - acc[x][y][2][r]) - (i == j ? 1.0 : 0.0);
+                    const double di = acc[x][y][0][r] + acc[x][y][1][r];
                     const double m2 = dr * dr + di * di;
                     tmax = fmax(tmax, sqrt(m2));
                     tsum += w * m2;
@@ -228,7 +235,7 @@ __global__ __launch_bounds__(256) void drift_final_kernel(int n, int count, cons
 // x_j = exp(2 pi i frac(j * g)) / sqrt(N) with g the golden-ratio conjugate
 // (unit-modulus entries, so |x| = 1).  y = U x and z = U^H y are accumulated in
 // float64 (products of float32 entries are exact in float64); the cost is two
-// passes over U instead of the 8 N^3 flops of the full check.
+// passes over U instead of the 3 N^3 float64 flops of the full check.
 constexpr double kGolden = 0.61803398874989484820;
 
 __device__ __forceinline__ void probe_x(uint32_t j, double inv_sqrt_n, double& xr, double& xi) {
