@@ -38,9 +38,11 @@ __device__ __forceinline__ void tile_of(int t, int T, int& tm, int& tn) {
 // A workgroup of 2 x 2 waves computes a DT x DT tile of G, DT = 32 * BX; each
 // wave owns BX x BX blocks of 16 x 16.  The tile edge sets the granularity of
 // the work split: at 11 qubits 64-wide tiles give 528 tiles for 256 CUs (16 CUs
-// take a third tile while the rest idle), 32-wide ones 2080.
+// take a third tile while the rest idle), 32-wide ones 2080.  The 32-wide
+// tile waits on its operand loads, so it is held to 96 registers: five
+// workgroups per CU (the compiler's own choice, 98 registers, allows four).
 template <int BX>
-__global__ __launch_bounds__(256, 3) void drift_mfma_kernel(int n, const float* __restrict__ U,
+__global__ __launch_bounds__(256, BX == 1 ? 5 : 3) void drift_mfma_kernel(int n, const float* __restrict__ U,
                                                             double* __restrict__ partials) {
     constexpr int DT = 32 * BX;
     constexpr int DLD = DT + 16;  // padded row stride (floats): the 4 k-rows of one MFMA land on distinct banks
