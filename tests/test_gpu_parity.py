@@ -223,7 +223,7 @@ def test_apply_basis_state_equals_first_column_exactly(ctx, n):
     np.testing.assert_array_equal(psi[N:], col0[1])
 
 
-@pytest.mark.parametrize("n", [2, 5, 6, 8, 10])
+@pytest.mark.parametrize("n", [2, 5, 6, 8, 10, 12])  # 12: the 64-wide drift tile
 def test_drift_matches_oracle_of_same_matrix(ctx, n):
     c = W.random_layers(n, 4, np.random.default_rng(n))
     U = gpu_chain(ctx, n, c.gates)
