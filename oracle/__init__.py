@@ -23,7 +23,8 @@ collapsing method of the Simulator interface, Section 5.2.3).
 Parity status: every function here is pinned by the tests in
 ``tests/test_oracle_pins.py`` (printed matrices of Table 1 and Eq. 8-11,
 closed forms for GHZ, QFT and Deutsch-Jozsa, unitarity, brute-force 1-2 qubit
-matrices, route A == route B, and for the sampler one-hot, uniform-grid and
-Deutsch-Jozsa outcomes).  No function is parity unpinned.
+matrices, route A == route B, the error metrics' closed forms on non-unitary
+matrices and unnormalised vectors, and for the sampler one-hot, uniform-grid
+and Deutsch-Jozsa outcomes).  No function is parity unpinned.
 """
 from . import gates, unitary, fsv, metrics, measure  # noqa: F401

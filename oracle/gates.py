@@ -65,11 +65,3 @@ def controlled_target(name: str, theta=None) -> np.ndarray:
         return one_qubit("R", theta)
     raise ValueError(f"not a controlled gate: {name}")
 
-
-def controlled_4x4(U: np.ndarray) -> np.ndarray:
-    """Eq. 7: the 4x4 controlled-U with the control as the first (high) tensor factor."""
-    m = np.zeros((4, 4), dtype=np.complex128)
-    m[0, 0] = 1
-    m[1, 1] = 1
-    m[2:, 2:] = U
-    return m

@@ -253,6 +253,47 @@ def test_metrics():
     assert metrics.fidelity(other, psi) == pytest.approx(abs(np.vdot(psi, other)) ** 2, abs=1e-14)
 
 
+def test_metrics_closed_forms_off_the_unit_sphere():
+    """Closed forms of the metrics on non-unitary matrices and unnormalised vectors.
+
+    U^H = U^{-1} characterises a unitary (Section 2.3); the drift measures how far
+    U^H U is from I.  For c*I_N, U^H U - I = (|c|^2 - 1) I, so both the largest entry
+    and ||.||_F / sqrt(N) equal ||c|^2 - 1|; for the shear [[1, 1], [0, 1]],
+    U^H U - I = [[0, 1], [1, 1]]: largest entry 1, Frobenius norm sqrt(3), over
+    sqrt(2).  A diagonal matrix with distinct moduli fixes the normalisation by
+    sqrt(N) (not N) at N = 4.  Fidelity is invariant under scaling of either
+    vector and a global phase, 0 for orthogonal vectors of any length, and 1/2
+    for (2, 0) against (3, 3).  The amplitude difference is a modulus, so
+    negative and complex differences count by size.
+    """
+    for n in (1, 3, 5):
+        N = 1 << n
+        for c in (0.5, 1.25, 0.8 + 0.9j, -1.1j):
+            mx, fro = metrics.unitarity_drift(c * np.eye(N))
+            assert mx == pytest.approx(abs(abs(c) ** 2 - 1), abs=1e-14)
+            assert fro == pytest.approx(abs(abs(c) ** 2 - 1), abs=1e-14)
+    mx, fro = metrics.unitarity_drift(np.array([[1.0, 1.0], [0.0, 1.0]]))
+    assert mx == pytest.approx(1.0, abs=1e-14)
+    assert fro == pytest.approx(math.sqrt(3.0 / 2.0), abs=1e-14)
+    d = np.array([1.0, 2.0, 0.5j, 0.0])
+    mx, fro = metrics.unitarity_drift(np.diag(d))
+    e = np.abs(d) ** 2 - 1  # 0, 3, -0.75, -1
+    assert mx == pytest.approx(3.0, abs=1e-14)
+    assert fro == pytest.approx(math.sqrt(float(np.sum(e * e)) / 4.0), abs=1e-14)
+
+    psi = W.random_state(4, 3)
+    assert metrics.fidelity(2.0 * psi, 3.0 * np.exp(1.9j) * psi) == pytest.approx(1.0, abs=1e-14)
+    a = np.zeros(16, dtype=np.complex128)
+    b = np.zeros(16, dtype=np.complex128)
+    a[3], b[5] = 2.0, 3.0j
+    assert metrics.fidelity(a, b) == 0.0
+    assert metrics.fidelity(np.array([2.0, 0.0]), np.array([3.0, 3.0])) == pytest.approx(0.5, abs=1e-15)
+
+    assert metrics.max_abs_diff(np.array([1.0, 2.0]), np.array([3.0, 2.5])) == 2.0
+    assert metrics.max_abs_diff(np.array([1.0 + 0j, -2.0]), np.array([1.0 + 3.0j, 2.0])) == 4.0
+    assert metrics.max_abs_diff(np.array([]), np.array([])) == 0.0
+
+
 # --- Measurement by inverse-CDF sampling (Section 5.2.3, simulateAndCollapse) -------------
 
 def test_sampler_one_hot_and_zero_probability_outcomes():
