@@ -12,8 +12,10 @@
 // a = Ur_ki, b = Ui_ki, c = Ur_kj, d = Ui_kj:
 //   K1 = sum (a - b) c,  K2 = sum a (d - c),  K3 = sum (-b)(c + d),
 //   Re G = K1 - K3,      Im G = K1 + K2,
-// three float64 MFMA products instead of four.  The operand sums of float32
-// values are exact in float64; only the accumulation order differs.
+// three float64 MFMA products instead of four.  Each operand sum of two float32
+// values is rounded once in float64 (relative error <= 2^-53; exact unless the
+// exponents differ by more than 29), so the result differs from the
+// four-product form by rounding of that order and by the accumulation order.
 // Both operands are rows k of U, read as contiguous 16-byte vectors.
 #include "common.h"
 
