@@ -250,6 +250,21 @@ qsim_status qsim_unitarity_drift(qsim_ctx* ctx, int n_qubits, const void* d_U, d
  * it.  Uses the context's scratch for partial sums: calls on one context must
  * not overlap on different streams. */
 qsim_status qsim_unitarity_drift_async(qsim_ctx* ctx, int n_qubits, const void* d_U, double* d_out, void* stream);
+/* The asynchronous drift check for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no context, no workspace argument, and no allocation on any call.
+ * Runs on the current device and `stream` with the same kernels, grid and
+ * fixed-order reduction as qsim_unitarity_drift_async, so d_out (device, 2
+ * doubles, 8-byte aligned) receives the same max |D_ij| and ||D||_F / sqrt(N)
+ * bit for bit.  The partial sums live in one static 32 KiB device array per
+ * GPU (2 x 2048 doubles, the most the drift grid ever uses; held until the
+ * process ends), so any 1 <= n_qubits <= 16 fits and larger n is rejected with
+ * QSIM_E_RANGE.  Every call on a device shares that array: calls that overlap
+ * on one device (different streams or threads) race and must be ordered by the
+ * caller.  Errors: QSIM_E_RANGE for n_qubits, QSIM_E_INVALID for NULL or
+ * unaligned pointers, QSIM_E_DEVICE if the array's address cannot be resolved
+ * or the launch fails. */
+qsim_status qsim_unitarity_drift_noalloc(int n_qubits, const void* d_U, double* d_out, void* stream);
 
 /* Probe form of the drift check for serving: with the fixed unit vector
  * x_j = exp(2 pi i frac(j g)) / sqrt(N) (g = (sqrt 5 - 1) / 2), computes

@@ -146,6 +146,7 @@ def lib() -> ctypes.CDLL:
         "qsim_unitarity_drift_probe": (i32, [vp, i32, vp, ctypes.POINTER(dbl), vp]),
         "qsim_sample": (i32, [vp, i32, vp, vp, i32, vp, vp]),
         "qsim_unitarity_drift_async": (i32, [vp, i32, vp, vp, vp]),
+        "qsim_unitarity_drift_noalloc": (i32, [i32, vp, vp, vp]),
         "qsim_register_unitary": (i32, [ctypes.c_char_p, i32, ctypes.POINTER(dbl), ctypes.POINTER(i32)]),
         "qsim_find_unitary": (i32, [ctypes.c_char_p, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "qsim_fsv_schedule": (i32, [i32, vp, i32, ctypes.POINTER(qsim_fsv_pass_info), i32,
@@ -465,6 +466,12 @@ def qsim_unitarity_drift_async(ctx, n_qubits: int, d_U, d_out, stream=None) -> N
     st = _stream(stream, _dev(ctx)) if _h(ctx) else None
     _check(lib().qsim_unitarity_drift_async(_h(ctx), n_qubits, _ptr(d_U), _ptr(d_out), st),
            "qsim_unitarity_drift_async")
+
+
+def qsim_unitarity_drift_noalloc(n_qubits: int, d_U, d_out, stream=None) -> None:
+    """Allocation-free drift check on d_U's device (current device, torch's current stream by default)."""
+    st = _stream(stream, d_U.device.index if hasattr(d_U, "device") else None)
+    _check(lib().qsim_unitarity_drift_noalloc(n_qubits, _ptr(d_U), _ptr(d_out), st), "qsim_unitarity_drift_noalloc")
 
 
 def qsim_unitarity_drift_probe(ctx, n_qubits: int, d_U, stream=None) -> tuple:

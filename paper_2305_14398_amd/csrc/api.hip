@@ -628,6 +628,23 @@ qsim_status qsim_unitarity_drift_async(qsim_ctx* ctx, int n_qubits, const void* 
     return e == hipSuccess ? ok() : device_fail("drift launch", e);
 }
 
+qsim_status qsim_unitarity_drift_noalloc(int n_qubits, const void* d_U, double* d_out, void* stream) {
+    if (!valid_n(n_qubits)) return fail(QSIM_E_RANGE, "n_qubits %d outside 1..%d", n_qubits, QSIM_MAX_QUBITS);
+    if (!d_U || !aligned(d_U)) return fail(QSIM_E_INVALID, "d_U is NULL or not 256-byte aligned");
+    if (!d_out || (reinterpret_cast<uintptr_t>(d_out) & 7u)) return fail(QSIM_E_INVALID, "d_out is NULL or unaligned");
+    double* partials = nullptr;
+    size_t bytes = 0;
+    hipError_t e = drift_static_scratch(&partials, &bytes);
+    if (e != hipSuccess) return device_fail("drift scratch address", e);
+    // launch_drift never runs more workgroups than kDriftMaxPartials, one pair each.
+    if (bytes < 2 * (size_t)kDriftMaxPartials * sizeof(double))
+        return fail(QSIM_E_RANGE, "static drift scratch holds %zu bytes, %zu needed", bytes,
+                    2 * (size_t)kDriftMaxPartials * sizeof(double));
+    e = launch_drift(n_qubits, static_cast<const float*>(d_U), partials, kDriftMaxPartials, d_out,
+                     static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? ok() : device_fail("drift launch", e);
+}
+
 qsim_status qsim_profile_enable(qsim_ctx* ctx, int enable) {
     if (ctx == nullptr) return fail(QSIM_E_INVALID, "context is NULL");
     DeviceGuard g(ctx->device);

@@ -106,5 +106,8 @@ constexpr int kProbeChunkEntries = 1 << 19;
 // Doubles of scratch the probe needs: y (2 N) + partials (2 * kProbeChunkEntries).
 constexpr size_t kProbeScratchDoubles = 2 * ((size_t)1 << QSIM_MAX_QUBITS) + 2 * (size_t)kProbeChunkEntries;
 hipError_t launch_drift_probe(int n, const float* U_row, double* scratch, double* d_out, hipStream_t stream);
+// Device address (on the current device) and size of the drift's static
+// partial-sum array, for the allocation-free drift entry point.
+hipError_t drift_static_scratch(double** out, size_t* bytes);
 
 }  // namespace qsim

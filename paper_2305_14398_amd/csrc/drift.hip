@@ -17,6 +17,8 @@
 // exponents differ by more than 29), so the result differs from the
 // four-product form by rounding of that order and by the accumulation order.
 // Both operands are rows k of U, read as contiguous 16-byte vectors.
+#include <mutex>
+
 #include "common.h"
 
 namespace qsim {
@@ -352,6 +354,37 @@ hipError_t launch_drift_probe(int n, const float* U_row, double* scratch, double
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(probe_final_kernel, dim3(1), dim3(1024), 0, stream, n, chunks, zpart, d_out);
     return hipGetLastError();
+}
+
+// Partial sums of the allocation-free entry point (qsim_unitarity_drift_noalloc):
+// one (max, sum of squares) pair per workgroup of the persistent drift grid,
+// whose size launch_drift caps at kDriftMaxPartials: 32 KiB per device, held
+// until the process ends.  Every launch writes all the pairs it later reads, so
+// nothing needs clearing between calls; calls that overlap on one device race
+// on it.  In host code `scratch` is only a handle: its device address comes
+// from hipGetSymbolAddress, once per device, with that device current.
+static __device__ __align__(256) double scratch[2 * kDriftMaxPartials];
+
+constexpr int kMaxDevices = 64;
+
+hipError_t drift_static_scratch(double** out, size_t* bytes) {
+    static std::mutex mu;
+    static double* ptr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (ptr[dev] == nullptr) {
+        double* p = nullptr;
+        e = hipGetSymbolAddress(reinterpret_cast<void**>(&p), HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (p == nullptr) return hipErrorInvalidSymbol;
+        ptr[dev] = p;
+    }
+    *out = ptr[dev];
+    *bytes = sizeof(scratch);
+    return hipSuccess;
 }
 
 hipError_t launch_drift(int n, const float* U_row, double* partials, int max_partials, double* d_out,
