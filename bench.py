@@ -28,8 +28,13 @@ if ROOT not in sys.path:
 
 METRIC = "complex-GEMM TFLOP/s + circuits/s at 11q; served p50/p99 latency vs plain"
 # MFMA peaks of the dtype each product issues, and the MFMA flops issued per 8 N^3 counted
-PEAK_TFLOPS = {"fp32_4m": 157.3, "fp32_3m": 157.3, "split_bf16": 2500.0, "split_fp16": 2500.0}
-ISSUED_PER_COUNTED = {"fp32_4m": 1.0, "fp32_3m": 6.0 / 8.0, "split_bf16": 24.0 / 8.0, "split_fp16": 24.0 / 8.0}
+PEAK_TFLOPS = {"fp32_4m": 157.3, "fp32_3m": 157.3, "split_bf16": 2500.0, "split_fp16": 2500.0,
+               "split_bf16_3m": 2500.0, "split_fp16_3m": 2500.0}
+ISSUED_PER_COUNTED = {"fp32_4m": 1.0, "fp32_3m": 6.0 / 8.0, "split_bf16": 24.0 / 8.0, "split_fp16": 24.0 / 8.0,
+                      "split_bf16_3m": 18.0 / 8.0, "split_fp16_3m": 18.0 / 8.0}
+# probe kind measuring the dtype each precision issues
+PROBE_OF = {"fp32_4m": "mfma_f32", "fp32_3m": "mfma_f32", "split_bf16": "mfma_bf16", "split_fp16": "mfma_f16",
+            "split_bf16_3m": "mfma_bf16", "split_fp16_3m": "mfma_f16"}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -210,12 +215,16 @@ def bench_served(B, ctx, torch, count: int, rate: float, seed: int, prec_name: s
     }
 
 
+SWEEP_POLICIES = {"lwf": "continuous_least_work_first", "aged": "continuous_least_work_first_aged",
+                  "fifo": "plain_fifo"}
+
+
 def bench_served_sweep(B, ctx, torch, rates, seconds: float, prec_name: str, arena_gib: int, slo_ms: float,
-                       drift: str = "full"):
+                       drift: str = "full", policies=("aged", "fifo")):
     """Offered-rate sweep of the served workload: for each Poisson rate, a trace of about `seconds` of arrivals
-    run to completion under continuous batching (least work first) and under plain FIFO. A rate counts as
-    sustained when the p99 latency meets the SLO; the highest rate's achieved TFLOP/s (saturated) gives the
-    capacity, and capacity / mean work per request the highest arrival rate any schedule could keep up with."""
+    run to completion under continuous batching (aged least work first, by default) and under plain FIFO. A rate
+    counts as sustained when the p99 latency meets the SLO; the highest rate's achieved TFLOP/s (saturated) gives
+    the capacity, and capacity / mean work per request the highest arrival rate any schedule could keep up with."""
     from paper_2305_14398_amd import workloads as W
     prec = B.PRECISIONS[prec_name]
     arena = torch.empty(arena_gib << 30, dtype=torch.uint8, device=torch.device("cuda:0"))
@@ -228,11 +237,12 @@ def bench_served_sweep(B, ctx, torch, rates, seconds: float, prec_name: str, are
         work = sum(flops_of(B, c) for _, c in trace)
         row = {"rate": rate, "requests": count, "offered_req_per_s": round(offered, 2),
                "offered_tflops": round(work / trace[-1][0] / 1e12, 1), "mean_tflop_per_request": round(work / count / 1e12, 2)}
-        for name, mode, act, pol in (("continuous_least_work_first", B.QSIM_SERVE_CONTINUOUS, 64,
-                                      B.QSIM_POLICY_SHORTEST),
-                                     ("continuous_least_work_first_aged", B.QSIM_SERVE_CONTINUOUS, 64,
-                                      B.QSIM_POLICY_AGED),
-                                     ("plain_fifo", B.QSIM_SERVE_FIFO, 1, 0)):
+        modes = {"lwf": (B.QSIM_SERVE_CONTINUOUS, 64, B.QSIM_POLICY_SHORTEST),
+                 "aged": (B.QSIM_SERVE_CONTINUOUS, 64, B.QSIM_POLICY_AGED),
+                 "fifo": (B.QSIM_SERVE_FIFO, 1, 0)}
+        for key in policies:
+            name = SWEEP_POLICIES[key]
+            mode, act, pol = modes[key]
             r = replay_trace(B, ctx, torch, trace, prec, mode, arena, act, pol, 2.0, 100.0, drift)
             r["meets_slo"] = r["p99_ms"] <= slo_ms
             row[name] = r
@@ -241,10 +251,10 @@ def bench_served_sweep(B, ctx, torch, rates, seconds: float, prec_name: str, are
         rows.append(row)
     del arena
     torch.cuda.empty_cache()
-    best = {m: max([r["rate"] for r in rows if r[m]["meets_slo"]] or [0])
-            for m in ("continuous_least_work_first", "continuous_least_work_first_aged", "plain_fifo")}
+    names = [SWEEP_POLICIES[k] for k in policies]
+    best = {m: max([r["rate"] for r in rows if r[m]["meets_slo"]] or [0]) for m in names}
     top = rows[-1]
-    capacity = max(top["continuous_least_work_first"]["achieved_tflops"], top["plain_fifo"]["achieved_tflops"])
+    capacity = max(top[m]["achieved_tflops"] for m in names)
     mean_work = sum(r["mean_tflop_per_request"] * r["requests"] for r in rows) / sum(r["requests"] for r in rows)
     return {"workload": f"Poisson arrivals (seed 1) at each rate for ~{seconds:g} s, n ~ U{{6..13}}, depth ~ "
                         f"U{{10..40}}, {prec_name}, float64 {DRIFT_TEXT[drift]} per request",
@@ -253,11 +263,12 @@ def bench_served_sweep(B, ctx, torch, rates, seconds: float, prec_name: str, are
             "throughput_bound_rate": round(capacity / mean_work, 2)}
 
 
-def bench_precision_sweep(B, ctx, torch, sizes, depth: int):
-    """Config 3: seeded random_layers(n, depth) chains at 12 and 13 qubits in every precision, timed, with the
-    product's roofline fraction and the float64 drift of each result; and the QFT chain at the same n in every
-    precision against its closed form U[j][k] = w^{jk}/sqrt(N) (max |dU| over sampled columns, and the fidelity of
-    U e_0 with the uniform state). No oracle is involved: random circuits are assessed by drift, QFT by its formula."""
+def bench_precision_sweep(B, ctx, torch, sizes, depth: int, seeds, precisions):
+    """Config 3: seeded random_layers(n, depth, default_rng(s)) chains, s in `seeds`, at 12 and 13 qubits in every
+    precision, timed, with the product's roofline fraction and the float64 drift of each result; and the QFT chain
+    at the same n in every precision against its closed form U[j][k] = w^{jk}/sqrt(N) (max |dU| over sampled
+    columns, and the fidelity of U e_0 with the uniform state). The QFT chain runs first and also warms the
+    kernels. No oracle is involved: random circuits are assessed by drift, QFT by its formula."""
     import numpy as np
     from paper_2305_14398_amd import workloads as W
     dev = torch.device("cuda:0")
@@ -265,24 +276,14 @@ def bench_precision_sweep(B, ctx, torch, sizes, depth: int):
     for n in sizes:
         N = 1 << n
         U = torch.empty((2, N, N), dtype=torch.float32, device=dev)
-        rand = W.random_layers(n, depth, np.random.default_rng(0))
+        rands = [W.random_layers(n, depth, np.random.default_rng(s)) for s in seeds]
         qft = W.qft(n)
         cols = W.random_columns(n, 16, 1)
         w = np.exp(2j * np.pi / N)
         closed = np.stack([w ** ((np.arange(N) * c) % N) for c in cols], axis=1) / math.sqrt(N)
-        for pname in ("fp32_4m", "fp32_3m", "split_bf16", "split_fp16"):
+        for pname in precisions:
             prec = B.PRECISIONS[pname]
             ws = torch.empty(B.qsim_chain_workspace_bytes(n, prec), dtype=torch.uint8, device=dev)
-            B.qsim_unitary_chain(ctx, n, rand.gates, prec, U, ws)  # warm-up
-            torch.cuda.synchronize()
-            B.qsim_profile_enable(ctx, 1)
-            t0 = time.perf_counter()
-            B.qsim_unitary_chain(ctx, n, rand.gates, prec, U, ws)
-            torch.cuda.synchronize()
-            wall = time.perf_counter() - t0
-            launches, kms = B.qsim_profile_read(ctx)["product"]
-            B.qsim_profile_enable(ctx, 0)
-            drift = B.qsim_unitarity_drift(ctx, n, U)
             B.qsim_unitary_chain(ctx, n, qft.gates, prec, U, ws)
             torch.cuda.synchronize()
             Uc = U[:, :, cols].double().cpu().numpy()
@@ -290,22 +291,40 @@ def bench_precision_sweep(B, ctx, torch, sizes, depth: int):
             col0 = U[:, :, 0].double().cpu().numpy()
             psi = col0[0] + 1j * col0[1]
             fid = abs(np.sum(psi) / math.sqrt(N)) ** 2 / float(np.sum(np.abs(psi) ** 2))
-            fl = flops_of(B, rand)
+            walls, drifts, products = [], [], []
+            launches = kms = 0.0
+            for rand in rands:
+                B.qsim_profile_enable(ctx, 1)
+                t0 = time.perf_counter()
+                B.qsim_unitary_chain(ctx, n, rand.gates, prec, U, ws)
+                torch.cuda.synchronize()
+                walls.append(time.perf_counter() - t0)
+                cnt, tot = B.qsim_profile_read(ctx)["product"]
+                B.qsim_profile_enable(ctx, 0)
+                launches += cnt
+                kms += tot
+                products.append(cnt)
+                drifts.append(B.qsim_unitarity_drift(ctx, n, U))
+            fl = sum(flops_of(B, r) for r in rands)
             per = 8.0 * N ** 3 / (kms / max(launches, 1) * 1e-3) / 1e12
             ceiling = PEAK_TFLOPS[pname] / ISSUED_PER_COUNTED[pname]
             out[f"{n}q_{pname}"] = {
-                "chain_ms": round(wall * 1e3, 2), "products": launches, "chain_tflops": round(fl / wall / 1e12, 1),
+                "seeds": list(seeds), "products_per_seed": products,
+                "chain_ms_per_seed": [round(x * 1e3, 2) for x in walls],
+                "chain_tflops": round(fl / sum(walls) / 1e12, 1),
                 "product_tflops": round(per, 1), "product_frac_of_ceiling": round(per / ceiling, 4),
+                "product_issued_tflops": round(per * ISSUED_PER_COUNTED[pname], 1),
                 "ceiling_tflops": round(ceiling, 1),
-                "random_drift_max": drift[0], "random_drift_fro": drift[1],
+                "random_drift_max_per_seed": [d[0] for d in drifts], "random_drift_fro_per_seed": [d[1] for d in drifts],
                 "qft_max_abs_dU_sampled": float(np.abs(Uc - closed).max()), "qft_state_fidelity": fid}
-            progress(f"precision sweep {n}q {pname}: {wall*1e3:.1f} ms, product {per:.1f} TFLOP/s, "
-                     f"qft |dU| {out[f'{n}q_{pname}']['qft_max_abs_dU_sampled']:.2e}")
+            progress(f"precision sweep {n}q {pname}: {sum(walls)*1e3:.1f} ms over {len(seeds)} seeds, product "
+                     f"{per:.1f} TFLOP/s, qft |dU| {out[f'{n}q_{pname}']['qft_max_abs_dU_sampled']:.2e}")
             del ws
         del U
         torch.cuda.empty_cache()
-    out["workload"] = (f"random_layers(n, {depth}, default_rng(0)) and qft(n) for n in {list(sizes)}; "
-                       "chain timing with HIP events per product; errors against closed forms and float64 drift")
+    out["workload"] = (f"random_layers(n, {depth}, default_rng(s)) for s in {list(seeds)} and qft(n), n in "
+                       f"{list(sizes)}; chain timing with HIP events per product; errors against closed forms and "
+                       f"float64 drift")
     return out
 
 
@@ -348,6 +367,30 @@ def bench_fsv(B, ctx, torch, n: int, reps: int):
     return out
 
 
+def measure_peaks(B, ctx, torch, copy_mib: int):
+    """On-box peaks next to the vendor ones: MFMA issue rate per dtype (independent accumulator chains, random
+    and constant operands) and a streaming HBM copy (qsim_probe_mfma / qsim_probe_copy)."""
+    vendor = {"mfma_f32": 157.3, "mfma_bf16": 2500.0, "mfma_f16": 2500.0, "mfma_f64": 78.6}
+    out = {}
+    for name, kind in B.PROBE_KINDS.items():
+        rnd = B.qsim_probe_mfma(ctx, kind, True)
+        const = B.qsim_probe_mfma(ctx, kind, False)
+        out[name] = {"random_operands_tflops": round(rnd, 1), "constant_operands_tflops": round(const, 1),
+                     "vendor_tflops": vendor[name], "random_frac_of_vendor": round(rnd / vendor[name], 4)}
+    nbytes = copy_mib << 20
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=torch.device("cuda:0"))
+    dst = torch.empty_like(src)
+    gbs = B.qsim_probe_copy(ctx, src, dst, nbytes)
+    del src, dst
+    torch.cuda.empty_cache()
+    out["hbm_copy"] = {"gb_per_s": round(gbs, 1), "bytes": nbytes, "vendor_gb_per_s": HBM_PEAK_GBS,
+                       "frac_of_vendor": round(gbs / HBM_PEAK_GBS, 4),
+                       "note": "read + write bytes of a 16-byte-vector device copy"}
+    out["method"] = ("MFMA: 2048 workgroups x 256 threads, four independent accumulator chains per wave, "
+                     "flops = 2 x M x N x K per instruction; random operands toggle their mantissa bits")
+    return out
+
+
 def counted_traffic(profile: str, source: str):
     """HBM bytes per launch from a committed rocprofv3 counter summary, or None when the kernel source changed
     since the counters were taken (the summary stores the source's sha256)."""
@@ -363,41 +406,59 @@ def counted_traffic(profile: str, source: str):
     return int(fields["hbm_bytes_per_launch"])
 
 
-def cpu_baseline(n: int, budget_s: float):
-    """The oracle (route A, complex128 numpy/OpenBLAS) on the first steps of qft(n) within a time budget."""
+def cpu_baseline(n: int, budget_s: float, warmups: int = 3, runs: int = 11):
+    """The oracle (route A: dense step operators and complex128 numpy/OpenBLAS products, all host cores) on the
+    bench's circuits, after the paper's protocol (Section 6.1: warm-ups, then the mean of the next runs): the
+    seeded balanced Deutsch-Jozsa(n) circuit `warmups` times untimed, then the mean of `runs` timed runs; the
+    QFT(n) once (its products are 8x more than the Deutsch-Jozsa's); and one product each at n + 1 and n + 2
+    qubits, whose time x the product count of random_layers(n', 20) is reported as an extrapolated chain time.
+    A single-BLAS-thread run over the first steps of the QFT is the analogue of the paper's single-threaded
+    baseline."""
     import numpy as np
-    from threadpoolctl import threadpool_info
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle import unitary as UA
     from paper_2305_14398_amd import workloads as W
 
-    steps = UA.pack_steps(W.gate_tuples(W.qft(n)))
-    N = 1 << n
-    # warm the BLAS threads once on a small product
-    a = np.ones((256, 256), dtype=np.complex128)
-    a @ a
-    t0 = time.perf_counter()
-    result = np.eye(N, dtype=np.complex128)
-    products = 0
-    for st in steps:
-        result = UA.step_operator(n, st) @ result
-        products += 1
-        if time.perf_counter() - t0 > budget_s and products >= 2:
-            break
-    dt = time.perf_counter() - t0
-    threads = max([p.get("num_threads", 1) for p in threadpool_info() if p.get("internal_api") == "openblas"] or [1])
-    # one BLAS thread: the analogue of the paper's single-threaded baseline, on a few products
-    from threadpoolctl import threadpool_limits
-    with threadpool_limits(limits=1):
-        t1 = time.perf_counter()
-        r1 = np.eye(N, dtype=np.complex128)
-        single = 0
-        for st in steps:
-            r1 = UA.step_operator(n, st) @ r1
-            single += 1
-            if time.perf_counter() - t1 > budget_s / 3 and single >= 1:
+    def chain(steps, nq, limit_s=None):
+        t0 = time.perf_counter()
+        result = UA.step_operator(nq, steps[0])
+        done = 0
+        for st in steps[1:]:
+            result = UA.step_operator(nq, st) @ result
+            done += 1
+            if limit_s is not None and time.perf_counter() - t0 > limit_s and done >= 1:
                 break
-        dt1 = time.perf_counter() - t1
+        return time.perf_counter() - t0, done
+
+    N = 1 << n
+    per = 8.0 * N ** 3
+    dj_steps = UA.pack_steps(W.gate_tuples(W.dj(n, W.dj_mask(n, 0))))
+    for _ in range(warmups):
+        chain(dj_steps, n)
+    times = [chain(dj_steps, n)[0] for _ in range(runs)]
+    dj_mean = sum(times) / len(times)
+    dj_products = len(dj_steps) - 1
+    qft_steps = UA.pack_steps(W.gate_tuples(W.qft(n)))
+    t_qft, qft_done = chain(qft_steps, n, limit_s=budget_s)
+    threads = max([p.get("num_threads", 1) for p in threadpool_info() if p.get("internal_api") == "openblas"] or [1])
+    per_gemm = {}
+    for m in (n + 1, n + 2):
+        M = 1 << m
+        rl = W.random_layers(m, 20, np.random.default_rng(0))
+        steps = UA.pack_steps(W.gate_tuples(rl))
+        A = UA.step_operator(m, steps[1])
+        X = UA.step_operator(m, steps[0])
+        t0 = time.perf_counter()
+        A @ X
+        dt = time.perf_counter() - t0
+        per_gemm[f"{m}q"] = {"gemm_s": round(dt, 3), "tflops": round(8.0 * M ** 3 / dt / 1e12, 3),
+                             "random_layers_20_products": len(steps) - 1,
+                             "extrapolated_chain_s": round(dt * (len(steps) - 1), 1),
+                             "note": "one product timed; the chain time is extrapolated (x products), not measured"}
+        del A, X
+    with threadpool_limits(limits=1):
+        t1, single = chain(qft_steps, n, limit_s=budget_s / 3)
     cpu_model = ""
     try:
         for line in open("/proc/cpuinfo"):
@@ -408,15 +469,20 @@ def cpu_baseline(n: int, budget_s: float):
         pass
     blas = [f"{p.get('internal_api')} {p.get('version')}" for p in threadpool_info() if p.get("user_api") == "blas"]
     return {
-        "value": 8.0 * N ** 3 * products / dt / 1e12,
+        "value": per * dj_products / dj_mean / 1e12,
         "unit": "TFLOP/s",
         "host": {"cpu_model": cpu_model, "cpus_visible": os.cpu_count(), "blas": blas},
         "cores": int(threads),
         "kind": "oracle",
-        "sample": f"route A (dense step + complex128 matmul) over the first {products} of {len(steps)} steps of "
-                  f"qft({n}); {dt:.1f} s; {os.cpu_count()} host CPUs visible",
-        "single_thread": {"value": 8.0 * N ** 3 * single / dt1 / 1e12, "unit": "TFLOP/s", "cores": 1,
-                          "sample": f"the first {single} steps of qft({n}) with one BLAS thread; {dt1:.1f} s"},
+        "sample": f"route A over deutsch_jozsa({n}) (mask seed 0, {dj_products} products): {warmups} warm-ups, "
+                  f"then the mean of {runs} runs ({dj_mean:.3f} s each); {os.cpu_count()} host CPUs visible",
+        "dj_circuits_per_s": round(1.0 / dj_mean, 3),
+        "dj_run_s": [round(x, 4) for x in times],
+        "qft": {"products": qft_done, "of": len(qft_steps) - 1, "s": round(t_qft, 3),
+                "tflops": round(per * qft_done / t_qft / 1e12, 3), "runs": 1},
+        "per_gemm": per_gemm,
+        "single_thread": {"value": per * single / t1 / 1e12, "unit": "TFLOP/s", "cores": 1,
+                          "sample": f"the first {single + 1} steps of qft({n}) with one BLAS thread; {t1:.1f} s"},
     }
 
 
@@ -426,7 +492,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--prec", default="fp32_3m", choices=sorted(PEAK_TFLOPS))
-    ap.add_argument("--variant", default="fp32_4m,split_fp16,split_bf16",
+    ap.add_argument("--variant", default="fp32_4m,split_fp16,split_bf16,split_fp16_3m,split_bf16_3m",
                     help="comma-separated further precisions timed on the same workload ('' to skip)")
     ap.add_argument("--fused", default="fp32_3m",
                     help="float32 precisions also timed with stages 4 and 5 fused ('' to skip)")
@@ -441,9 +507,14 @@ def main() -> int:
                     help="drift check per served request: the full ||U^H U - I|| or the two-pass probe")
     ap.add_argument("--fsv", type=int, default=30, help="qubits of the full-state-vector workload (0: skip)")
     ap.add_argument("--sweep-qubits", default="12,13", help="qubit counts of the precision sweep ('' to skip)")
-    ap.add_argument("--served-sweep", default="", help="comma-separated Poisson rates for an offered-rate sweep")
-    ap.add_argument("--served-sweep-seconds", type=float, default=10.0)
+    ap.add_argument("--sweep-seeds", default="0,1,2,3,4", help="seeds of the precision sweep's random circuits")
+    ap.add_argument("--sweep-precisions", default="fp32_4m,fp32_3m,split_bf16,split_fp16,split_bf16_3m,split_fp16_3m")
+    ap.add_argument("--served-sweep", default="4,8,12",
+                    help="comma-separated Poisson rates for an offered-rate sweep ('' to skip)")
+    ap.add_argument("--served-sweep-seconds", type=float, default=5.0)
+    ap.add_argument("--served-sweep-policies", default="aged,fifo", help=f"of {sorted(SWEEP_POLICIES)}")
     ap.add_argument("--served-slo-ms", type=float, default=2500.0)
+    ap.add_argument("--peaks", type=int, default=1, help="measure on-box MFMA and HBM peaks (0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a known-size kernel that "
                          "scales the HBM byte counters of a profiler run)")
@@ -638,6 +709,12 @@ def main() -> int:
         "note": "expand + chain + apply + float64 norm, each state copied to pinned host memory (no drift check)"}
     del ws_main
     progress(f"headline done: {tflops:.1f} TFLOP/s")
+    if args.peaks:
+        out["peaks"] = measure_peaks(B, ctx, torch, 1024)
+        mp = out["peaks"][PROBE_OF[args.prec]]["random_operands_tflops"] / ISSUED_PER_COUNTED[args.prec]
+        out["roofline"]["measured_peak"] = round(mp, 1)
+        out["roofline"]["frac_of_measured_peak"] = round(achieved / mp, 4)
+        progress("peaks done")
     if args.batched:
         out["batched"] = bench_batched(B, ctx, torch, args.batched, 0, "fp32_4m" if args.prec == "fp32_4m"
                                        else args.prec, reps=2)
@@ -647,12 +724,15 @@ def main() -> int:
                                      drift=args.served_drift)
         progress("served done")
     if args.sweep_qubits:
-        out["precision_sweep"] = bench_precision_sweep(B, ctx, torch, [int(x) for x in args.sweep_qubits.split(",")], 20)
+        out["precision_sweep"] = bench_precision_sweep(B, ctx, torch, [int(x) for x in args.sweep_qubits.split(",")], 20,
+                                                       [int(x) for x in args.sweep_seeds.split(",")],
+                                                       [p for p in args.sweep_precisions.split(",") if p])
         progress("precision sweep done")
     if args.served_sweep:
         rates = [float(x) for x in args.served_sweep.split(",") if x]
         out["served_sweep"] = bench_served_sweep(B, ctx, torch, rates, args.served_sweep_seconds, args.served_prec, 96,
-                                                 args.served_slo_ms, args.served_drift)
+                                                 args.served_slo_ms, args.served_drift,
+                                                 [p for p in args.served_sweep_policies.split(",") if p])
         progress("served sweep done")
     if args.fsv:
         out["full_state"] = bench_fsv(B, ctx, torch, args.fsv, reps=3)

@@ -23,8 +23,17 @@
  *   [N*N + c*N + r].
  * Split 16-bit operands (QSIM_SPLIT_BF16 / QSIM_SPLIT_FP16): four N x N
  *   16-bit planes in the order re_hi, re_lo, im_hi, im_lo (8*N*N bytes),
- *   value = hi + lo * 2^-QSIM_LO_SCALE_LOG2 (lo is stored pre-scaled;
- *   the scale is 2^0 for bf16).
+ *   value = hi + lo * 2^-QSIM_LO_SCALE_LOG2 for fp16 (lo is stored
+ *   pre-scaled) and hi + lo for bf16.  The three-product split precisions
+ *   (QSIM_SPLIT_BF16_3M / QSIM_SPLIT_FP16_3M) add two planes sum_hi, sum_lo
+ *   holding the split of the float32 sum re + im (12*N*N bytes, six planes);
+ *   qsim_op_bytes gives the size of one operand in any precision.  From
+ *   n_qubits = 6 on, three-product operands are fragment-blocked: with i the
+ *   storage row and k the storage column (the contraction index), element
+ *   (plane p, i, k) is at 16-bit index
+ *     (((i/32) * (N/16) + k/16) * 6 + p) * 512 + ((i%32) + 32*((k/8)%2)) * 8 + k%8,
+ *   i.e. 32 x 16 blocks in row-block-major order, each holding its six planes
+ *   as contiguous 1 KiB MFMA fragments.  Below 6 qubits they are planar.
  * State vectors: planar complex64, N float32 real parts then N imaginary.
  * Device pointers are hipMalloc'd (or torch-allocated) memory on the
  *   context's device, 256-byte aligned, owned by the caller; the library does
@@ -68,7 +77,9 @@ typedef enum qsim_precision {
     QSIM_FP32_4M = 0,     /* float32 MFMA, four real products per complex product */
     QSIM_FP32_3M = 1,     /* float32 MFMA, three real products (Gauss) */
     QSIM_SPLIT_BF16 = 2,  /* operands split into bf16 hi + lo, three bf16 MFMA passes, fp32 accumulate */
-    QSIM_SPLIT_FP16 = 3   /* operands split into fp16 hi + scaled lo, three passes, fp32 accumulate */
+    QSIM_SPLIT_FP16 = 3,  /* operands split into fp16 hi + scaled lo, three passes, fp32 accumulate */
+    QSIM_SPLIT_BF16_3M = 4, /* as QSIM_SPLIT_BF16 with three real products (Gauss): 9 MFMAs per k-block, not 12 */
+    QSIM_SPLIT_FP16_3M = 5  /* as QSIM_SPLIT_FP16 with three real products (Gauss) */
 } qsim_precision;
 
 /* Gate kinds.  A gate with control >= 0 is the controlled version of its kind
@@ -147,14 +158,22 @@ qsim_status qsim_pack_steps(int n_qubits, const qsim_gate* gates, int n_gates,
  * (scratch step operator + ping-pong chain buffers), or 0 if out of range. */
 size_t qsim_chain_workspace_bytes(int n_qubits, int prec);
 
+/* Bytes of one N x N operand in the format of `prec` (what qsim_build_step
+ * writes and qsim_step_multiply reads): 8*N*N for the float32 precisions and
+ * the four-plane split ones, 12*N*N for the six-plane three-product split
+ * ones; 0 if out of range. */
+size_t qsim_op_bytes(int n_qubits, int prec);
+
 /* Stage 4 (Algorithm 2, Eq. 9s1): write the dense operator of ONE step.
  * gates[0..n_gates) must have pairwise disjoint spans (QSIM_E_INVALID
  * otherwise).  Each entry is the product over the step's gates of their
  * matrix entries (identity on idle qubits), computed in float64 and rounded
  * once to the output format.
  * prec QSIM_FP32_4M / QSIM_FP32_3M: planar complex64 in `layout`;
- * prec QSIM_SPLIT_BF16 / QSIM_SPLIT_FP16: split 16-bit planes in `layout`.
- * d_op: 8*N*N bytes, caller-owned. */
+ * prec QSIM_SPLIT_BF16 / QSIM_SPLIT_FP16: four split 16-bit planes in `layout`;
+ * prec QSIM_SPLIT_BF16_3M / QSIM_SPLIT_FP16_3M: six planes, the last two the
+ *      split of the float32 sum of each entry's rounded real and imaginary parts.
+ * d_op: qsim_op_bytes(n_qubits, prec) bytes, caller-owned. */
 qsim_status qsim_build_step(qsim_ctx* ctx, int n_qubits, const qsim_gate* gates, int n_gates,
                             int prec, int layout, void* d_op, void* stream);
 
@@ -164,11 +183,14 @@ qsim_status qsim_build_step(qsim_ctx* ctx, int n_qubits, const qsim_gate* gates,
  *   QSIM_FP32_4M / QSIM_FP32_3M: d_S planar complex64 COLUMN-major, d_Uin
  *      planar complex64 row-major, d_Uout (required) planar complex64
  *      row-major; d_Uout_split must be NULL.
- *   QSIM_SPLIT_BF16 / QSIM_SPLIT_FP16: d_S split planes ROW-major, d_Uin split
- *      planes COLUMN-major.  d_Uout (optional): C as planar complex64
- *      row-major; d_Uout_split (optional): C as split planes column-major, i.e.
- *      the d_Uin of the next product.  At least one output; each requested
- *      output costs one kernel launch.
+ *   QSIM_SPLIT_BF16 / QSIM_SPLIT_FP16 (four planes) and QSIM_SPLIT_BF16_3M /
+ *      QSIM_SPLIT_FP16_3M (six planes, qsim_op_bytes): d_S split planes
+ *      ROW-major, d_Uin split planes COLUMN-major.  d_Uout (optional): C as
+ *      planar complex64 row-major; d_Uout_split (optional): C as split planes
+ *      column-major, i.e. the d_Uin of the next product.  At least one output;
+ *      each requested output costs one kernel launch.  The three-product forms
+ *      take T1 = Sr Ur, T2 = Si Ui, T3 = (Sr + Si)(Ur + Ui), Re C = T1 - T2,
+ *      Im C = T3 - T1 - T2 (9 MFMAs per 16-deep k-block instead of 12).
  * Outputs must not alias inputs or each other. */
 qsim_status qsim_step_multiply(qsim_ctx* ctx, int n_qubits, int prec, const void* d_S,
                                const void* d_Uin, void* d_Uout, void* d_Uout_split, void* stream);
@@ -184,7 +206,8 @@ qsim_status qsim_step_multiply(qsim_ctx* ctx, int n_qubits, int prec, const void
  *      n_steps+1 monotone offsets with offsets[0] = 0 and offsets[n_steps] =
  *      n_gates, each step of pairwise disjoint spans and 1..16 gates.
  * d_ws: device workspace of ws_bytes >= qsim_chain_workspace_bytes(n, prec)
- *      (2 matrices for float32, 3 for split precisions), not overlapping d_U.
+ *      (2 matrices for float32, 3 operands of qsim_op_bytes for split
+ *      precisions), not overlapping d_U.
  * n_gates == 0 yields the identity. */
 qsim_status qsim_unitary_chain(qsim_ctx* ctx, int n_qubits, const qsim_gate* gates, int n_gates,
                                const int32_t* step_offsets, int n_steps, int prec,
@@ -293,7 +316,8 @@ typedef struct qsim_circuit_desc {
 
 typedef struct qsim_batch_plan qsim_batch_plan;
 
-/* Workspace a batch needs (2 matrices per circuit for float32, 3 for split precisions, each rounded up to 256 bytes). */
+/* Workspace a batch needs (2 matrices per circuit for float32, 3 operands of qsim_op_bytes for split
+ * precisions, each rounded up to 256 bytes). */
 qsim_status qsim_batch_workspace_bytes(const qsim_circuit_desc* circuits, int count, int prec, size_t* out);
 /* Validate the batch, build and upload the job tables of every iteration (this
  * allocates the tables on the device; launching allocates nothing).  The
@@ -329,9 +353,10 @@ qsim_status qsim_tune_set(qsim_ctx* ctx, int prec, int n_qubits, int tile);
 /* ---- Serving: continuous batching of submitted circuits ----
  * qsim_serve_start runs an engine thread for the context with its own HIP
  * stream.  A request is admitted in arrival order once the caller's device
- * arena has room for its footprint (chain workspace: 2 matrices for float32,
- * 3 for split precisions, plus U when d_U is NULL; 8*N*N bytes per matrix,
- * each rounded up to 256) and fewer than max_active requests are admitted.
+ * arena has room for its footprint (chain workspace: 2 matrices of 8*N*N
+ * bytes for float32, 3 operands of qsim_op_bytes for split precisions, plus U
+ * (8*N*N) when d_U is NULL; each rounded up to 256) and fewer than max_active
+ * requests are admitted.
  * QSIM_SERVE_CONTINUOUS: every engine iteration advances every admitted
  *   request by one step (stages 4-5) in one grouped expansion launch and one
  *   grouped product launch; a request whose chain is complete gets stage 6
@@ -517,6 +542,23 @@ qsim_status qsim_fsv_norm2(qsim_ctx* ctx, int n_qubits, const void* d_psi, doubl
 size_t qsim_fsv_sample_workspace_bytes(int n_qubits);
 qsim_status qsim_fsv_sample(qsim_ctx* ctx, int n_qubits, const void* d_psi, const double* d_uniform, int shots,
                             int64_t* d_out, void* d_ws, size_t ws_bytes, void* stream);
+
+/* ---- Device peaks (measurement) ----
+ * The rooflines are quoted against vendor peaks; these probes measure what one
+ * device sustains.  qsim_probe_mfma: the issue rate of one MFMA shape with
+ * four independent accumulator chains per wave (no dependency stalls),
+ * 2048 workgroups x 256 threads, in TFLOP/s (2 flops per multiply-add):
+ *   kind 0 v_mfma_f32_32x32x2f32, 1 v_mfma_f32_32x32x16_bf16,
+ *   2 v_mfma_f32_32x32x16_f16, 3 v_mfma_f64_16x16x4f64.
+ * random_operands != 0: operands with pseudo-random mantissas (toggling bits,
+ * as in dense products; the chip may lower its clock); 0: constant operands.
+ * Writes one float per workgroup into the context's scratch; synchronous.
+ * qsim_probe_copy: a streaming device copy of `bytes` (multiple of 16) from
+ * d_src to d_dst (non-overlapping, 256-byte aligned), 16-byte loads and
+ * stores; *gbs_out = 2 * bytes / time (read + write), mean of 10 copies after
+ * one warm-up; synchronous. */
+qsim_status qsim_probe_mfma(qsim_ctx* ctx, int kind, int random_operands, double* tflops_out);
+qsim_status qsim_probe_copy(qsim_ctx* ctx, const void* d_src, void* d_dst, size_t bytes, double* gbs_out);
 
 #ifdef __cplusplus
 }

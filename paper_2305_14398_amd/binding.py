@@ -23,7 +23,8 @@ STATUS_NAMES = {0: "QSIM_OK", 1: "QSIM_PENDING", -1: "QSIM_E_INVALID", -2: "QSIM
                 -4: "QSIM_E_DEVICE", -5: "QSIM_E_FULL", -6: "QSIM_E_UNKNOWN_ID"}
 
 QSIM_FP32_4M, QSIM_FP32_3M, QSIM_SPLIT_BF16, QSIM_SPLIT_FP16 = 0, 1, 2, 3
-PRECISIONS = {"fp32_4m": 0, "fp32_3m": 1, "split_bf16": 2, "split_fp16": 3}
+QSIM_SPLIT_BF16_3M, QSIM_SPLIT_FP16_3M = 4, 5
+PRECISIONS = {"fp32_4m": 0, "fp32_3m": 1, "split_bf16": 2, "split_fp16": 3, "split_bf16_3m": 4, "split_fp16_3m": 5}
 QSIM_LAYOUT_ROW, QSIM_LAYOUT_COL = 0, 1
 
 KIND = {"H": 0, "X": 1, "Y": 2, "Z": 3, "S": 4, "T": 5, "R": 6, "RX": 7, "RY": 8, "RZ": 9, "U2": 10, "SWAP": 11,
@@ -126,6 +127,9 @@ def lib() -> ctypes.CDLL:
         "qsim_ctx_destroy": (i32, [vp]),
         "qsim_pack_steps": (i32, [i32, gp, i32, ip, ctypes.POINTER(i32)]),
         "qsim_chain_workspace_bytes": (sz, [i32, i32]),
+        "qsim_op_bytes": (sz, [i32, i32]),
+        "qsim_probe_mfma": (i32, [vp, i32, i32, ctypes.POINTER(dbl)]),
+        "qsim_probe_copy": (i32, [vp, vp, vp, sz, ctypes.POINTER(dbl)]),
         "qsim_build_step": (i32, [vp, i32, gp, i32, i32, i32, vp, vp]),
         "qsim_step_multiply": (i32, [vp, i32, i32, vp, vp, vp, vp, vp]),
         "qsim_unitary_chain": (i32, [vp, i32, gp, i32, ip, i32, i32, vp, vp, sz, vp]),
@@ -299,6 +303,10 @@ def qsim_pack_steps(n_qubits: int, gates: Sequence) -> list:
 
 def qsim_chain_workspace_bytes(n_qubits: int, prec: int) -> int:
     return int(lib().qsim_chain_workspace_bytes(n_qubits, prec))
+
+
+def qsim_op_bytes(n_qubits: int, prec: int) -> int:
+    return int(lib().qsim_op_bytes(n_qubits, prec))
 
 
 def qsim_build_step(ctx, n_qubits: int, gates: Sequence, prec: int, layout: int, d_op, stream=None) -> None:
@@ -627,3 +635,20 @@ def qsim_fsv_sample(ctx, n_qubits: int, d_psi, d_uniform, shots: int, d_out, d_w
         ws_bytes = d_ws.numel() * d_ws.element_size() if hasattr(d_ws, "numel") else 0
     _check(lib().qsim_fsv_sample(_h(ctx), n_qubits, _ptr(d_psi), _ptr(d_uniform), shots, _ptr(d_out), _ptr(d_ws),
                                  ws_bytes, st), "qsim_fsv_sample")
+
+
+# --- device peaks (measurement) ---------------------------------------------------------------
+
+PROBE_KINDS = {"mfma_f32": 0, "mfma_bf16": 1, "mfma_f16": 2, "mfma_f64": 3}
+
+
+def qsim_probe_mfma(ctx, kind: int, random_operands: bool = True) -> float:
+    out = ctypes.c_double()
+    _check(lib().qsim_probe_mfma(_h(ctx), kind, 1 if random_operands else 0, ctypes.byref(out)), "qsim_probe_mfma")
+    return out.value
+
+
+def qsim_probe_copy(ctx, d_src, d_dst, nbytes: int) -> float:
+    out = ctypes.c_double()
+    _check(lib().qsim_probe_copy(_h(ctx), _ptr(d_src), _ptr(d_dst), nbytes, ctypes.byref(out)), "qsim_probe_copy")
+    return out.value

@@ -45,7 +45,7 @@ bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 
 
 bool valid_n(int n) { return n >= 1 && n <= QSIM_MAX_QUBITS; }
 
-bool valid_prec(int p) { return p >= QSIM_FP32_4M && p <= QSIM_SPLIT_FP16; }
+bool valid_prec(int p) { return p >= QSIM_FP32_4M && p <= QSIM_SPLIT_FP16_3M; }
 
 // Precisions with a kernel in this library.
 static bool built_prec(int p) { return valid_prec(p); }
@@ -313,8 +313,9 @@ qsim_status chain_impl(int n, const qsim_gate* gates, int n_gates, const int32_t
     // form (two ping-pong buffers), each step operator row-major in split form;
     // the last product is taken in the direct orientation and written as
     // float32 row-major into d_U.
+    const size_t ob = op_bytes(n, prec);
     void* S = ws;
-    void* P[2] = {ws + mb, ws + 2 * mb};
+    void* P[2] = {ws + ob, ws + 2 * ob};
     const int k = n_steps;
     s = make_step(n, gates + off[0], off[1] - off[0], st);
     if (s != QSIM_OK) return s;
@@ -399,7 +400,12 @@ qsim_status qsim_pack_steps(int n_qubits, const qsim_gate* gates, int n_gates, i
 
 size_t qsim_chain_workspace_bytes(int n_qubits, int prec) {
     if (!valid_n(n_qubits) || !valid_prec(prec)) return 0;
-    return (format_of(prec) == FMT_F32 ? 2 : 3) * mat_bytes(n_qubits);
+    return format_of(prec) == FMT_F32 ? 2 * mat_bytes(n_qubits) : 3 * op_bytes(n_qubits, prec);
+}
+
+size_t qsim_op_bytes(int n_qubits, int prec) {
+    if (!valid_n(n_qubits) || !valid_prec(prec)) return 0;
+    return op_bytes(n_qubits, prec);
 }
 
 size_t qsim_chain_fused_workspace_bytes(int n_qubits, int prec) {

@@ -40,7 +40,9 @@ namespace {
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-size_t per_circuit_ws(int n, int prec) { return (prec >= QSIM_SPLIT_BF16 ? 3 : 2) * align256(mat_bytes(n)); }
+size_t per_circuit_ws(int n, int prec) {
+    return is_split(prec) ? 3 * align256(op_bytes(n, prec)) : 2 * align256(mat_bytes(n));
+}
 
 qsim_status check_desc(const qsim_circuit_desc& c, int idx, std::vector<int32_t>& off) {
     if (!valid_n(c.n_qubits)) return fail(QSIM_E_RANGE, "circuit %d: n_qubits %d outside 1..%d", idx, c.n_qubits, QSIM_MAX_QUBITS);
@@ -145,7 +147,7 @@ qsim_status qsim_batch_plan_create(qsim_ctx* ctx, const qsim_circuit_desc* circu
         const qsim_circuit_desc& c = circuits[i];
         const int n = c.n_qubits;
         const int k = (int)offs[i].size() - 1;
-        const size_t mb = align256(mat_bytes(n));
+        const size_t mb = is_split(prec) ? align256(op_bytes(n, prec)) : align256(mat_bytes(n));
         char* S = ws + base;
         char* W1 = ws + base + mb;
         char* W2 = ws + base + 2 * mb;
@@ -307,7 +309,7 @@ qsim_status qsim_autotune(qsim_ctx* ctx, int prec, int n_lo, int n_hi, double* m
     if (s != QSIM_OK) return s;
     DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return device_fail("hipSetDevice", g.err);
-    const bool split = prec >= QSIM_SPLIT_BF16;
+    const bool split = is_split(prec);
     const int cus = device_cus(ctx->device);
     const int grid = grouped_gemm_grid(prec, cus);
     hipStream_t st = nullptr;
@@ -317,7 +319,7 @@ qsim_status qsim_autotune(qsim_ctx* ctx, int prec, int n_lo, int n_hi, double* m
     if (e == hipSuccess) e = hipEventCreate(&e1);
     for (int n = n_lo; n <= n_hi && e == hipSuccess; ++n) {
         const int copies = std::max(1, (2 * grid) / tiles_of(n, 128));
-        const size_t mb = align256(mat_bytes(n));
+        const size_t mb = align256(split ? op_bytes(n, prec) : mat_bytes(n));
         void* buf = nullptr;
         GemmJob* dj = nullptr;
         e = hipMalloc(&buf, 3 * mb * copies);

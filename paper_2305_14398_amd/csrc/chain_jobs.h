@@ -45,7 +45,7 @@ struct ChainCursor {
     qsim_status emit(int j, ExpandJob& E, GemmJob& Gj, bool& has_gemm) {
         std::memset(&E, 0, sizeof E);
         has_gemm = false;
-        const bool split = prec >= QSIM_SPLIT_BF16;
+        const bool split = is_split(prec);
         const OpFormat fmt = format_of(prec);
         E.n = n;
         E.blocks = expand_blocks(n);

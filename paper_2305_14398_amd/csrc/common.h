@@ -63,12 +63,28 @@ struct GemmJob {
     int32_t tiles;
 };
 
-// Output formats of the expansion kernel and operand formats of the GEMMs.
-enum OpFormat : int { FMT_F32 = 0, FMT_BF16 = 1, FMT_F16 = 2 };
+// Output formats of the expansion kernel and operand formats of the GEMMs:
+// planar float32; four split 16-bit planes (re_hi, re_lo, im_hi, im_lo); or six
+// (the same plus sum_hi, sum_lo of re + im) for the three-product split forms.
+enum OpFormat : int { FMT_F32 = 0, FMT_BF16 = 1, FMT_F16 = 2, FMT_BF16_G = 3, FMT_F16_G = 4 };
 
 inline OpFormat format_of(int prec) {
-    return prec == QSIM_SPLIT_BF16 ? FMT_BF16 : prec == QSIM_SPLIT_FP16 ? FMT_F16 : FMT_F32;
+    switch (prec) {
+        case QSIM_SPLIT_BF16: return FMT_BF16;
+        case QSIM_SPLIT_FP16: return FMT_F16;
+        case QSIM_SPLIT_BF16_3M: return FMT_BF16_G;
+        case QSIM_SPLIT_FP16_3M: return FMT_F16_G;
+        default: return FMT_F32;
+    }
 }
+inline bool is_split(int prec) { return format_of(prec) != FMT_F32; }
+// 16-bit element type of a split format (FMT_BF16 or FMT_F16), FMT_F32 otherwise.
+__host__ __device__ constexpr int fmt_elem(int fmt) {
+    return fmt == FMT_BF16_G ? FMT_BF16 : fmt == FMT_F16_G ? FMT_F16 : fmt;
+}
+__host__ __device__ constexpr bool fmt_gauss(int fmt) { return fmt == FMT_BF16_G || fmt == FMT_F16_G; }
+// Bytes of one N x N operand in a format (8 N^2 for float32 and four planes, 12 N^2 for six).
+inline size_t fmt_bytes(int fmt, int n) { return (fmt_gauss(fmt) ? 12u : 8u) * ((size_t)1 << (2 * n)); }
 
 // float32 -> bfloat16, round to nearest even (inputs are finite).
 __device__ __forceinline__ uint16_t bf16_rne(float f) {

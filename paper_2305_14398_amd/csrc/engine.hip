@@ -113,7 +113,7 @@ Engine::Engine(qsim_ctx* ctx, const qsim_serve_config& cfg) : ctx_(ctx), cfg_(cf
 
 size_t Engine::footprint(int n, const qsim_request& r) const {
     const size_t mb = a256(mat_bytes(n));
-    const size_t ws = (cfg_.prec >= QSIM_SPLIT_BF16 ? 3 : 2) * mb;
+    const size_t ws = is_split(cfg_.prec) ? 3 * a256(op_bytes(n, cfg_.prec)) : 2 * mb;
     return ws + (r.d_U ? 0 : mb);
 }
 
@@ -290,7 +290,7 @@ void Engine::admit_locked() {
         free_slots_.pop_back();
         q->res.t_start_ns = now_ns();
         char* base = static_cast<char*>(cfg_.d_arena) + off;
-        const size_t mb = a256(mat_bytes(q->n));
+        const size_t mb = is_split(cfg_.prec) ? a256(op_bytes(q->n, cfg_.prec)) : a256(mat_bytes(q->n));
         ChainCursor& cc = q->cc;
         cc.n = q->n;
         cc.k = (int)q->off.size() - 1;
@@ -301,7 +301,7 @@ void Engine::admit_locked() {
         cc.S = base;
         cc.W1 = base + mb;
         cc.W2 = base + 2 * mb;
-        cc.U = q->d_U ? q->d_U : base + (cfg_.prec >= QSIM_SPLIT_BF16 ? 3 : 2) * mb;
+        cc.U = q->d_U ? q->d_U : base + (is_split(cfg_.prec) ? 3 : 2) * mb;
         active_.push_back(q);
         stats_.admitted += 1;
         if ((int64_t)active_.size() > stats_.peak_active) stats_.peak_active = (int64_t)active_.size();

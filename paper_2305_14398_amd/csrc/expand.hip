@@ -29,8 +29,12 @@ hipError_t launch_expand_step(const DevStep& st, int n, int layout_col, OpFormat
         hipLaunchKernelGGL(expand_step_kernel<FMT_F32>, dim3(grid), dim3(256), 0, stream, st, n, layout_col, out);
     else if (fmt == FMT_BF16)
         hipLaunchKernelGGL(expand_step_kernel<FMT_BF16>, dim3(grid), dim3(256), 0, stream, st, n, layout_col, out);
-    else
+    else if (fmt == FMT_F16)
         hipLaunchKernelGGL(expand_step_kernel<FMT_F16>, dim3(grid), dim3(256), 0, stream, st, n, layout_col, out);
+    else if (fmt == FMT_BF16_G)
+        hipLaunchKernelGGL(expand_step_kernel<FMT_BF16_G>, dim3(grid), dim3(256), 0, stream, st, n, layout_col, out);
+    else
+        hipLaunchKernelGGL(expand_step_kernel<FMT_F16_G>, dim3(grid), dim3(256), 0, stream, st, n, layout_col, out);
     return hipGetLastError();
 }
 

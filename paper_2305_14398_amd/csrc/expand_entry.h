@@ -117,7 +117,7 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_floa
 // Split a float64 value into 16-bit hi + lo with value ~= hi + lo * 2^-shift.
 template <int FMT>
 __device__ __forceinline__ void split16(double v, uint16_t& hi, uint16_t& lo) {
-    if (FMT == FMT_BF16) {
+    if (fmt_elem(FMT) == FMT_BF16) {
         hi = bf16_rne((float)v);
         lo = bf16_rne((float)(v - (double)bf16_to_f32(hi)));
     } else {
@@ -128,14 +128,64 @@ __device__ __forceinline__ void split16(double v, uint16_t& hi, uint16_t& lo) {
     }
 }
 
+// Work item `it` of the three-product split formats from n = 6 on, whose
+// operands are fragment-blocked (32 x 16 blocks of six 1 KiB fragments, see
+// tile_split_gauss.h): item it writes 8 bytes per plane at element 4 it of the
+// block order, i.e. storage row a and storage columns b .. b+3, so consecutive
+// items write consecutive bytes.
+__device__ __forceinline__ void fb_item(uint64_t it, int n, uint32_t& a, uint32_t& b, uint64_t& base) {
+    const uint64_t blk = it >> 7;                 // 128 items per 32 x 16 block
+    const uint32_t w = (uint32_t)(it & 127);
+    const uint32_t fl = w >> 1;                   // fragment lane
+    const uint64_t kblocks = (1ull << n) >> 4;
+    a = (uint32_t)((blk / kblocks) * 32 + (fl & 31));
+    b = (uint32_t)((blk % kblocks) * 16 + (fl >> 5) * 8 + (w & 1) * 4);
+    base = blk * 6 * 512 + fl * 8 + (w & 1) * 4;  // element index in plane 0; planes 512 apart
+}
+
+__device__ __forceinline__ uint2 pack4(const uint16_t* h) {
+    return make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16));
+}
+
+// Four entries in the six-plane three-product format: re, im and the float32
+// sum of the rounded parts (what the products' epilogue splits), each split
+// into hi + lo; element `o` of plane 0, planes `ps` elements apart.
+template <int FMT>
+__device__ __forceinline__ void store_planes6(const double (&vr)[4], const double (&vi)[4], uint16_t* o, uint64_t e,
+                                              uint64_t ps) {
+    uint16_t h[6][4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        split16<FMT>(vr[c], h[0][c], h[1][c]);
+        split16<FMT>(vi[c], h[2][c], h[3][c]);
+        split16<FMT>((double)((float)vr[c] + (float)vi[c]), h[4][c], h[5][c]);
+    }
+#pragma unroll
+    for (int p = 0; p < 6; ++p) *reinterpret_cast<uint2*>(o + p * ps + e) = pack4(h[p]);
+}
+
 // Entries e0 .. e0+3 of the storage order (row-major storage index; logical
 // (r, s) = (a, b) for row-major output and (b, a) for column-major), computed
-// and stored in the output format.
+// and stored in the output format.  Fragment-blocked formats (three-product
+// split, n >= 6) take e0 / 4 as a block-order item instead (fb_item).
 template <int FMT>
 __device__ __forceinline__ void expand_four(const DevStep& st, int n, int layout_col, void* out, uint64_t e0) {
     const uint64_t N = 1ull << n;
     const uint64_t NN = N * N;
     double vr[4], vi[4];
+    if constexpr (fmt_gauss(FMT)) {
+        if (n >= 6) {
+            uint32_t a, b;
+            uint64_t base;
+            fb_item(e0 >> 2, n, a, b, base);
+            if (layout_col)
+                step_entries4<false>(st, b, a, vr, vi);
+            else
+                step_entries4<true>(st, a, b, vr, vi);
+            store_planes6<FMT>(vr, vi, reinterpret_cast<uint16_t*>(out), base, 512);
+            return;
+        }
+    }
     if (n >= 2) {  // the four entries share a storage row
         const uint32_t a = (uint32_t)(e0 >> n);
         const uint32_t b = (uint32_t)(e0 & (N - 1));
@@ -157,6 +207,8 @@ __device__ __forceinline__ void expand_four(const DevStep& st, int n, int layout
         float* o = reinterpret_cast<float*>(out);
         *reinterpret_cast<float4*>(o + e0) = make_float4((float)vr[0], (float)vr[1], (float)vr[2], (float)vr[3]);
         *reinterpret_cast<float4*>(o + NN + e0) = make_float4((float)vi[0], (float)vi[1], (float)vi[2], (float)vi[3]);
+    } else if constexpr (fmt_gauss(FMT)) {
+        store_planes6<FMT>(vr, vi, reinterpret_cast<uint16_t*>(out), e0, NN);
     } else {
         uint16_t rh[4], rl[4], ih[4], il[4];
 #pragma unroll
@@ -165,13 +217,10 @@ __device__ __forceinline__ void expand_four(const DevStep& st, int n, int layout
             split16<FMT>(vi[c], ih[c], il[c]);
         }
         uint16_t* o = reinterpret_cast<uint16_t*>(out);
-        auto pack = [](const uint16_t* h) {
-            return make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16));
-        };
-        *reinterpret_cast<uint2*>(o + e0) = pack(rh);
-        *reinterpret_cast<uint2*>(o + NN + e0) = pack(rl);
-        *reinterpret_cast<uint2*>(o + 2 * NN + e0) = pack(ih);
-        *reinterpret_cast<uint2*>(o + 3 * NN + e0) = pack(il);
+        *reinterpret_cast<uint2*>(o + e0) = pack4(rh);
+        *reinterpret_cast<uint2*>(o + NN + e0) = pack4(rl);
+        *reinterpret_cast<uint2*>(o + 2 * NN + e0) = pack4(ih);
+        *reinterpret_cast<uint2*>(o + 3 * NN + e0) = pack4(il);
     }
 }
 

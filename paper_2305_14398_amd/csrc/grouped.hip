@@ -9,6 +9,7 @@
 #include "expand_entry.h"
 #include "tile_f32.h"
 #include "tile_split.h"
+#include "tile_split_gauss.h"
 
 namespace qsim {
 namespace {
@@ -47,8 +48,12 @@ __global__ __launch_bounds__(256) void grouped_expand_kernel(const ExpandJob* __
                 expand_four<FMT_F32>(J.st, J.n, J.layout_col, J.out, it << 2);
             else if (J.fmt == FMT_BF16)
                 expand_four<FMT_BF16>(J.st, J.n, J.layout_col, J.out, it << 2);
-            else
+            else if (J.fmt == FMT_F16)
                 expand_four<FMT_F16>(J.st, J.n, J.layout_col, J.out, it << 2);
+            else if (J.fmt == FMT_BF16_G)
+                expand_four<FMT_BF16_G>(J.st, J.n, J.layout_col, J.out, it << 2);
+            else
+                expand_four<FMT_F16_G>(J.st, J.n, J.layout_col, J.out, it << 2);
         }
     }
 }
@@ -117,6 +122,39 @@ __global__ __launch_bounds__(256) void grouped_split_kernel(const GemmJob* __res
     }
 }
 
+// Three-product split jobs: 128 x 128 tiles (one wave per SIMD, 96 KiB LDS),
+// 64 x 64 tiles, or the whole product by one workgroup.
+template <int FMT>
+__global__ __launch_bounds__(256) void grouped_split_gauss_kernel(const GemmJob* __restrict__ jobs, int njobs,
+                                                                  int total_tiles) {
+    using T128 = SplitTileG<2, 2, 2, 2, FMT>;
+    using T64 = SplitTileG<2, 2, 1, 1, FMT>;
+    __shared__ u32x4 smem[T128::SMEM_CHUNKS];
+    const int rounds = (total_tiles + gridDim.x - 1) / gridDim.x;
+    for (int r = 0; r < rounds; ++r) {
+        const int t = persistent_tile(r, blockIdx.x, gridDim.x);
+        if (t >= total_tiles) continue;
+        const int j = find_job(jobs, njobs, t, &GemmJob::tile_begin);
+        const GemmJob& J = jobs[j];
+        const int local = t - J.tile_begin;
+        const int N = 1 << J.n;
+        const uint16_t* X = static_cast<const uint16_t*>(J.X);
+        const uint16_t* Y = static_cast<const uint16_t*>(J.Y);
+        uint16_t* Ds = static_cast<uint16_t*>(J.D0);
+        float* Df = static_cast<float*>(J.D1);
+        int tm, tn;
+        if (J.cfg == 128) {
+            grouped_tile_order(local, N / 128, N / 128, tm, tn);
+            T128::run(J.n, X, Y, Ds, Df, tm, tn, smem);
+        } else if (J.cfg != 0) {
+            grouped_tile_order(local, N / 64, N / 64, tm, tn);
+            T64::run(J.n, X, Y, Ds, Df, tm, tn, smem);
+        } else {
+            split_small_product_gauss<FMT>(J.n, X, Y, Ds, Df, threadIdx.x, 256);
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_grouped_expand(const ExpandJob* jobs, int njobs, int total_blocks, int grid, hipStream_t stream) {
@@ -141,8 +179,16 @@ hipError_t launch_grouped_gemm(int prec, const GemmJob* jobs, int njobs, int tot
             hipLaunchKernelGGL(grouped_split_kernel<FMT_BF16>, dim3(grid), dim3(256), 0, stream, jobs, njobs,
                                total_tiles);
             break;
-        default:
+        case QSIM_SPLIT_FP16:
             hipLaunchKernelGGL(grouped_split_kernel<FMT_F16>, dim3(grid), dim3(256), 0, stream, jobs, njobs,
+                               total_tiles);
+            break;
+        case QSIM_SPLIT_BF16_3M:
+            hipLaunchKernelGGL(grouped_split_gauss_kernel<FMT_BF16>, dim3(grid), dim3(256), 0, stream, jobs, njobs,
+                               total_tiles);
+            break;
+        default:
+            hipLaunchKernelGGL(grouped_split_gauss_kernel<FMT_F16>, dim3(grid), dim3(256), 0, stream, jobs, njobs,
                                total_tiles);
             break;
     }

@@ -34,6 +34,8 @@ qsim_status make_step(int n, const qsim_gate* gates, int count, DevStep& st);
 // Step formation rule (see qsim_pack_steps).
 void pack(const qsim_gate* gates, int n_gates, std::vector<int32_t>& off);
 inline size_t mat_bytes(int n) { return (size_t)8 << (2 * n); }
+// Bytes of one chain operand (step operator or running product) in the format of `prec`.
+inline size_t op_bytes(int n, int prec) { return fmt_bytes(format_of(prec), n); }
 
 // Makes `dev` current for the lifetime of the guard and restores the caller's device.
 struct DeviceGuard {
@@ -109,18 +111,20 @@ hipError_t timed(Profiler* prof, int kind, hipStream_t s, F&& launch) {
 }
 
 
-// MFMA tile edge per qubit count, per arithmetic family (0 float32, 1 split
-// bf16, 2 split fp16); filled by the autotuner or by the default rule (128
-// for n >= 7, 64 for n = 6).  Split fp16 always uses 64: its 128-wide tile
-// needs every register and would spill inside the grouped kernel.
+// MFMA tile edge per qubit count, per precision; filled by the autotuner or by
+// the default rule (128 for n >= 7, 64 for n = 6).  The four-product split
+// fp16 form always uses 64: its 128-wide tile needs every register and would
+// spill inside the grouped kernel.
+constexpr int kPrecisions = QSIM_SPLIT_FP16_3M + 1;
 struct TuneTable {
-    static int family(int prec) { return prec == QSIM_SPLIT_FP16 ? 2 : prec == QSIM_SPLIT_BF16 ? 1 : 0; }
-    int tile[3][QSIM_MAX_QUBITS + 1];
-    bool tuned[3];
+    static int family(int prec) { return prec; }
+    int tile[kPrecisions][QSIM_MAX_QUBITS + 1];
+    bool tuned[kPrecisions];
     TuneTable() {
-        for (int f = 0; f < 3; ++f) {
+        for (int f = 0; f < kPrecisions; ++f) {
             tuned[f] = false;
-            for (int n = 0; n <= QSIM_MAX_QUBITS; ++n) tile[f][n] = n >= 7 && f != 2 ? 128 : (n >= 6 ? 64 : 0);
+            for (int n = 0; n <= QSIM_MAX_QUBITS; ++n)
+                tile[f][n] = n >= 7 && f != QSIM_SPLIT_FP16 ? 128 : (n >= 6 ? 64 : 0);
         }
     }
     // Never wider than the matrix: n = 6 always uses 64, n <= 5 the whole-product path.

@@ -54,7 +54,7 @@ def serve(ctx, circuits, prec, mode=B.QSIM_SERVE_CONTINUOUS, max_active=64, aren
     return out, stats
 
 
-@pytest.mark.parametrize("prec", [B.QSIM_FP32_4M, B.QSIM_SPLIT_BF16])
+@pytest.mark.parametrize("prec", [B.QSIM_FP32_4M, B.QSIM_SPLIT_BF16, B.QSIM_SPLIT_BF16_3M])
 def test_served_results_match_oracle(ctx, prec):
     circuits = W.batch_mixed(30, seed=21, n_lo=2, n_hi=10, d_lo=2, d_hi=12)
     out, stats = serve(ctx, circuits, prec, want_U=True)
@@ -66,6 +66,9 @@ def test_served_results_match_oracle(ctx, prec):
         if prec == B.QSIM_FP32_4M:
             assert np.abs(psi - ref).max() <= 1e-5
             assert 0 <= res["drift_max"] <= 1e-5
+        else:  # the derived split-chain bound on the state (tests/gpu_util.py)
+            fmt, gauss = G.split_kind(prec)
+            assert G.max_col_err(psi, ref) <= G.split_chain_bound(fmt, G.chain_products(c.n, c.gates), gauss)
         assert res["norm2"] == pytest.approx(float(np.sum(np.abs(psi) ** 2)), rel=1e-12)
         assert res["t_submit_ns"] <= res["t_start_ns"] <= res["t_done_ns"]
         assert res["n_steps"] == len(B.qsim_pack_steps(c.n, c.gates)) - 1
@@ -74,7 +77,7 @@ def test_served_results_match_oracle(ctx, prec):
 def test_alone_and_in_the_mix_are_identical(ctx):
     probe = W.random_layers(9, 10, np.random.default_rng(4))
     mix = W.batch_mixed(40, seed=5, n_lo=3, n_hi=10, d_lo=5, d_hi=20)
-    for prec in (B.QSIM_FP32_4M, B.QSIM_SPLIT_BF16):
+    for prec in (B.QSIM_FP32_4M, B.QSIM_SPLIT_BF16, B.QSIM_SPLIT_BF16_3M):
         alone, _ = serve(ctx, [probe], prec, want_U=True)
         mixed, stats = serve(ctx, mix[:20] + [probe] + mix[20:], prec, want_U=True, stagger=0.0005)
         assert stats["peak_active"] > 1
@@ -232,6 +235,7 @@ def test_full_served_config_sampled_against_oracle(ctx):
         c = circuits[i]
         ref = fsv.final_state(c.n, W.gate_tuples(c))
         assert metrics.fidelity(out[i][0], ref) >= 1 - 1e-6, (i, c.family, c.n)
+        assert G.max_col_err(out[i][0], ref) <= G.split_chain_bound("bf16", G.chain_products(c.n, c.gates))
 
 
 def test_served_full_drift_equals_the_synchronous_check(ctx):

@@ -72,9 +72,14 @@ def test_workspace_bytes():
         assert B.qsim_chain_workspace_bytes(n, B.QSIM_FP32_4M) == 2 * mb
         assert B.qsim_chain_workspace_bytes(n, B.QSIM_FP32_3M) == 2 * mb
         assert B.qsim_chain_workspace_bytes(n, B.QSIM_SPLIT_BF16) == 3 * mb
+        assert B.qsim_chain_workspace_bytes(n, B.QSIM_SPLIT_FP16) == 3 * mb
+        # three-product split operands carry six 16-bit planes (12 N^2 bytes)
+        assert B.qsim_chain_workspace_bytes(n, B.QSIM_SPLIT_BF16_3M) == 3 * (12 << (2 * n))
+        assert B.qsim_chain_workspace_bytes(n, B.QSIM_SPLIT_FP16_3M) == 3 * (12 << (2 * n))
     assert B.qsim_chain_workspace_bytes(0, 0) == 0
     assert B.qsim_chain_workspace_bytes(17, 0) == 0
     assert B.qsim_chain_workspace_bytes(5, 9) == 0
+    assert B.qsim_chain_workspace_bytes(5, 6) == 0
 
 
 def _expect(status, fn, *args, match=None):
@@ -210,6 +215,7 @@ def test_batch_validation_without_device():
     need = B.qsim_batch_workspace_bytes(circuits, B.QSIM_FP32_4M)
     assert need == 2 * (8 << 10) + 2 * (8 << 12)
     assert B.qsim_batch_workspace_bytes(circuits, B.QSIM_SPLIT_BF16) == 3 * (8 << 10) + 3 * (8 << 12)
+    assert B.qsim_batch_workspace_bytes(circuits, B.QSIM_SPLIT_FP16_3M) == 3 * (12 << 10) + 3 * (12 << 12)
     outs = [FAKE * 64, FAKE * 65]
     with pytest.raises(B.QsimError, match="workspace"):
         B.BatchPlan(None, circuits, outs, B.QSIM_FP32_4M, FAKE * 4, need - 256)
