@@ -502,7 +502,7 @@ def main() -> int:
     ap.add_argument("--batched", type=int, default=512, help="circuits in the batched workload (0: skip)")
     ap.add_argument("--served", type=int, default=200, help="requests in the served trace (0: skip)")
     ap.add_argument("--served-rate", type=float, default=200.0)
-    ap.add_argument("--served-prec", default="split_bf16", choices=sorted(PEAK_TFLOPS))
+    ap.add_argument("--served-prec", default="split_bf16_3m", choices=sorted(PEAK_TFLOPS))
     ap.add_argument("--served-drift", default="full", choices=sorted(DRIFT_TEXT),
                     help="drift check per served request: the full ||U^H U - I|| or the two-pass probe")
     ap.add_argument("--fsv", type=int, default=30, help="qubits of the full-state-vector workload (0: skip)")
@@ -627,7 +627,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "fp32" if args.prec.startswith("fp32") else "bf16" if args.prec == "split_bf16" else "fp16",
+        "dtype": "fp32" if args.prec.startswith("fp32") else "bf16" if args.prec.startswith("split_bf16") else "fp16",
         "data": "synthetic",
         "config": {
             "workload": f"qft({n}) + 3 seeded balanced deutsch_jozsa({n}); complex64 chains ({args.prec}); "
@@ -644,7 +644,7 @@ def main() -> int:
                       for k, (c, t) in stats.items()},
         "roofline": {
             "bound": "mfma",
-            "kernel": f"{'cgemm_f32_kernel' if args.prec.startswith('fp32') else 'cgemm_split_kernel'} "
+            "kernel": f"{'cgemm_f32_kernel' if args.prec.startswith('fp32') else 'cgemm_split_gauss_kernel' if args.prec.endswith('_3m') else 'cgemm_split_kernel'} "
                       f"({args.prec}, complex product of stage 5, 2048^3)",
             "achieved": round(achieved, 2),
             "peak": round(peak, 1),

@@ -40,10 +40,17 @@
 // or 16-byte (float32) vector.
 //
 // Tiling: 256 threads, 2 x 2 waves, each wave 2 x 2 blocks of 32 x 32 (a
-// 128 x 128 tile; 192 accumulator registers, one wave per SIMD), K-tiles of 16
-// double buffered in LDS (6 planes x 2 operands x 128 rows x 32 B x 2 stages =
-// 96 KiB), stored in the same fragment order as in HBM, so every LDS write and
-// fragment read is 1 KiB contiguous across the wave (no bank conflicts).
+// 128 x 128 tile; 192 accumulator registers, one wave per SIMD).  K-steps of 16
+// go through a ring of three LDS stages (6 planes x 2 operands x 128 rows x
+// 32 B = 48 KiB each, 144 KiB), stored in the same fragment order as in HBM,
+// so every LDS write and fragment read is 1 KiB contiguous across the wave (no
+// bank conflicts).  With one wave per SIMD nothing else hides latency, so the
+// tile pipelines it: a stage's global loads are issued two k-steps before it
+// is stored to LDS (two register sets), a stage is stored two k-steps before
+// it is used (the ring), and each component's fragments are read from LDS
+// while the previous component's 12 MFMAs run, across k-steps too (the next
+// step's stage was made visible a barrier earlier).  One barrier per k-step
+// guards the reuse of the oldest stage.
 #pragma once
 
 #include "tile_split.h"
@@ -129,7 +136,7 @@ struct SplitTileG {
     static constexpr int FRAG = 64;                                   // 16-byte chunks per fragment (1 KiB)
     static constexpr int XCH = (TM / 32) * 6 * FRAG;                  // chunks per X stage
     static constexpr int YCH = (TN / 32) * 6 * FRAG;
-    static constexpr int SMEM_CHUNKS = 2 * (XCH + YCH);
+    static constexpr int SMEM_CHUNKS = 3 * (XCH + YCH);
 
     __device__ __forceinline__ static void run(int n, const uint16_t* __restrict__ X, const uint16_t* __restrict__ Y,
                                                uint16_t* __restrict__ Dsplit, float* __restrict__ Df32, int tm,
@@ -138,8 +145,8 @@ struct SplitTileG {
         static_assert(XV * NT == XCH && YV * NT == YCH, "tile/thread mismatch");
         constexpr bool F16 = (FMT == FMT_F16);
 
-        u32x4* Xs = smem;                // [2][XCH]
-        u32x4* Ys = smem + 2 * XCH;      // [2][YCH]
+        u32x4* Xs = smem;                // [3][XCH]
+        u32x4* Ys = smem + 3 * XCH;      // [3][YCH]
 
         const int N = 1 << n;
         const size_t NN = (size_t)N * N;
@@ -169,62 +176,135 @@ struct SplitTileG {
 
         // A stage is TM / 32 runs of 6 fragments (6 KiB), one per row-block,
         // copied in order: chunk f of the stage is chunk f % 384 of run f / 384.
-        u32x4 rx[XV], ry[YV];
-        auto gload = [&](int kb) {
+        // Loads go through buffer resources based at the tile's first row-block
+        // (its runs span TM / 32 x N x 384 bytes), so a lane's offsets are fixed
+        // for the tile and each k-step only moves the scalar offset.
+        constexpr int RUN = 6 * FRAG;
+        const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<u32x4*>(Xc + (size_t)(i0 / 32) * KB * RUN), (short)0, (TM / 32) * KB * RUN * 16, 0x00020000);
+        const __amdgpu_buffer_rsrc_t yr = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<u32x4*>(Yc + (size_t)(j0 / 32) * KB * RUN), (short)0, (TN / 32) * KB * RUN * 16, 0x00020000);
+        int xo[XV], yo[YV];
 #pragma unroll
-            for (int u = 0; u < XV; ++u) {
-                const int f = tid + NT * u;
-                rx[u] = Xc[chunk0(i0 / 32 + f / (6 * FRAG), kb) + f % (6 * FRAG)];
+        for (int u = 0; u < XV; ++u) {
+            const int f = tid + NT * u;
+            xo[u] = ((f / RUN) * KB * RUN + f % RUN) * 16;
+        }
+#pragma unroll
+        for (int u = 0; u < YV; ++u) {
+            const int f = tid + NT * u;
+            yo[u] = ((f / RUN) * KB * RUN + f % RUN) * 16;
+        }
+        // part q of 3 of a stage's loads / LDS stores (one part per component phase)
+        auto gload = [&](u32x4 (&rx)[XV], u32x4 (&ry)[YV], int kb, int q) {
+            const int so = kb * RUN * 16;
+#pragma unroll
+            for (int u = q * XV / 3; u < (q + 1) * XV / 3; ++u)
+                rx[u] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(xr, xo[u], so, 0));
+#pragma unroll
+            for (int u = q * YV / 3; u < (q + 1) * YV / 3; ++u)
+                ry[u] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(yr, yo[u], so, 0));
+        };
+        auto lstore = [&](const u32x4 (&rx)[XV], const u32x4 (&ry)[YV], int stage, int q) {
+            u32x4* xs = Xs + (stage % 3) * XCH;
+            u32x4* ys = Ys + (stage % 3) * YCH;
+#pragma unroll
+            for (int u = q * XV / 3; u < (q + 1) * XV / 3; ++u) xs[tid + NT * u] = rx[u];
+#pragma unroll
+            for (int u = q * YV / 3; u < (q + 1) * YV / 3; ++u) ys[tid + NT * u] = ry[u];
+        };
+        // Fragments of component c (planes 2c, 2c + 1) of k-step t.
+        struct Frags {
+            u32x4 xh[BMB], xl[BMB], yh[BNB], yl[BNB];
+        };
+        auto fread = [&](Frags& F, int t, int c) {
+            const u32x4* xs = Xs + (t % 3) * XCH;
+            const u32x4* ys = Ys + (t % 3) * YCH;
+#pragma unroll
+            for (int x = 0; x < BMB; ++x) {
+                const u32x4* fr = xs + ((wm * BMB + x) * 6 + 2 * c) * FRAG + lane;
+                F.xh[x] = fr[0];
+                F.xl[x] = fr[FRAG];
             }
 #pragma unroll
-            for (int u = 0; u < YV; ++u) {
-                const int f = tid + NT * u;
-                ry[u] = Yc[chunk0(j0 / 32 + f / (6 * FRAG), kb) + f % (6 * FRAG)];
+            for (int y = 0; y < BNB; ++y) {
+                const u32x4* fr = ys + ((wn * BNB + y) * 6 + 2 * c) * FRAG + lane;
+                F.yh[y] = fr[0];
+                F.yl[y] = fr[FRAG];
             }
         };
-        auto lstore = [&](int s) {
+        // The three passes go round the BMB x BNB accumulators in turn, so
+        // consecutive MFMAs never feed one another.
+        auto fmma = [&](const Frags& F, int c) {
+            u32x4 xhh[BMB];
 #pragma unroll
-            for (int u = 0; u < XV; ++u) Xs[s * XCH + tid + NT * u] = rx[u];
+            for (int x = 0; x < BMB; ++x) xhh[x] = F16 ? f16x8_times_4096(F.xh[x]) : F.xh[x];
 #pragma unroll
-            for (int u = 0; u < YV; ++u) Ys[s * YCH + tid + NT * u] = ry[u];
+            for (int x = 0; x < BMB; ++x)
+#pragma unroll
+                for (int y = 0; y < BNB; ++y) acc[x][y][c] = mfma16<FMT>(F.yh[y], xhh[x], acc[x][y][c]);
+#pragma unroll
+            for (int x = 0; x < BMB; ++x)
+#pragma unroll
+                for (int y = 0; y < BNB; ++y) acc[x][y][c] = mfma16<FMT>(F.yl[y], F.xh[x], acc[x][y][c]);
+#pragma unroll
+            for (int x = 0; x < BMB; ++x)
+#pragma unroll
+                for (int y = 0; y < BNB; ++y) acc[x][y][c] = mfma16<FMT>(F.yh[y], F.xl[x], acc[x][y][c]);
         };
-
-        gload(0);
-        lstore(0);
-        __syncthreads();
-
-        for (int kt = 0; kt < KB; ++kt) {
-            const int cur = kt & 1;
-            if (kt + 1 < KB) gload(kt + 1);
+        // One component phase: its MFMAs with the next fragments' LDS reads,
+        // a third of the next-but-two stage's global loads and a third of the
+        // next-but-one stage's LDS stores interleaved between them.
+        constexpr int NM = 3 * BMB * BNB, NDR = 2 * (BMB + BNB), NG = (XV + YV) / 3;
+        auto interleave = [&]() {
+            if constexpr (NDR > NM) __builtin_amdgcn_sched_group_barrier(0x100, NDR - NM, 0);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {  // component r, i, s: planes 2c (hi), 2c + 1 (lo)
-                u32x4 xh[BMB], xl[BMB], yh[BNB], yl[BNB];
-#pragma unroll
-                for (int x = 0; x < BMB; ++x) {
-                    const u32x4* fr = Xs + cur * XCH + ((wm * BMB + x) * 6 + 2 * c) * FRAG + lane;
-                    xh[x] = fr[0];
-                    xl[x] = fr[FRAG];
-                }
-#pragma unroll
-                for (int y = 0; y < BNB; ++y) {
-                    const u32x4* fr = Ys + cur * YCH + ((wn * BNB + y) * 6 + 2 * c) * FRAG + lane;
-                    yh[y] = fr[0];
-                    yl[y] = fr[FRAG];
-                }
-#pragma unroll
-                for (int x = 0; x < BMB; ++x) {
-                    const u32x4 xhh = F16 ? f16x8_times_4096(xh[x]) : xh[x];
-#pragma unroll
-                    for (int y = 0; y < BNB; ++y) {
-                        floatx16& a = acc[x][y][c];
-                        a = mfma16<FMT>(yh[y], xhh, a);
-                        a = mfma16<FMT>(yl[y], xh[x], a);
-                        a = mfma16<FMT>(yh[y], xl[x], a);
-                    }
-                }
+            for (int i = 0; i < NM; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);      // MFMA
+                if (i < NDR) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
+                if (i < NG) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);   // VMEM read
+                if (i < NG) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);   // DS write
             }
-            if (kt + 1 < KB) lstore(cur ^ 1);
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        // k-step t: F holds (t, r) on entry; on exit G holds (t + 1, r).
+        // R0 holds stage t + 2 (stored to LDS during this step); stage t + 3 is loaded into R1.
+        // No branches, so each phase is one scheduling region: past the last
+        // stage the loads repeat stage KB - 1 (in range) and the stores and the
+        // reads of step KB touch ring slots that hold no live stage any more.
+        auto step = [&](int t, Frags& F, Frags& G, u32x4 (&R0x)[XV], u32x4 (&R0y)[YV], u32x4 (&R1x)[XV],
+                        u32x4 (&R1y)[YV]) {
+            const int ld = t + 3 < KB ? t + 3 : KB - 1;
+            fread(G, t, 1);
+            gload(R1x, R1y, ld, 0);
+            lstore(R0x, R0y, t + 2, 0);
+            fmma(F, 0);
+            interleave();
+            fread(F, t, 2);
+            gload(R1x, R1y, ld, 1);
+            lstore(R0x, R0y, t + 2, 1);
+            fmma(G, 1);
+            interleave();
+            fread(G, t + 1, 0);
+            gload(R1x, R1y, ld, 2);
+            lstore(R0x, R0y, t + 2, 2);
+            fmma(F, 2);
+            interleave();
             __syncthreads();
+        };
+
+        u32x4 Ax[XV], Ay[YV], Bx[XV], By[YV];
+        Frags F, G;
+        for (int q = 0; q < 3; ++q) gload(Ax, Ay, 0, q);
+        for (int q = 0; q < 3; ++q) lstore(Ax, Ay, 0, q);
+        for (int q = 0; q < 3; ++q) gload(Bx, By, 1, q);
+        for (int q = 0; q < 3; ++q) lstore(Bx, By, 1, q);
+        for (int q = 0; q < 3; ++q) gload(Ax, Ay, 2, q);  // stored during k-step 0
+        __syncthreads();
+        fread(F, 0, 0);
+        for (int t = 0; t < KB; t += 2) {  // KB = N / 16 is even (n >= 6)
+            step(t, F, G, Ax, Ay, Bx, By);
+            step(t + 1, G, F, Bx, By, Ax, Ay);
         }
 
         // Lane l of block (x, y) holds row i = l % 32 and columns 8 g + 4 (l / 32) + q in register 4 g + q.
