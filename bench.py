@@ -32,6 +32,14 @@ PEAK_TFLOPS = {"fp32_4m": 157.3, "fp32_3m": 157.3, "split_bf16": 2500.0, "split_
                "split_bf16_3m": 2500.0, "split_fp16_3m": 2500.0}
 ISSUED_PER_COUNTED = {"fp32_4m": 1.0, "fp32_3m": 6.0 / 8.0, "split_bf16": 24.0 / 8.0, "split_fp16": 24.0 / 8.0,
                       "split_bf16_3m": 18.0 / 8.0, "split_fp16_3m": 18.0 / 8.0}
+# source of each precision's product tile (a committed counter profile counts only while its hash matches)
+TILE_SOURCE = {"fp32_4m": "paper_2305_14398_amd/csrc/tile_f32.h", "fp32_3m": "paper_2305_14398_amd/csrc/tile_f32.h",
+               "split_bf16": "paper_2305_14398_amd/csrc/tile_split.h",
+               "split_fp16": "paper_2305_14398_amd/csrc/tile_split.h",
+               "split_bf16_3m": "paper_2305_14398_amd/csrc/tile_split_gauss.h",
+               "split_fp16_3m": "paper_2305_14398_amd/csrc/tile_split_gauss.h"}
+OPERAND_BYTES_PER_ENTRY = {"fp32_4m": 8, "fp32_3m": 8, "split_bf16": 8, "split_fp16": 8, "split_bf16_3m": 12,
+                           "split_fp16_3m": 12}
 # probe kind measuring the dtype each precision issues
 PROBE_OF = {"fp32_4m": "mfma_f32", "fp32_3m": "mfma_f32", "split_bf16": "mfma_bf16", "split_fp16": "mfma_f16",
             "split_bf16_3m": "mfma_bf16", "split_fp16_3m": "mfma_f16"}
@@ -386,8 +394,29 @@ def measure_peaks(B, ctx, torch, copy_mib: int):
     out["hbm_copy"] = {"gb_per_s": round(gbs, 1), "bytes": nbytes, "vendor_gb_per_s": HBM_PEAK_GBS,
                        "frac_of_vendor": round(gbs / HBM_PEAK_GBS, 4),
                        "note": "read + write bytes of a 16-byte-vector device copy"}
+    # the vendor GEMM library on random operands, as a reference for what a tuned dense product reaches here
+    lib = {}
+    for dtype, name in ((torch.bfloat16, "bf16"), (torch.float16, "fp16"), (torch.float32, "fp32")):
+        for m in ((4096, 8192) if name != "fp32" else (8192,)):
+            a = torch.randn(m, m, device="cuda:0").to(dtype)
+            b = torch.randn(m, m, device="cuda:0").to(dtype)
+            for _ in range(2):
+                a @ b
+            torch.cuda.synchronize()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 10 if name != "fp32" else 3
+            ev0.record()
+            for _ in range(reps):
+                a @ b
+            ev1.record()
+            torch.cuda.synchronize()
+            lib[f"{name}_{m}"] = round(2.0 * m ** 3 / (ev0.elapsed_time(ev1) / reps * 1e-3) / 1e12, 1)
+            del a, b
+    torch.cuda.empty_cache()
+    out["library_gemm_tflops"] = lib
     out["method"] = ("MFMA: 2048 workgroups x 256 threads, four independent accumulator chains per wave, "
-                     "flops = 2 x M x N x K per instruction; random operands toggle their mantissa bits")
+                     "flops = 2 x M x N x K per instruction; random operands toggle their mantissa bits. "
+                     "library_gemm_tflops: torch.matmul (hipBLASLt) on random m x m operands, events over the calls")
     return out
 
 
@@ -509,9 +538,9 @@ def main() -> int:
     ap.add_argument("--sweep-qubits", default="12,13", help="qubit counts of the precision sweep ('' to skip)")
     ap.add_argument("--sweep-seeds", default="0,1,2,3,4", help="seeds of the precision sweep's random circuits")
     ap.add_argument("--sweep-precisions", default="fp32_4m,fp32_3m,split_bf16,split_fp16,split_bf16_3m,split_fp16_3m")
-    ap.add_argument("--served-sweep", default="4,8,12",
+    ap.add_argument("--served-sweep", default="8,12,16",
                     help="comma-separated Poisson rates for an offered-rate sweep ('' to skip)")
-    ap.add_argument("--served-sweep-seconds", type=float, default=5.0)
+    ap.add_argument("--served-sweep-seconds", type=float, default=10.0)
     ap.add_argument("--served-sweep-policies", default="aged,fifo", help=f"of {sorted(SWEEP_POLICIES)}")
     ap.add_argument("--served-slo-ms", type=float, default=2500.0)
     ap.add_argument("--peaks", type=int, default=1, help="measure on-box MFMA and HBM peaks (0: skip)")
@@ -652,10 +681,10 @@ def main() -> int:
                           f"{ISSUED_PER_COUNTED[args.prec] * 8:g} N^3 issued",
             "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4),
-            "traffic": counted_traffic(f"cgemm_{args.prec}_qft11_dj11.md", "paper_2305_14398_amd/csrc/tile_f32.h")
-            if (args.prec.startswith("fp32") and n == 11) else None,
+            "traffic": counted_traffic(f"cgemm_{args.prec}_qft{n}_dj{n}.md", TILE_SOURCE[args.prec]),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE, copy-calibrated)",
-            "algorithmic_bytes_per_launch": 3 * 8 * N * N,
+            # operands in and result out, each in the precision's format (the last product writes float32)
+            "algorithmic_bytes_per_launch": 3 * OPERAND_BYTES_PER_ENTRY[args.prec] * N * N,
         },
         "expand_roofline": {
             "bound": "hbm",

@@ -553,10 +553,10 @@ qsim_status qsim_fsv_sample(qsim_ctx* ctx, int n_qubits, const void* d_psi, cons
  * random_operands != 0: operands with pseudo-random mantissas (toggling bits,
  * as in dense products; the chip may lower its clock); 0: constant operands.
  * Writes one float per workgroup into the context's scratch; synchronous.
- * qsim_probe_copy: a streaming device copy of `bytes` (multiple of 16) from
- * d_src to d_dst (non-overlapping, 256-byte aligned), 16-byte loads and
- * stores; *gbs_out = 2 * bytes / time (read + write), mean of 10 copies after
- * one warm-up; synchronous. */
+ * qsim_probe_copy: a streaming device copy of `bytes` (a multiple of 64 MiB)
+ * from d_src to d_dst (non-overlapping, 256-byte aligned), 16-byte loads and
+ * stores, four in flight per thread; *gbs_out = 2 * bytes / time (read +
+ * write), mean of 10 copies after one warm-up; synchronous. */
 qsim_status qsim_probe_mfma(qsim_ctx* ctx, int kind, int random_operands, double* tflops_out);
 qsim_status qsim_probe_copy(qsim_ctx* ctx, const void* d_src, void* d_dst, size_t bytes, double* gbs_out);
 

@@ -99,11 +99,20 @@ __global__ __launch_bounds__(kProbeThreads) void mfma_probe_kernel(int iters, in
     if (threadIdx.x == 0) sink[blockIdx.x] = total;  // keeps the work live
 }
 
-// Streaming copy, 16 bytes per load and store, grid-stride.
+// Streaming copy, 16 bytes per load and store, grid-stride; each thread has
+// up to four loads in flight before it stores.
 __global__ __launch_bounds__(256) void copy_probe_kernel(const floatx4* __restrict__ src, floatx4* __restrict__ dst,
                                                          size_t n16) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += 4 * stride) {
+        floatx4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (i + u * stride < n16) v[u] = __builtin_nontemporal_load(src + i + u * stride);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (i + u * stride < n16) __builtin_nontemporal_store(v[u], dst + i + u * stride);
+    }
 }
 
 // flops of one MFMA of each probe kind
@@ -168,7 +177,8 @@ qsim_status qsim_probe_mfma(qsim_ctx* ctx, int kind, int random_operands, double
 
 qsim_status qsim_probe_copy(qsim_ctx* ctx, const void* d_src, void* d_dst, size_t bytes, double* gbs_out) {
     if (!d_src || !d_dst || !aligned(d_src) || !aligned(d_dst)) return fail(QSIM_E_INVALID, "NULL or unaligned buffer");
-    if (bytes < 256 || (bytes & 15u)) return fail(QSIM_E_RANGE, "bytes must be a multiple of 16, at least 256");
+    if (bytes < (64u << 20) || (bytes & ((64u << 20) - 1)))
+        return fail(QSIM_E_RANGE, "bytes must be a multiple of 64 MiB");
     if (gbs_out == nullptr) return fail(QSIM_E_INVALID, "gbs_out is NULL");
     const char* a = static_cast<const char*>(d_src);
     const char* b = static_cast<const char*>(d_dst);
