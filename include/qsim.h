@@ -343,12 +343,29 @@ qsim_status qsim_unitary_chain_batched(qsim_ctx* ctx, const qsim_circuit_desc* c
  * float32, split bf16 or split fp16; split fp16 always uses 64).  ms_out
  * (nullable, 2 doubles per n from 7): milliseconds per product for tile 64 and
  * tile 128 (-1 if not applicable).
- * Synchronises; allocates scratch for the timing runs. */
+ * The timed operands are seeded pseudo-random values (not zeros: the chip's
+ * clock follows the switching power, so all-zero operands would time faster
+ * than any chain).  The 64 / 128 timings stay in the context (qsim_tune_ms,
+ * qsim_tune_save).  Synchronises; allocates scratch for the timing runs. */
 qsim_status qsim_autotune(qsim_ctx* ctx, int prec, int n_lo, int n_hi, double* ms_out);
 /* Current tile edge per qubit count (17 ints, index n; 0 = whole-product path). */
 qsim_status qsim_tune_get(qsim_ctx* ctx, int prec, int* tiles_out);
 /* Override the tile edge (64 or 128; split fp16: 64 only) for n in 7..16. */
 qsim_status qsim_tune_set(qsim_ctx* ctx, int prec, int n_qubits, int tile);
+/* Milliseconds per product the autotuner measured for (prec, n): ms_out[2n]
+ * with 64-wide tiles, ms_out[2n + 1] with 128-wide ones, -1 where not measured
+ * (34 doubles, n = 0..16). */
+qsim_status qsim_tune_ms(qsim_ctx* ctx, int prec, double* ms_out);
+/* Tile cache: qsim_tune_save writes the context's tile table, its tuned flags
+ * and the measured timings of every precision to a small JSON file, with the
+ * device (name, architecture, compute units) and the library build
+ * (qsim_build_id: a hash of the sources it was built from).  qsim_tune_load
+ * reads such a file into the context; QSIM_E_INVALID (table unchanged) if it
+ * cannot be read, is malformed, holds an invalid tile, or was written by
+ * another build or for another device, so a stale choice is never applied. */
+qsim_status qsim_tune_save(qsim_ctx* ctx, const char* path);
+qsim_status qsim_tune_load(qsim_ctx* ctx, const char* path);
+const char* qsim_build_id(void);
 
 /* ---- Serving: continuous batching of submitted circuits ----
  * qsim_serve_start runs an engine thread for the context with its own HIP
@@ -507,7 +524,10 @@ typedef struct qsim_fsv_pass_info {
  * both are diagonal; within that rule a pass may take gates from further on in
  * the circuit, so passes hold ranges of an execution order rather than of the
  * gate list.  order (NULL, or n_gates entries) receives that order: gate
- * indices, pass by pass. */
+ * indices, pass by pass, and within a pass in the order its launch applies
+ * them (operations on disjoint qubits, and diagonal ones, commute, so the
+ * pass is reordered to need fewer register-layout changes; a run of diagonal
+ * operations is applied as one multiplied-out table, in any order equal). */
 qsim_status qsim_fsv_schedule(int n_qubits, const qsim_gate* gates, int n_gates, qsim_fsv_pass_info* passes,
                               int capacity, int* n_passes, int32_t* order);
 /* Validates the gates, schedules them and uploads the operation table to the

@@ -170,6 +170,10 @@ def lib() -> ctypes.CDLL:
         "qsim_serve_get_stats": (i32, [vp, ctypes.POINTER(qsim_serve_stats)]),
         "qsim_tune_get": (i32, [vp, i32, ctypes.POINTER(i32)]),
         "qsim_tune_set": (i32, [vp, i32, i32, i32]),
+        "qsim_tune_ms": (i32, [vp, i32, ctypes.POINTER(dbl)]),
+        "qsim_tune_save": (i32, [vp, ctypes.c_char_p]),
+        "qsim_tune_load": (i32, [vp, ctypes.c_char_p]),
+        "qsim_build_id": (ctypes.c_char_p, []),
         "qsim_profile_read": (i32, [vp, ctypes.POINTER(qsim_kernel_stats)]),
     }
     for name, (res, args) in sigs.items():
@@ -468,6 +472,25 @@ def qsim_tune_get(ctx, prec: int) -> list:
 
 def qsim_tune_set(ctx, prec: int, n_qubits: int, tile: int) -> None:
     _check(lib().qsim_tune_set(_h(ctx), prec, n_qubits, tile), "qsim_tune_set")
+
+
+def qsim_tune_ms(ctx, prec: int) -> dict:
+    """{n: (ms per product with 64-wide tiles, with 128-wide tiles)} for the qubit counts the autotuner timed."""
+    out = (ctypes.c_double * 34)()
+    _check(lib().qsim_tune_ms(_h(ctx), prec, out), "qsim_tune_ms")
+    return {n: (out[2 * n], out[2 * n + 1]) for n in range(17) if out[2 * n] >= 0 or out[2 * n + 1] >= 0}
+
+
+def qsim_tune_save(ctx, path: str) -> None:
+    _check(lib().qsim_tune_save(_h(ctx), path.encode()), "qsim_tune_save")
+
+
+def qsim_tune_load(ctx, path: str) -> None:
+    _check(lib().qsim_tune_load(_h(ctx), path.encode()), "qsim_tune_load")
+
+
+def qsim_build_id() -> str:
+    return lib().qsim_build_id().decode()
 
 
 def qsim_unitarity_drift_async(ctx, n_qubits: int, d_U, d_out, stream=None) -> None:

@@ -31,9 +31,22 @@ FLAGS = [
 ]
 
 
-def _compile(src: str):
+def build_id() -> str:
+    """Hash of the kernel and host sources and the public header: a tile cache records it and is only loaded
+    by a library built from the same sources."""
+    import hashlib
+    h = hashlib.sha256()
+    for path in sorted(glob.glob(os.path.join(CSRC, "*"))) + [os.path.join(ROOT, "include", "qsim.h")]:
+        h.update(os.path.basename(path).encode())
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _compile(src: str, bid: str):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-Rpass-analysis=kernel-resource-usage", "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, f"-DQSIM_BUILD_ID=\"{bid}\"", "-Rpass-analysis=kernel-resource-usage", "-c", src,
+           "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
@@ -53,8 +66,9 @@ def _compile(src: str):
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    bid = build_id()
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        done = list(ex.map(_compile, srcs))
+        done = list(ex.map(lambda s: _compile(s, bid), srcs))
     objs = [o for o, _ in done]
     spills = [x for _, sp in done for x in sp]
     if spills:

@@ -11,6 +11,11 @@
 #include <cstdio>
 #include <cstring>
 #include <numeric>
+#include <string>
+
+#ifndef QSIM_BUILD_ID
+#define QSIM_BUILD_ID "unknown"
+#endif
 
 #include "chain_jobs.h"
 
@@ -39,6 +44,23 @@ struct qsim_batch_plan {
 namespace {
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Operand words for the autotuner's timing runs: seeded pseudo-random
+// mantissas under a fixed small exponent, so the timed products switch their
+// multiplier inputs as dense chain operands do (all-zero operands run faster
+// than any real chain, and the tile chosen on them need not be the fastest).
+__global__ __launch_bounds__(256) void tune_fill_kernel(uint32_t* __restrict__ p, size_t words, uint32_t seed,
+                                                        uint32_t one, uint32_t mant) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < words; i += (size_t)gridDim.x * 256) {
+        uint32_t x = (uint32_t)i * 0x9e3779b9u ^ seed;
+        x ^= x >> 16;
+        x *= 0x7feb352du;
+        x ^= x >> 15;
+        x *= 0x846ca68bu;
+        x ^= x >> 16;
+        p[i] = one | (x & mant);
+    }
+}
 
 size_t per_circuit_ws(int n, int prec) {
     return is_split(prec) ? 3 * align256(op_bytes(n, prec)) : 2 * align256(mat_bytes(n));
@@ -323,7 +345,16 @@ qsim_status qsim_autotune(qsim_ctx* ctx, int prec, int n_lo, int n_hi, double* m
         void* buf = nullptr;
         GemmJob* dj = nullptr;
         e = hipMalloc(&buf, 3 * mb * copies);
-        if (e == hipSuccess) e = hipMemsetAsync(buf, 0, 3 * mb * copies, st);
+        if (e == hipSuccess) {
+            // float32: values in [2^-7, 2^-6); bf16 / fp16 halves: the same range in their own format
+            const int elem = fmt_elem(format_of(prec));
+            const uint32_t one = elem == FMT_F32 ? 0x3c000000u : elem == FMT_BF16 ? 0x3c003c00u : 0x20002000u;
+            const uint32_t mant = elem == FMT_F32 ? 0x007fffffu : elem == FMT_BF16 ? 0x007f007fu : 0x03ff03ffu;
+            const size_t words = 3 * mb * copies / 4;
+            hipLaunchKernelGGL(tune_fill_kernel, dim3(std::min<size_t>((words + 255) / 256, 8192)), dim3(256), 0, st,
+                               static_cast<uint32_t*>(buf), words, 0x5eedu + (uint32_t)n, one, mant);
+            e = hipGetLastError();
+        }
         if (e == hipSuccess) e = hipMalloc(&dj, copies * sizeof(GemmJob));
         double best = 1e30;
         int best_cfg = 128;
@@ -332,6 +363,7 @@ qsim_status qsim_autotune(qsim_ctx* ctx, int prec, int n_lo, int n_hi, double* m
             const int cfg = cfgs[ci];
             if (split && prec == QSIM_SPLIT_FP16 && cfg == 128) {
                 if (ms_out) ms_out[(n - 7) * 2 + ci] = -1.0;  // fp16 grouped tiles are always 64 x 64
+                ctx->tune.ms[TuneTable::family(prec)][n][ci] = -1.0;
                 continue;
             }
             std::vector<GemmJob> jobs(copies);
@@ -360,6 +392,7 @@ qsim_status qsim_autotune(qsim_ctx* ctx, int prec, int n_lo, int n_hi, double* m
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
             const double per = ms / reps / copies;  // per product
             if (ms_out) ms_out[(n - 7) * 2 + ci] = per;
+            if (e == hipSuccess) ctx->tune.ms[TuneTable::family(prec)][n][ci] = per;
             if (e == hipSuccess && per < best) {
                 best = per;
                 best_cfg = cfg;
@@ -374,6 +407,123 @@ qsim_status qsim_autotune(qsim_ctx* ctx, int prec, int n_lo, int n_hi, double* m
     if (st) (void)hipStreamDestroy(st);
     if (e != hipSuccess) return device_fail("autotune", e);
     ctx->tune.tuned[TuneTable::family(prec)] = true;
+    return ok();
+}
+
+const char* qsim_build_id(void) { return QSIM_BUILD_ID; }
+
+}  // extern "C"
+
+namespace {
+std::string device_key(int device) {
+    hipDeviceProp_t p{};
+    if (hipGetDeviceProperties(&p, device) != hipSuccess) return "unknown";
+    char buf[512];
+    snprintf(buf, sizeof buf, "%s|%s|%d", p.name, p.gcnArchName, p.multiProcessorCount);
+    for (char* c = buf; *c; ++c)
+        if (*c == '"' || *c == '\\') *c = '_';
+    return buf;
+}
+
+// The string value of `"key": "..."` in text, or "" if absent.
+std::string json_string(const std::string& text, const char* key) {
+    const std::string k = std::string("\"") + key + "\":";
+    size_t at = text.find(k);
+    if (at == std::string::npos) return "";
+    at = text.find('"', at + k.size());
+    if (at == std::string::npos) return "";
+    const size_t end = text.find('"', at + 1);
+    return end == std::string::npos ? "" : text.substr(at + 1, end - at - 1);
+}
+}  // namespace
+
+extern "C" {
+
+qsim_status qsim_tune_save(qsim_ctx* ctx, const char* path) {
+    if (ctx == nullptr || path == nullptr) return fail(QSIM_E_INVALID, "context or path is NULL");
+    FILE* f = fopen(path, "w");
+    if (!f) return fail(QSIM_E_INVALID, "cannot write %s", path);
+    fprintf(f, "{\n \"library\": \"libqsim\",\n \"build\": \"%s\",\n \"device\": \"%s\",\n \"tiles\": [",
+            QSIM_BUILD_ID, device_key(ctx->device).c_str());
+    for (int p = 0; p < kPrecisions; ++p) {
+        fprintf(f, "%s\n  [", p ? "," : "");
+        for (int n = 0; n <= QSIM_MAX_QUBITS; ++n) fprintf(f, "%s%d", n ? ", " : "", ctx->tune.tile[p][n]);
+        fprintf(f, "]");
+    }
+    fprintf(f, "\n ],\n \"tuned\": [");
+    for (int p = 0; p < kPrecisions; ++p) fprintf(f, "%s%d", p ? ", " : "", ctx->tune.tuned[p] ? 1 : 0);
+    fprintf(f, "],\n \"ms_per_product_tile64_tile128\": [");
+    for (int p = 0; p < kPrecisions; ++p) {
+        fprintf(f, "%s\n  [", p ? "," : "");
+        for (int n = 0; n <= QSIM_MAX_QUBITS; ++n)
+            fprintf(f, "%s[%.17g, %.17g]", n ? ", " : "", ctx->tune.ms[p][n][0], ctx->tune.ms[p][n][1]);
+        fprintf(f, "]");
+    }
+    fprintf(f, "\n ]\n}\n");
+    const bool bad = ferror(f) != 0;
+    fclose(f);
+    return bad ? fail(QSIM_E_INVALID, "write error on %s", path) : ok();
+}
+
+qsim_status qsim_tune_load(qsim_ctx* ctx, const char* path) {
+    if (ctx == nullptr || path == nullptr) return fail(QSIM_E_INVALID, "context or path is NULL");
+    FILE* f = fopen(path, "r");
+    if (!f) return fail(QSIM_E_INVALID, "cannot read %s", path);
+    std::string text;
+    char chunk[4096];
+    size_t got;
+    while ((got = fread(chunk, 1, sizeof chunk, f)) > 0) text.append(chunk, got);
+    fclose(f);
+    if (json_string(text, "library") != "libqsim") return fail(QSIM_E_INVALID, "%s is not a libqsim tile cache", path);
+    if (json_string(text, "build") != QSIM_BUILD_ID)
+        return fail(QSIM_E_INVALID, "%s was written by another library build", path);
+    if (json_string(text, "device") != device_key(ctx->device))
+        return fail(QSIM_E_INVALID, "%s was written for another device", path);
+    TuneTable t = ctx->tune;
+    auto numbers = [&](const char* key, std::vector<double>& out, size_t count) {
+        size_t at = text.find(std::string("\"") + key + "\":");
+        if (at == std::string::npos) return false;
+        at = text.find('[', at);
+        const char* c = text.c_str() + at;
+        while (out.size() < count && *c) {
+            if ((*c >= '0' && *c <= '9') || *c == '-') {
+                char* end = nullptr;
+                out.push_back(strtod(c, &end));
+                c = end;
+            } else {
+                ++c;
+            }
+        }
+        return out.size() == count;
+    };
+    std::vector<double> tiles, tuned, ms;
+    if (!numbers("tiles", tiles, (size_t)kPrecisions * (QSIM_MAX_QUBITS + 1)) ||
+        !numbers("tuned", tuned, kPrecisions) ||
+        !numbers("ms_per_product_tile64_tile128", ms, (size_t)kPrecisions * (QSIM_MAX_QUBITS + 1) * 2))
+        return fail(QSIM_E_INVALID, "%s: malformed tile cache", path);
+    for (int p = 0; p < kPrecisions; ++p) {
+        for (int n = 0; n <= QSIM_MAX_QUBITS; ++n) {
+            const int tile = (int)tiles[p * (QSIM_MAX_QUBITS + 1) + n];
+            const bool okv = (n <= 5 && tile == 0) || (n == 6 && tile == 64) ||
+                             (n >= 7 && (tile == 64 || (tile == 128 && p != QSIM_SPLIT_FP16)));
+            if (!okv) return fail(QSIM_E_INVALID, "%s: tile %d for precision %d, n = %d is not valid", path, tile, p, n);
+            t.tile[p][n] = tile;
+            t.ms[p][n][0] = ms[(p * (QSIM_MAX_QUBITS + 1) + n) * 2];
+            t.ms[p][n][1] = ms[(p * (QSIM_MAX_QUBITS + 1) + n) * 2 + 1];
+        }
+        t.tuned[p] = tuned[p] != 0.0;
+    }
+    ctx->tune = t;
+    return ok();
+}
+
+qsim_status qsim_tune_ms(qsim_ctx* ctx, int prec, double* ms_out) {
+    if (ctx == nullptr || ms_out == nullptr) return fail(QSIM_E_INVALID, "context or output is NULL");
+    if (!valid_prec(prec)) return fail(QSIM_E_INVALID, "unknown precision %d", prec);
+    for (int n = 0; n <= QSIM_MAX_QUBITS; ++n) {
+        ms_out[2 * n] = ctx->tune.ms[prec][n][0];
+        ms_out[2 * n + 1] = ctx->tune.ms[prec][n][1];
+    }
     return ok();
 }
 

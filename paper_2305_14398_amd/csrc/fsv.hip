@@ -76,9 +76,18 @@ struct FsvGate {
     int32_t cglob;  // a non-local control qubit, or -1
     int32_t width;  // dense: qubits in the range; phase: non-local qubits of its table
     int32_t moff;   // dense / table / phase: offset of its float32 data in the plan's pool
-    int32_t real;   // general: 1 if every matrix entry is real
+    int32_t real;   // general: the matrix's form (FSV_COMPLEX .. FSV_IMAGOFF), which fixes its arithmetic
     float m[8];  // row-major 2x2 (re, im); a diagonal gate uses m[0..1] and m[6..7]
 };
+
+// Forms of a non-diagonal 2x2 (after rounding to float32), each applied with
+// only the arithmetic it needs:
+//   FSV_COMPLEX  any matrix: 16 multiply-adds per amplitude pair;
+//   FSV_REAL     every entry real (H, RY): 8;
+//   FSV_XSWAP    [[0, 1], [1, 0]] (X, the target of CNOT): an exact exchange;
+//   FSV_ANTI     [[0, b], [c, 0]] (Y, phases times X): 8;
+//   FSV_IMAGOFF  real diagonal, imaginary off-diagonal (RX): 8.
+enum : int32_t { FSV_COMPLEX = 0, FSV_REAL = 1, FSV_XSWAP = 2, FSV_ANTI = 3, FSV_IMAGOFF = 4 };
 
 struct FsvPass {
     int32_t L;   // local bits 0..L-1 are qubits 0..L-1
@@ -107,6 +116,17 @@ __device__ __forceinline__ int fsv_pos(const FsvPass& p, int b) {
     for (int h = 0; h < kFsvMaxHigh; ++h)
         if (h < p.nh && b == p.L + h) q = p.high[h];
     return q;
+}
+
+// Form of a float32 2x2 (row-major (re, im)); exact tests on the rounded entries.
+inline int fsv_form(const float m[8]) {
+    const bool real = m[1] == 0.f && m[3] == 0.f && m[5] == 0.f && m[7] == 0.f;
+    const bool anti = m[0] == 0.f && m[1] == 0.f && m[6] == 0.f && m[7] == 0.f;
+    if (anti && real && m[2] == 1.f && m[4] == 1.f) return FSV_XSWAP;
+    if (anti) return FSV_ANTI;
+    if (real) return FSV_REAL;
+    if (m[1] == 0.f && m[7] == 0.f && m[2] == 0.f && m[4] == 0.f) return FSV_IMAGOFF;
+    return FSV_COMPLEX;
 }
 
 // Complex multiply-accumulate helpers (float32, fused).
@@ -167,6 +187,66 @@ __device__ __forceinline__ void fsv_general(f32x16& ar_out, f32x16& ai_out, cons
     ai_out = ai;
 }
 
+// X on register bit RB (exact exchange of the pair); CP as in fsv_general.
+// LANE: a control on a lane bit keeps the pair where it is 0 (a select, still
+// exact); without one the exchange is unconditional.
+template <int RB, int CP, bool LANE>
+__device__ __forceinline__ void fsv_xswap(f32x16& ar_out, f32x16& ai_out, bool lane_on) {
+    f32x16 ar = ar_out, ai = ai_out;
+    fsv_for16([&](auto I_) {
+        constexpr int r0 = decltype(I_)::value;
+        if ((r0 >> RB) & 1) return;
+        if constexpr (CP >= 0) {
+            if (!((r0 >> CP) & 1)) return;
+        }
+        constexpr int r1 = r0 | (1 << RB);
+        const float x0r = ar[r0], x0i = ai[r0], x1r = ar[r1], x1i = ai[r1];
+        if constexpr (LANE) {
+            ar[r0] = lane_on ? x1r : x0r;
+            ai[r0] = lane_on ? x1i : x0i;
+            ar[r1] = lane_on ? x0r : x1r;
+            ai[r1] = lane_on ? x0i : x1i;
+        } else {
+            ar[r0] = x1r;
+            ai[r0] = x1i;
+            ar[r1] = x0r;
+            ai[r1] = x0i;
+        }
+    });
+    ar_out = ar;
+    ai_out = ai;
+}
+
+// [[0, b], [c, 0]] (ANTI) or [[a, i b'], [i c', d]] with a, d, b', c' real
+// (IMAGOFF) on register bit RB, no register-bit control; a lane control that is
+// 0 makes the pair the identity (ANTI: a select; IMAGOFF: the identity has the
+// same form).
+template <int RB, int FORM>
+__device__ __forceinline__ void fsv_sparse(f32x16& ar_out, f32x16& ai_out, const Mat2 M, bool lane_on) {
+    f32x16 ar = ar_out, ai = ai_out;
+    fsv_for16([&](auto I_) {
+        constexpr int r0 = decltype(I_)::value;
+        if ((r0 >> RB) & 1) return;
+        constexpr int r1 = r0 | (1 << RB);
+        const float x0r = ar[r0], x0i = ai[r0], x1r = ar[r1], x1i = ai[r1];
+        if constexpr (FORM == FSV_ANTI) {
+            const float y0r = fmaf(M.m1r, x1r, -M.m1i * x1i), y0i = fmaf(M.m1r, x1i, M.m1i * x1r);
+            const float y1r = fmaf(M.m2r, x0r, -M.m2i * x0i), y1i = fmaf(M.m2r, x0i, M.m2i * x0r);
+            ar[r0] = lane_on ? y0r : x0r;
+            ai[r0] = lane_on ? y0i : x0i;
+            ar[r1] = lane_on ? y1r : x1r;
+            ai[r1] = lane_on ? y1i : x1i;
+        } else {
+            ar[r0] = fmaf(M.m0r, x0r, -M.m1i * x1i);
+            ai[r0] = fmaf(M.m0r, x0i, M.m1i * x1r);
+            ar[r1] = fmaf(M.m3r, x1r, -M.m2i * x0i);
+            ai[r1] = fmaf(M.m3r, x1i, M.m2i * x0r);
+        }
+    });
+    ar_out = ar;
+    ai_out = ai;
+}
+
 template <int RB, bool REAL>
 __device__ __forceinline__ void fsv_general_cp(f32x16& ar, f32x16& ai, const Mat2 M, int cp, bool lane_ctrl,
                                                bool lane_on) {
@@ -197,9 +277,38 @@ __device__ __forceinline__ void fsv_general_cp(f32x16& ar, f32x16& ai, const Mat
 }
 
 template <int RB>
-__device__ __forceinline__ void fsv_general_rb(f32x16& ar, f32x16& ai, const Mat2 M, bool real, int cp,
+__device__ __forceinline__ void fsv_general_rb(f32x16& ar, f32x16& ai, const Mat2 M, int form, int cp,
                                                bool lane_ctrl, bool lane_on) {
-    if (real)
+    if (form == FSV_XSWAP) {
+        switch (cp) {
+            case 0: if constexpr (RB != 0) fsv_xswap<RB, 0, false>(ar, ai, true); return;
+            case 1: if constexpr (RB != 1) fsv_xswap<RB, 1, false>(ar, ai, true); return;
+            case 2: if constexpr (RB != 2) fsv_xswap<RB, 2, false>(ar, ai, true); return;
+            case 3: if constexpr (RB != 3) fsv_xswap<RB, 3, false>(ar, ai, true); return;
+            default:
+                if (lane_ctrl)
+                    fsv_xswap<RB, -1, true>(ar, ai, lane_on);
+                else
+                    fsv_xswap<RB, -1, false>(ar, ai, true);
+                return;
+        }
+    }
+    if (cp < 0 && form == FSV_ANTI) {
+        fsv_sparse<RB, FSV_ANTI>(ar, ai, M, !lane_ctrl || lane_on);
+        return;
+    }
+    if (cp < 0 && form == FSV_IMAGOFF) {
+        Mat2 L = M;
+        if (lane_ctrl && !lane_on) {
+            L.m0r = 1.f;
+            L.m3r = 1.f;
+            L.m1i = 0.f;
+            L.m2i = 0.f;
+        }
+        fsv_sparse<RB, FSV_IMAGOFF>(ar, ai, L, true);
+        return;
+    }
+    if (form == FSV_REAL)
         fsv_general_cp<RB, true>(ar, ai, M, cp, lane_ctrl, lane_on);
     else
         fsv_general_cp<RB, false>(ar, ai, M, cp, lane_ctrl, lane_on);
@@ -499,12 +608,12 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
         }
         if (g.kind == FSV_GENERAL) {
             const Mat2 M = {g.m[0], g.m[1], g.m[2], g.m[3], g.m[4], g.m[5], g.m[6], g.m[7]};
-            const bool real = g.real != 0;
+            const int form = g.real;
             switch (g.tloc & 3) {
-                case 0: fsv_general_rb<0>(ar, ai, M, real, cp, lane_ctrl, lane_on); break;
-                case 1: fsv_general_rb<1>(ar, ai, M, real, cp, lane_ctrl, lane_on); break;
-                case 2: fsv_general_rb<2>(ar, ai, M, real, cp, lane_ctrl, lane_on); break;
-                default: fsv_general_rb<3>(ar, ai, M, real, cp, lane_ctrl, lane_on); break;
+                case 0: fsv_general_rb<0>(ar, ai, M, form, cp, lane_ctrl, lane_on); break;
+                case 1: fsv_general_rb<1>(ar, ai, M, form, cp, lane_ctrl, lane_on); break;
+                case 2: fsv_general_rb<2>(ar, ai, M, form, cp, lane_ctrl, lane_on); break;
+                default: fsv_general_rb<3>(ar, ai, M, form, cp, lane_ctrl, lane_on); break;
             }
             continue;
         }
@@ -832,7 +941,7 @@ uint64_t op_qubits(const LoweredGate& l) {
 // become ready during the sweep are considered in the same sweep.  So a pass may
 // take gates from later layers on its local qubits while a gate on a qubit that
 // is not local waits for a later pass.  exec_order (optional) receives the
-// operations pass by pass.
+// operations pass by pass, each pass in the order its launch applies them.
 void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass>& passes,
                   std::vector<FsvGate>& table, std::vector<float>& pool, std::vector<int>* exec_order = nullptr) {
     passes.clear();
@@ -917,7 +1026,6 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
         p.op0 = executed;
         executed += (int)pass_ops.size();
         p.op1 = executed;
-        if (exec_order) exec_order->insert(exec_order->end(), pass_ops.begin(), pass_ops.end());
         auto local_bit = [&](int q) {
             if (q < 0) return -1;
             if (q < p.L) return q;
@@ -937,7 +1045,7 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
                 d.width = l.width;
                 d.moff = pool_offset(l.op, l.width, pool, seen);
             }
-            d.real = (l.m[1] == 0.f && l.m[3] == 0.f && l.m[5] == 0.f && l.m[7] == 0.f) ? 1 : 0;
+            d.real = fsv_form(l.m);
             std::copy(l.m, l.m + 8, d.m);
             return d;
         };
@@ -989,6 +1097,10 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
                 for (int b : succ[pick]) --indeg[b];
             }
         }
+        // the order the kernel runs them in (runs of diagonal operations are
+        // multiplied out below, but commute, so any order within a run is this one)
+        if (exec_order)
+            for (size_t q : order) exec_order->push_back((int)q);
         for (size_t k = 0; k < order.size();) {
             if (gs[order[k]].kind != FSV_DIAG) {
                 table.push_back(record(gs[order[k]]));

@@ -120,11 +120,15 @@ struct TuneTable {
     static int family(int prec) { return prec; }
     int tile[kPrecisions][QSIM_MAX_QUBITS + 1];
     bool tuned[kPrecisions];
+    // milliseconds per product measured by the autotuner for tile 64 and 128 (-1: not measured)
+    double ms[kPrecisions][QSIM_MAX_QUBITS + 1][2];
     TuneTable() {
         for (int f = 0; f < kPrecisions; ++f) {
             tuned[f] = false;
-            for (int n = 0; n <= QSIM_MAX_QUBITS; ++n)
+            for (int n = 0; n <= QSIM_MAX_QUBITS; ++n) {
                 tile[f][n] = n >= 7 && f != QSIM_SPLIT_FP16 ? 128 : (n >= 6 ? 64 : 0);
+                ms[f][n][0] = ms[f][n][1] = -1.0;
+            }
         }
     }
     // Never wider than the matrix: n = 6 always uses 64, n <= 5 the whole-product path.

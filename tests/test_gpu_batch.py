@@ -123,6 +123,37 @@ def test_autotune_records_choices_and_stays_correct(ctx):
     B.qsim_tune_set(ctx, B.QSIM_FP32_4M, 9, tiles[9])
 
 
+def test_tile_cache_round_trip_and_rejection(ctx, tmp_path):
+    """qsim_tune_save / qsim_tune_load: the table, tuned flags and timings come back as saved; a file from
+    another build or device, or with an invalid tile, is rejected and leaves the table unchanged."""
+    prec = B.QSIM_SPLIT_BF16_3M
+    B.qsim_autotune(ctx, prec, 7, 9)
+    saved_tiles = B.qsim_tune_get(ctx, prec)
+    saved_ms = B.qsim_tune_ms(ctx, prec)
+    assert set(saved_ms) == {7, 8, 9} and all(a > 0 and b > 0 for a, b in saved_ms.values())
+    path = tmp_path / "tiles.json"
+    B.qsim_tune_save(ctx, str(path))
+    text = path.read_text()
+    import json
+    doc = json.loads(text)
+    assert doc["build"] == B.qsim_build_id()
+    assert doc["tiles"][prec] == saved_tiles
+    other = 64 if saved_tiles[8] == 128 else 128
+    B.qsim_tune_set(ctx, prec, 8, other)
+    B.qsim_tune_load(ctx, str(path))
+    assert B.qsim_tune_get(ctx, prec) == saved_tiles
+    assert B.qsim_tune_ms(ctx, prec) == saved_ms
+    B.qsim_tune_set(ctx, prec, 8, other)
+    for bad in (text.replace(doc["build"], "0" * 16), text.replace(doc["device"], "another device"),
+                text.replace('"tiles": [', '"tiles": [\n  [0, 0, 0, 0, 0, 0, 64, 96,', 1)):
+        path.write_text(bad)
+        with pytest.raises(B.QsimError) as e:
+            B.qsim_tune_load(ctx, str(path))
+        assert e.value.status == B.QSIM_E_INVALID
+        assert B.qsim_tune_get(ctx, prec)[8] == other
+    B.qsim_tune_set(ctx, prec, 8, saved_tiles[8])
+
+
 def test_one_shot_batched_call(ctx):
     circuits = [W.ghz_chain(5), W.dj(7, 5), W.qft(8)]
     outs = [G.planar(c.n) for c in circuits]

@@ -361,3 +361,23 @@ def test_fsv_schedule_keeps_custom_ranges_local():
         for x in (lg[i] for i in order[first:first + cnt]):
             if x[0] == "CUSTOM":
                 assert set(x[1]) <= local, (x[1], low, highs)
+
+
+def test_build_id_is_the_hash_of_the_sources_the_library_was_built_from():
+    """A tile cache records qsim_build_id and is only loaded by a library built from the same sources."""
+    from paper_2305_14398_amd import build
+    assert B.qsim_build_id() == build.build_id()
+    assert len(B.qsim_build_id()) == 16
+
+
+def test_fsv_schedule_order_replays_to_the_same_state():
+    """The reported order is the one each pass applies (reordered where operations commute); replayed gate by
+    gate through the oracle (route B) it gives the circuit's own final state."""
+    from oracle import fsv
+    n = 14
+    gates = W.gate_tuples(W.random_layers(n, 3, np.random.default_rng(11))) + W.gate_tuples(W.qft(n))
+    sched, order = B.qsim_fsv_schedule(n, gates, with_order=True)
+    assert len(sched) > 1 and order != sorted(order)
+    a = fsv.final_state(n, gates)
+    b = fsv.final_state(n, [gates[i] for i in order])
+    assert np.abs(a - b).max() <= 1e-12
