@@ -43,10 +43,18 @@ def build_id() -> str:
     return h.hexdigest()[:16]
 
 
+# Per-source extra flags.  fsv.hip: branches on uniform values (the operation
+# dispatch of the full-state pass) are left unstructured, so each dispatch
+# target updates the state registers in place and jumps straight to the loop
+# latch; structuring them joins every target through flow blocks whose merges
+# the register allocator resolves with whole-state copies.
+EXTRA_FLAGS = {"fsv.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions"]}
+
+
 def _compile(src: str, bid: str):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, f"-DQSIM_BUILD_ID=\"{bid}\"", "-Rpass-analysis=kernel-resource-usage", "-c", src,
-           "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA_FLAGS.get(os.path.basename(src), []), f"-DQSIM_BUILD_ID=\"{bid}\"",
+           "-Rpass-analysis=kernel-resource-usage", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

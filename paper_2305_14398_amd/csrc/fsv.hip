@@ -49,9 +49,15 @@ constexpr int kFsvLocal = 12;     // local qubits per workgroup: 4096 amplitudes
 constexpr int kFsvMinLow = 6;     // low qubits always local: 64 lanes x 4 B contiguous per plane
 constexpr int kFsvMaxHigh = kFsvLocal - kFsvMinLow;
 constexpr int kFsvNormBlocks = 1024;
-constexpr int kFsvMaxOps = 256;   // operations per pass, staged in LDS (16 KiB)
+constexpr int kFsvMaxOps = 256;   // operations per pass (a planning cap)
 
-typedef float f32x16 __attribute__((ext_vector_type(16)));
+// A thread's 16 values of one plane: 16 scalars (every index is a compile-time
+// constant), so that each register is coalesced on its own.
+struct f32x16 {
+    float v[16];
+    __device__ __forceinline__ float& operator[](int i) { return v[i]; }
+    __device__ __forceinline__ const float& operator[](int i) const { return v[i]; }
+};
 
 // Calls f(std::integral_constant<int, r>) for r = 0..15: every register index
 // is a compile-time constant from the start, so the amplitude vectors never
@@ -129,260 +135,308 @@ inline int fsv_form(const float m[8]) {
     return FSV_COMPLEX;
 }
 
-// Complex multiply-accumulate helpers (float32, fused).
-__device__ __forceinline__ void cmul(float& xr, float& xi, float fr, float fi) {
-    const float yr = fmaf(fr, xr, -fi * xi);
-    const float yi = fmaf(fr, xi, fi * xr);
-    xr = yr;
-    xi = yi;
+// ---- In-place amplitude updates ----
+// The operation loop keeps a thread's 32 amplitude values (16 re, 16 im) in
+// fixed registers, and every update below rewrites its inputs in place.  They
+// are short inline-assembly sequences with tied operands: written as plain
+// expressions, each branch of the operation dispatch gets fresh result
+// registers and the compiler copies the whole state back at the merge, which
+// costs more than the arithmetic itself.  Only plain float32 VALU instructions
+// appear (v_mul_f32, v_fma_f32, v_fmac_f32, v_cndmask_b32, v_swap_b32, v_mov_b32);
+// each sequence keeps the rounding of the expression written beside it.
+// Coefficients are SGPRs when they are uniform (VC = false) and VGPRs when a
+// control on a lane index bit makes them per lane (VC = true).
+
+// x <- f x (complex):  xr' = fma(fr, xr, -(fi xi)),  xi' = fma(fr, xi, fi xr)
+#define FSV_CMUL_ASM                 \
+    "v_mul_f32 %0, %5, %3\n\t"      \
+    "v_mul_f32 %1, %5, %2\n\t"      \
+    "v_fma_f32 %2, %4, %2, -%0\n\t" \
+    "v_fma_f32 %3, %4, %3, %1"
+template <bool VC>
+__device__ __forceinline__ void fsv_cmul(float& xr, float& xi, float fr, float fi) {
+    float t, u;
+    if constexpr (VC)
+        asm(FSV_CMUL_ASM : "=&v"(t), "=&v"(u), "+v"(xr), "+v"(xi) : "v"(fr), "v"(fi));
+    else
+        asm(FSV_CMUL_ASM : "=&v"(t), "=&v"(u), "+v"(xr), "+v"(xi) : "s"(fr), "s"(fi));
 }
 
-__device__ __forceinline__ void cmul_at(f32x16& ar, f32x16& ai, int r, float fr, float fi) {
-    const float xr = ar[r], xi = ai[r];
-    ar[r] = fmaf(fr, xr, -fi * xi);
-    ai[r] = fmaf(fr, xi, fi * xr);
+// One real plane of a pair under a real 2x2 [[a, b], [c, d]]:
+//   x0' = fma(a, x0, b x1),  x1' = fma(c, x0, d x1)
+#define FSV_ROT_ASM              \
+    "v_mul_f32 %0, %4, %2\n\t"  \
+    "v_mul_f32 %2, %6, %2\n\t"  \
+    "v_fmac_f32 %2, %5, %1\n\t" \
+    "v_fma_f32 %1, %3, %1, %0"
+template <bool VC>
+__device__ __forceinline__ void fsv_rot(float& x0, float& x1, float a, float b, float c, float d) {
+    float t;
+    if constexpr (VC)
+        asm(FSV_ROT_ASM : "=&v"(t), "+v"(x0), "+v"(x1) : "v"(a), "v"(b), "v"(c), "v"(d));
+    else
+        asm(FSV_ROT_ASM : "=&v"(t), "+v"(x0), "+v"(x1) : "s"(a), "s"(b), "s"(c), "s"(d));
 }
 
-// A 2x2 complex matrix in scalars (row-major (re, im)), so that it lives in
-// registers whatever the control flow around it.
+// A pair under [[a, i b], [i c, d]] with a, b, c, d real (RX and its kind):
+//   x0r' = fma(a, x0r, -(b x1i)),  x0i' = fma(a, x0i, b x1r)
+//   x1r' = fma(d, x1r, -(c x0i)),  x1i' = fma(d, x1i, c x0r)
+#define FSV_IMAGOFF_ASM              \
+    "v_mul_f32 %0, %9, %7\n\t"       \
+    "v_mul_f32 %1, %9, %6\n\t"       \
+    "v_mul_f32 %2, %10, %5\n\t"      \
+    "v_mul_f32 %3, %10, %4\n\t"      \
+    "v_fma_f32 %4, %8, %4, -%0\n\t"  \
+    "v_fma_f32 %5, %8, %5, %1\n\t"   \
+    "v_fma_f32 %6, %11, %6, -%2\n\t" \
+    "v_fma_f32 %7, %11, %7, %3"
+template <bool VC>
+__device__ __forceinline__ void fsv_imagoff(float& x0r, float& x0i, float& x1r, float& x1i, float a, float b,
+                                            float c, float d) {
+    float t0, t1, t2, t3;
+    if constexpr (VC)
+        asm(FSV_IMAGOFF_ASM
+            : "=&v"(t0), "=&v"(t1), "=&v"(t2), "=&v"(t3), "+v"(x0r), "+v"(x0i), "+v"(x1r), "+v"(x1i)
+            : "v"(a), "v"(b), "v"(c), "v"(d));
+    else
+        asm(FSV_IMAGOFF_ASM
+            : "=&v"(t0), "=&v"(t1), "=&v"(t2), "=&v"(t3), "+v"(x0r), "+v"(x0i), "+v"(x1r), "+v"(x1i)
+            : "s"(a), "s"(b), "s"(c), "s"(d));
+}
+
+// A pair under any complex 2x2 m (row-major m0 m1 / m2 m3):
+//   y0r = fma(m0r, x0r, fma(-m0i, x0i, fma(m1r, x1r, -(m1i x1i))))
+//   y0i = fma(m0r, x0i, fma( m0i, x0r, fma(m1r, x1i,   m1i x1r)))
+//   y1r = fma(m2r, x0r, fma(-m2i, x0i, fma(m3r, x1r, -(m3i x1i))))
+//   y1i = fma(m2r, x0i, fma( m2i, x0r, fma(m3r, x1i,   m3i x1r)))
+// The partial sums need x1 last, so y1 lands in x1's registers and y0 in x0's.
+#define FSV_CPLX_ASM                   \
+    "v_mul_f32 %0, %11, %7\n\t"        \
+    "v_fma_f32 %0, %10, %6, -%0\n\t"   \
+    "v_fma_f32 %0, -%9, %5, %0\n\t"    \
+    "v_mul_f32 %1, %11, %6\n\t"        \
+    "v_fmac_f32 %1, %10, %7\n\t"       \
+    "v_fmac_f32 %1, %9, %4\n\t"        \
+    "v_mul_f32 %2, %15, %7\n\t"        \
+    "v_fma_f32 %2, %14, %6, -%2\n\t"   \
+    "v_fma_f32 %2, -%13, %5, %2\n\t"   \
+    "v_mul_f32 %3, %15, %6\n\t"        \
+    "v_fmac_f32 %3, %14, %7\n\t"       \
+    "v_fmac_f32 %3, %13, %4\n\t"       \
+    "v_fma_f32 %6, %12, %4, %2\n\t"    \
+    "v_fma_f32 %7, %12, %5, %3\n\t"    \
+    "v_fma_f32 %4, %8, %4, %0\n\t"     \
+    "v_fma_f32 %5, %8, %5, %1"
 struct Mat2 {
     float m0r, m0i, m1r, m1i, m2r, m2i, m3r, m3i;
 };
-
-// Non-diagonal 2x2 on register bit RB.  CP = register bit of the control
-// (compile time), or -1 (no control, or a control on a lane index bit: lanes
-// whose control bit is 0 multiply by the identity).  REAL:
-// every entry is real (H, X, RY, CNOT), half the multiply-adds.
-template <int RB, int CP, bool REAL>
-__device__ __forceinline__ void fsv_general(f32x16& ar_out, f32x16& ai_out, const Mat2 M) {
-    f32x16 ar = ar_out, ai = ai_out;  // value copies: the caller sees whole-vector accesses only
-    const float m0r = M.m0r, m0i = M.m0i, m1r = M.m1r, m1i = M.m1i;
-    const float m2r = M.m2r, m2i = M.m2i, m3r = M.m3r, m3i = M.m3i;
-    fsv_for16([&](auto I_) {
-        constexpr int r0 = decltype(I_)::value;
-        if ((r0 >> RB) & 1) return;
-        if constexpr (CP >= 0) {
-            if (!((r0 >> CP) & 1)) return;
-        }
-        const int r1 = r0 | (1 << RB);
-        const float x0r = ar[r0], x0i = ai[r0], x1r = ar[r1], x1i = ai[r1];
-        float y0r, y0i, y1r, y1i;
-        if (REAL) {
-            y0r = fmaf(m0r, x0r, m1r * x1r);
-            y0i = fmaf(m0r, x0i, m1r * x1i);
-            y1r = fmaf(m2r, x0r, m3r * x1r);
-            y1i = fmaf(m2r, x0i, m3r * x1i);
-        } else {
-            y0r = fmaf(m0r, x0r, fmaf(-m0i, x0i, fmaf(m1r, x1r, -m1i * x1i)));
-            y0i = fmaf(m0r, x0i, fmaf(m0i, x0r, fmaf(m1r, x1i, m1i * x1r)));
-            y1r = fmaf(m2r, x0r, fmaf(-m2i, x0i, fmaf(m3r, x1r, -m3i * x1i)));
-            y1i = fmaf(m2r, x0i, fmaf(m2i, x0r, fmaf(m3r, x1i, m3i * x1r)));
-        }
-        ar[r0] = y0r;
-        ai[r0] = y0i;
-        ar[r1] = y1r;
-        ai[r1] = y1i;
-    });
-    ar_out = ar;
-    ai_out = ai;
-}
-
-// X on register bit RB (exact exchange of the pair); CP as in fsv_general.
-// LANE: a control on a lane bit keeps the pair where it is 0 (a select, still
-// exact); without one the exchange is unconditional.
-template <int RB, int CP, bool LANE>
-__device__ __forceinline__ void fsv_xswap(f32x16& ar_out, f32x16& ai_out, bool lane_on) {
-    f32x16 ar = ar_out, ai = ai_out;
-    fsv_for16([&](auto I_) {
-        constexpr int r0 = decltype(I_)::value;
-        if ((r0 >> RB) & 1) return;
-        if constexpr (CP >= 0) {
-            if (!((r0 >> CP) & 1)) return;
-        }
-        constexpr int r1 = r0 | (1 << RB);
-        const float x0r = ar[r0], x0i = ai[r0], x1r = ar[r1], x1i = ai[r1];
-        if constexpr (LANE) {
-            ar[r0] = lane_on ? x1r : x0r;
-            ai[r0] = lane_on ? x1i : x0i;
-            ar[r1] = lane_on ? x0r : x1r;
-            ai[r1] = lane_on ? x0i : x1i;
-        } else {
-            ar[r0] = x1r;
-            ai[r0] = x1i;
-            ar[r1] = x0r;
-            ai[r1] = x0i;
-        }
-    });
-    ar_out = ar;
-    ai_out = ai;
-}
-
-// [[0, b], [c, 0]] (ANTI) or [[a, i b'], [i c', d]] with a, d, b', c' real
-// (IMAGOFF) on register bit RB, no register-bit control; a lane control that is
-// 0 makes the pair the identity (ANTI: a select; IMAGOFF: the identity has the
-// same form).
-template <int RB, int FORM>
-__device__ __forceinline__ void fsv_sparse(f32x16& ar_out, f32x16& ai_out, const Mat2 M, bool lane_on) {
-    f32x16 ar = ar_out, ai = ai_out;
-    fsv_for16([&](auto I_) {
-        constexpr int r0 = decltype(I_)::value;
-        if ((r0 >> RB) & 1) return;
-        constexpr int r1 = r0 | (1 << RB);
-        const float x0r = ar[r0], x0i = ai[r0], x1r = ar[r1], x1i = ai[r1];
-        if constexpr (FORM == FSV_ANTI) {
-            const float y0r = fmaf(M.m1r, x1r, -M.m1i * x1i), y0i = fmaf(M.m1r, x1i, M.m1i * x1r);
-            const float y1r = fmaf(M.m2r, x0r, -M.m2i * x0i), y1i = fmaf(M.m2r, x0i, M.m2i * x0r);
-            ar[r0] = lane_on ? y0r : x0r;
-            ai[r0] = lane_on ? y0i : x0i;
-            ar[r1] = lane_on ? y1r : x1r;
-            ai[r1] = lane_on ? y1i : x1i;
-        } else {
-            ar[r0] = fmaf(M.m0r, x0r, -M.m1i * x1i);
-            ai[r0] = fmaf(M.m0r, x0i, M.m1i * x1r);
-            ar[r1] = fmaf(M.m3r, x1r, -M.m2i * x0i);
-            ai[r1] = fmaf(M.m3r, x1i, M.m2i * x0r);
-        }
-    });
-    ar_out = ar;
-    ai_out = ai;
-}
-
-template <int RB, bool REAL>
-__device__ __forceinline__ void fsv_general_cp(f32x16& ar, f32x16& ai, const Mat2 M, int cp, bool lane_ctrl,
-                                               bool lane_on) {
-    switch (cp) {
-        case 0: if constexpr (RB != 0) fsv_general<RB, 0, REAL>(ar, ai, M); break;
-        case 1: if constexpr (RB != 1) fsv_general<RB, 1, REAL>(ar, ai, M); break;
-        case 2: if constexpr (RB != 2) fsv_general<RB, 2, REAL>(ar, ai, M); break;
-        case 3: if constexpr (RB != 3) fsv_general<RB, 3, REAL>(ar, ai, M); break;
-        default:
-            if (lane_ctrl) {
-                // a control on one of the lane's index bits: lanes where it is 0
-                // apply the identity (exact: products with 1 and 0)
-                Mat2 L = M;
-                L.m0r = lane_on ? M.m0r : 1.f;
-                L.m0i = lane_on ? M.m0i : 0.f;
-                L.m1r = lane_on ? M.m1r : 0.f;
-                L.m1i = lane_on ? M.m1i : 0.f;
-                L.m2r = lane_on ? M.m2r : 0.f;
-                L.m2i = lane_on ? M.m2i : 0.f;
-                L.m3r = lane_on ? M.m3r : 1.f;
-                L.m3i = lane_on ? M.m3i : 0.f;
-                fsv_general<RB, -1, REAL>(ar, ai, L);
-            } else {
-                fsv_general<RB, -1, REAL>(ar, ai, M);
-            }
-            break;
-    }
-}
-
-template <int RB>
-__device__ __forceinline__ void fsv_general_rb(f32x16& ar, f32x16& ai, const Mat2 M, int form, int cp,
-                                               bool lane_ctrl, bool lane_on) {
-    if (form == FSV_XSWAP) {
-        switch (cp) {
-            case 0: if constexpr (RB != 0) fsv_xswap<RB, 0, false>(ar, ai, true); return;
-            case 1: if constexpr (RB != 1) fsv_xswap<RB, 1, false>(ar, ai, true); return;
-            case 2: if constexpr (RB != 2) fsv_xswap<RB, 2, false>(ar, ai, true); return;
-            case 3: if constexpr (RB != 3) fsv_xswap<RB, 3, false>(ar, ai, true); return;
-            default:
-                if (lane_ctrl)
-                    fsv_xswap<RB, -1, true>(ar, ai, lane_on);
-                else
-                    fsv_xswap<RB, -1, false>(ar, ai, true);
-                return;
-        }
-    }
-    if (cp < 0 && form == FSV_ANTI) {
-        fsv_sparse<RB, FSV_ANTI>(ar, ai, M, !lane_ctrl || lane_on);
-        return;
-    }
-    if (cp < 0 && form == FSV_IMAGOFF) {
-        Mat2 L = M;
-        if (lane_ctrl && !lane_on) {
-            L.m0r = 1.f;
-            L.m3r = 1.f;
-            L.m1i = 0.f;
-            L.m2i = 0.f;
-        }
-        fsv_sparse<RB, FSV_IMAGOFF>(ar, ai, L, true);
-        return;
-    }
-    if (form == FSV_REAL)
-        fsv_general_cp<RB, true>(ar, ai, M, cp, lane_ctrl, lane_on);
+template <bool VC>
+__device__ __forceinline__ void fsv_cplx(float& x0r, float& x0i, float& x1r, float& x1i, const Mat2& M) {
+    float a, b, c, d;
+    if constexpr (VC)
+        asm(FSV_CPLX_ASM
+            : "=&v"(a), "=&v"(b), "=&v"(c), "=&v"(d), "+v"(x0r), "+v"(x0i), "+v"(x1r), "+v"(x1i)
+            : "v"(M.m0r), "v"(M.m0i), "v"(M.m1r), "v"(M.m1i), "v"(M.m2r), "v"(M.m2i), "v"(M.m3r), "v"(M.m3i));
     else
-        fsv_general_cp<RB, false>(ar, ai, M, cp, lane_ctrl, lane_on);
+        asm(FSV_CPLX_ASM
+            : "=&v"(a), "=&v"(b), "=&v"(c), "=&v"(d), "+v"(x0r), "+v"(x0i), "+v"(x1r), "+v"(x1i)
+            : "s"(M.m0r), "s"(M.m0i), "s"(M.m1r), "s"(M.m1i), "s"(M.m2r), "s"(M.m2i), "s"(M.m3r), "s"(M.m3i));
+}
+
+// Exact exchanges: always, or in the lanes whose bit is set in a uniform mask.
+__device__ __forceinline__ void fsv_swap(float& x0, float& x1) { asm("v_swap_b32 %0, %1" : "+v"(x0), "+v"(x1)); }
+__device__ __forceinline__ void fsv_cswap(float& x0, float& x1, uint64_t mask) {
+    float t;
+    asm("v_mov_b32 %0, %1\n\t"
+        "v_cndmask_b32_e64 %1, %1, %2, %3\n\t"
+        "v_cndmask_b32_e64 %2, %2, %0, %3"
+        : "=&v"(t), "+v"(x0), "+v"(x1)
+        : "s"(mask));
+}
+
+// A non-diagonal 2x2 of form FORM on register bit RB; with CP >= 0 only the
+// pairs whose register bit CP is set (a control on that bit).
+template <int RB, int CP, int FORM, bool VC>
+__device__ __forceinline__ void fsv_pairs(f32x16& ar, f32x16& ai, const Mat2& M) {
+    fsv_for16([&](auto I_) {
+        constexpr int r0 = decltype(I_)::value;
+        if constexpr (((r0 >> RB) & 1) == 0 && (CP < 0 || ((r0 >> CP) & 1) == 1)) {
+            constexpr int r1 = r0 | (1 << RB);
+            float x0r = ar[r0], x0i = ai[r0], x1r = ar[r1], x1i = ai[r1];
+            if constexpr (FORM == FSV_REAL) {
+                fsv_rot<VC>(x0r, x1r, M.m0r, M.m1r, M.m2r, M.m3r);
+                fsv_rot<VC>(x0i, x1i, M.m0r, M.m1r, M.m2r, M.m3r);
+            } else if constexpr (FORM == FSV_IMAGOFF) {
+                fsv_imagoff<VC>(x0r, x0i, x1r, x1i, M.m0r, M.m1i, M.m2i, M.m3r);
+            } else if constexpr (FORM == FSV_ANTI) {  // y0 = m1 x1, y1 = m2 x0
+                fsv_swap(x0r, x1r);
+                fsv_swap(x0i, x1i);
+                fsv_cmul<VC>(x0r, x0i, M.m1r, M.m1i);
+                fsv_cmul<VC>(x1r, x1i, M.m2r, M.m2i);
+            } else if constexpr (FORM == FSV_XSWAP) {
+                fsv_swap(x0r, x1r);
+                fsv_swap(x0i, x1i);
+            } else {
+                fsv_cplx<VC>(x0r, x0i, x1r, x1i, M);
+            }
+            ar[r0] = x0r;
+            ai[r0] = x0i;
+            ar[r1] = x1r;
+            ai[r1] = x1i;
+        }
+    });
+}
+
+// X on register bit RB in the lanes whose bit is set in mask (a control on a
+// lane index bit; exact).
+template <int RB>
+__device__ __forceinline__ void fsv_xswap_lanes(f32x16& ar, f32x16& ai, uint64_t mask) {
+    fsv_for16([&](auto I_) {
+        constexpr int r0 = decltype(I_)::value;
+        if constexpr (((r0 >> RB) & 1) == 0) {
+            constexpr int r1 = r0 | (1 << RB);
+            float x0r = ar[r0], x0i = ai[r0], x1r = ar[r1], x1i = ai[r1];
+            fsv_cswap(x0r, x1r, mask);
+            fsv_cswap(x0i, x1i, mask);
+            ar[r0] = x0r;
+            ai[r0] = x0i;
+            ar[r1] = x1r;
+            ai[r1] = x1i;
+        }
+    });
+}
+
+// Register control cp (compile-time cases) for the forms that allow it.
+template <int RB, int FORM>
+__device__ __forceinline__ void fsv_pairs_cp(f32x16& ar, f32x16& ai, const Mat2& M, int cp) {
+    switch (cp) {
+        case 0: if constexpr (RB != 0) fsv_pairs<RB, 0, FORM, false>(ar, ai, M); break;
+        case 1: if constexpr (RB != 1) fsv_pairs<RB, 1, FORM, false>(ar, ai, M); break;
+        case 2: if constexpr (RB != 2) fsv_pairs<RB, 2, FORM, false>(ar, ai, M); break;
+        default: if constexpr (RB != 3) fsv_pairs<RB, 3, FORM, false>(ar, ai, M); break;
+    }
+}
+
+// A non-diagonal 2x2 on register bit RB: control on register bit cp (>= 0),
+// on a lane bit (lane_ctrl, on in this lane when lane_on), or none.
+template <int RB>
+__device__ __forceinline__ void fsv_general_rb(f32x16& ar, f32x16& ai, const Mat2& M, int form, int cp,
+                                               bool lane_ctrl, bool lane_on) {
+    if (cp >= 0) {
+        // ANTI and IMAGOFF under a register control take the general arithmetic
+        if (form == FSV_XSWAP)
+            fsv_pairs_cp<RB, FSV_XSWAP>(ar, ai, M, cp);
+        else if (form == FSV_REAL)
+            fsv_pairs_cp<RB, FSV_REAL>(ar, ai, M, cp);
+        else
+            fsv_pairs_cp<RB, FSV_COMPLEX>(ar, ai, M, cp);
+        return;
+    }
+    if (lane_ctrl) {
+        if (form == FSV_XSWAP) {
+            fsv_xswap_lanes<RB>(ar, ai, __builtin_amdgcn_ballot_w64(lane_on));
+            return;
+        }
+        // lanes whose control bit is 0 apply the identity (exact: products
+        // with 1 and 0); the identity is REAL and IMAGOFF, not ANTI
+        Mat2 L;
+        L.m0r = lane_on ? M.m0r : 1.f;
+        L.m0i = lane_on ? M.m0i : 0.f;
+        L.m1r = lane_on ? M.m1r : 0.f;
+        L.m1i = lane_on ? M.m1i : 0.f;
+        L.m2r = lane_on ? M.m2r : 0.f;
+        L.m2i = lane_on ? M.m2i : 0.f;
+        L.m3r = lane_on ? M.m3r : 1.f;
+        L.m3i = lane_on ? M.m3i : 0.f;
+        if (form == FSV_REAL)
+            fsv_pairs<RB, -1, FSV_REAL, true>(ar, ai, L);
+        else if (form == FSV_IMAGOFF)
+            fsv_pairs<RB, -1, FSV_IMAGOFF, true>(ar, ai, L);
+        else
+            fsv_pairs<RB, -1, FSV_COMPLEX, true>(ar, ai, L);
+        return;
+    }
+    switch (form) {
+        case FSV_XSWAP: fsv_pairs<RB, -1, FSV_XSWAP, false>(ar, ai, M); break;
+        case FSV_REAL: fsv_pairs<RB, -1, FSV_REAL, false>(ar, ai, M); break;
+        case FSV_ANTI: fsv_pairs<RB, -1, FSV_ANTI, false>(ar, ai, M); break;
+        case FSV_IMAGOFF: fsv_pairs<RB, -1, FSV_IMAGOFF, false>(ar, ai, M); break;
+        default: fsv_pairs<RB, -1, FSV_COMPLEX, false>(ar, ai, M); break;
+    }
 }
 
 // A run of diagonal operations on local qubits, multiplied out on the host:
 // amplitude j (local index) times tab[j].
-__device__ __forceinline__ void fsv_table(f32x16& ar_out, f32x16& ai_out, const float* __restrict__ tab, int jt,
-                                          int sh) {
-    f32x16 ar = ar_out, ai = ai_out;  // value copies: the caller sees whole-vector accesses only
+__device__ __forceinline__ void fsv_table(f32x16& ar, f32x16& ai, const float* __restrict__ tab, int jt, int sh) {
     fsv_for16([&](auto I_) {
         constexpr int r = decltype(I_)::value;
         const int j = jt | (r << sh);
         const float2 f = *reinterpret_cast<const float2*>(tab + 2 * j);
-        cmul_at(ar, ai, r, f.x, f.y);
+        float xr = ar[r], xi = ai[r];
+        fsv_cmul<true>(xr, xi, f.x, f.y);
+        ar[r] = xr;
+        ai[r] = xi;
     });
-    ar_out = ar;
-    ai_out = ai;
 }
 
 // Registers whose bit P is set (or all, P < 0) times the per-lane factor f.
 template <int P>
-__device__ __forceinline__ void fsv_scale(f32x16& ar_out, f32x16& ai_out, float fr, float fi) {
-    f32x16 ar = ar_out, ai = ai_out;  // value copies: the caller sees whole-vector accesses only
+__device__ __forceinline__ void fsv_scale(f32x16& ar, f32x16& ai, float fr, float fi) {
     fsv_for16([&](auto I_) {
         constexpr int r = decltype(I_)::value;
-        if constexpr (P >= 0) {
-            if (!((r >> P) & 1)) return;
+        if constexpr (P < 0 || ((r >> P) & 1) == 1) {
+            float xr = ar[r], xi = ai[r];
+            fsv_cmul<true>(xr, xi, fr, fi);
+            ar[r] = xr;
+            ai[r] = xi;
         }
-        cmul_at(ar, ai, r, fr, fi);
     });
-    ar_out = ar;
-    ai_out = ai;
 }
 
-// Registers with bit CP set (all if CP < 0) times d1 where bit TP is set, else d0
-// (d0 skipped when it is exactly 1).
-template <int TP, int CP>
-__device__ __forceinline__ void fsv_diag_reg(f32x16& ar_out, f32x16& ai_out, float d0r, float d0i, float d1r,
-                                             float d1i, bool d0_one) {
-    f32x16 ar = ar_out, ai = ai_out;  // value copies: the caller sees whole-vector accesses only
+// Registers with bit CP set (all if CP < 0) times d1 where bit TP is set, else
+// d0 (D0 false: d0 is exactly 1 and is skipped).
+template <int TP, int CP, bool D0>
+__device__ __forceinline__ void fsv_diag_reg(f32x16& ar, f32x16& ai, float d0r, float d0i, float d1r, float d1i) {
     fsv_for16([&](auto I_) {
         constexpr int r = decltype(I_)::value;
-        if constexpr (CP >= 0) {
-            if (!((r >> CP) & 1)) return;
+        if constexpr (CP < 0 || ((r >> CP) & 1) == 1) {
+            float xr = ar[r], xi = ai[r];
+            if constexpr (((r >> TP) & 1) == 1)
+                fsv_cmul<true>(xr, xi, d1r, d1i);
+            else if constexpr (D0)
+                fsv_cmul<true>(xr, xi, d0r, d0i);
+            ar[r] = xr;
+            ai[r] = xi;
         }
-        if ((r >> TP) & 1)
-            cmul_at(ar, ai, r, d1r, d1i);
-        else if (!d0_one)
-            cmul_at(ar, ai, r, d0r, d0i);
     });
-    ar_out = ar;
-    ai_out = ai;
 }
 
-__device__ __forceinline__ void fsv_flush(f32x16& ar, f32x16& ai, float& lpr, float& lpi, bool& pending) {
-    if (pending) {
-        fsv_scale<-1>(ar, ai, lpr, lpi);
-        lpr = 1.f;
-        lpi = 0.f;
-        pending = false;
+// Applies the pending per-lane phase to all 16 registers (unconditionally:
+// a phase of exactly 1 leaves every amplitude bit-identical).
+__device__ __forceinline__ void fsv_flush(f32x16& ar, f32x16& ai, float& lpr, float& lpi) {
+    fsv_scale<-1>(ar, ai, lpr, lpi);
+    lpr = 1.f;
+    lpi = 0.f;
+}
+
+template <int TP, bool D0>
+__device__ __forceinline__ void fsv_diag_tp_d(f32x16& ar, f32x16& ai, int cp, float d0r, float d0i, float d1r,
+                                              float d1i) {
+    switch (cp) {
+        case 0: if constexpr (TP != 0) fsv_diag_reg<TP, 0, D0>(ar, ai, d0r, d0i, d1r, d1i); break;
+        case 1: if constexpr (TP != 1) fsv_diag_reg<TP, 1, D0>(ar, ai, d0r, d0i, d1r, d1i); break;
+        case 2: if constexpr (TP != 2) fsv_diag_reg<TP, 2, D0>(ar, ai, d0r, d0i, d1r, d1i); break;
+        case 3: if constexpr (TP != 3) fsv_diag_reg<TP, 3, D0>(ar, ai, d0r, d0i, d1r, d1i); break;
+        default: fsv_diag_reg<TP, -1, D0>(ar, ai, d0r, d0i, d1r, d1i); break;
     }
 }
-
 template <int TP>
 __device__ __forceinline__ void fsv_diag_tp(f32x16& ar, f32x16& ai, int cp, float d0r, float d0i, float d1r,
                                             float d1i, bool d0_one) {
-    switch (cp) {
-        case 0: if constexpr (TP != 0) fsv_diag_reg<TP, 0>(ar, ai, d0r, d0i, d1r, d1i, d0_one); break;
-        case 1: if constexpr (TP != 1) fsv_diag_reg<TP, 1>(ar, ai, d0r, d0i, d1r, d1i, d0_one); break;
-        case 2: if constexpr (TP != 2) fsv_diag_reg<TP, 2>(ar, ai, d0r, d0i, d1r, d1i, d0_one); break;
-        case 3: if constexpr (TP != 3) fsv_diag_reg<TP, 3>(ar, ai, d0r, d0i, d1r, d1i, d0_one); break;
-        default: fsv_diag_reg<TP, -1>(ar, ai, d0r, d0i, d1r, d1i, d0_one); break;
-    }
+    if (d0_one)
+        fsv_diag_tp_d<TP, false>(ar, ai, cp, d0r, d0i, d1r, d1i);
+    else
+        fsv_diag_tp_d<TP, true>(ar, ai, cp, d0r, d0i, d1r, d1i);
 }
 
 // A dense operation on local bits lb .. lb+w-1: out[j] = sum_s M[row(j)][s] in[j with
@@ -478,7 +532,6 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
                                                       const float* __restrict__ pool, float* __restrict__ re,
                                                       float* __restrict__ im) {
     __shared__ float s_re[1 << kFsvLocal], s_im[1 << kFsvLocal];
-    __shared__ FsvGate s_ops[kFsvMaxOps];
     const int t = threadIdx.x;
 
     // Global index of local index 0: the workgroup number with zero bits
@@ -505,32 +558,6 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
     const bool full = n >= kFsvLocal;
     const int nloc = full ? (1 << kFsvLocal) : (1 << n);
 
-    // Stage the pass's operation records in LDS once per workgroup: every
-    // thread then reads each record at LDS latency instead of a scalar-cache miss.
-    // A grouped-diagonal record holds a table over some non-local qubits: this
-    // workgroup's entry turns it into a plain diagonal record on its local bit
-    // (no local bit: d0 = d1, the same factor whatever bit it reads).
-    const int nops = p.g1 - p.g0;
-    const uint32_t base_lo = (uint32_t)base, base_hi = (uint32_t)(base >> 32);
-    for (int r = t; r < nops; r += 256) {
-        FsvGate o = gates[p.g0 + r];
-        if (o.kind == FSV_PHASE) {
-            int idx = 0;
-            for (int b = 0; b < o.width; ++b) {
-                const int q = (o.tglob >> (6 * b)) & 63;
-                idx |= (int)(((q < 32 ? base_lo >> q : base_hi >> (q - 32))) & 1u) << b;
-            }
-            const float4 e = *reinterpret_cast<const float4*>(pool + o.moff + 4 * idx);
-            o.m[0] = e.x;
-            o.m[1] = e.y;
-            o.m[6] = e.z;
-            o.m[7] = e.w;
-            o.kind = FSV_DIAG;
-            if (o.tloc < 0) o.tglob = 0;
-        }
-        s_ops[r] = o;
-    }
-    __syncthreads();
     f32x16 ar, ai;
     fsv_for16([&](auto I_) {
         constexpr int r = decltype(I_)::value;
@@ -549,47 +576,59 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
     });
 
     // Diagonal factors that depend only on this lane's index bits (and the
-    // workgroup's) are gathered into one per-lane phase and applied to all 16
-    // registers only when the layout changes, a non-diagonal operation comes,
-    // or the pass ends.
+    // workgroup's) are gathered into one per-lane phase.  A factor common to a
+    // lane's 16 registers commutes with every operation that acts within the
+    // current layout (they are linear maps on those 16 values), so the phase is
+    // applied only when amplitudes move between lanes (a layout change, SWAP,
+    // a dense operation) and when the pass ends.
     float lpr = 1.f, lpi = 0.f;
-    bool lp_pending = false;
 
+    // Operation records are read with scalar loads (uniform addresses), so
+    // every field and coefficient is an SGPR; the next record is requested
+    // while the current one executes.
+    const int nops = p.g1 - p.g0;
+    const FsvGate* __restrict__ ops = gates + p.g0;
     int cur = 2;
-    // The next record is read from LDS while the current one executes.
-    FsvGate nxt = nops > 0 ? s_ops[0] : FsvGate{};
+    FsvGate nxt = nops > 0 ? ops[0] : FsvGate{};
     for (int gi = 0; gi < nops; ++gi) {
-        FsvGate g;
-        g.kind = __builtin_amdgcn_readfirstlane(nxt.kind);
-        g.tloc = __builtin_amdgcn_readfirstlane(nxt.tloc);
-        g.tglob = __builtin_amdgcn_readfirstlane(nxt.tglob);
-        g.cloc = __builtin_amdgcn_readfirstlane(nxt.cloc);
-        g.cglob = __builtin_amdgcn_readfirstlane(nxt.cglob);
-        g.width = __builtin_amdgcn_readfirstlane(nxt.width);
-        g.moff = __builtin_amdgcn_readfirstlane(nxt.moff);
-        g.real = __builtin_amdgcn_readfirstlane(nxt.real);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) g.m[k] = nxt.m[k];
-        if (gi + 1 < nops) nxt = s_ops[gi + 1];
+        FsvGate g = nxt;
+        if (gi + 1 < nops) nxt = ops[gi + 1];
         if (g.cglob >= 0 && !((base >> g.cglob) & 1)) continue;  // non-local control is 0 here
+        if (g.kind == FSV_PHASE) {
+            // A grouped-diagonal record holds a table over some non-local
+            // qubits: this workgroup's entry makes it a plain diagonal on its
+            // local bit (no local bit: d0 = d1, the same factor whatever bit it reads).
+            int idx = 0;
+            for (int b = 0; b < g.width; ++b) {
+                const int q = (g.tglob >> (6 * b)) & 63;
+                idx |= (int)((base >> q) & 1) << b;
+            }
+            const float4 e = *reinterpret_cast<const float4*>(pool + g.moff + 4 * idx);
+            g.m[0] = e.x;
+            g.m[1] = e.y;
+            g.m[6] = e.z;
+            g.m[7] = e.w;
+            g.kind = FSV_DIAG;
+            if (g.tloc < 0) g.tglob = 0;
+        }
         if (g.kind == FSV_TABLE) {
             fsv_table(ar, ai, pool + g.moff, fsv_thread_bits(t, cur), 4 * cur);
             continue;
         }
         if (g.kind == FSV_DENSE) {
-            fsv_flush(ar, ai, lpr, lpi, lp_pending);
+            fsv_flush(ar, ai, lpr, lpi);
             fsv_dense(ar, ai, t, cur, g, pool, s_re, s_im);
             continue;
         }
         if (g.kind == FSV_SWAP) {
-            fsv_flush(ar, ai, lpr, lpi, lp_pending);
+            fsv_flush(ar, ai, lpr, lpi);
             fsv_swap_bits(ar, ai, t, cur, g.tloc, g.cloc, s_re, s_im);
             continue;
         }
         if (g.kind == FSV_GENERAL) {
             const int k = g.tloc >> 2;
-            fsv_flush(ar, ai, lpr, lpi, lp_pending);
             if (k != cur) {
+                fsv_flush(ar, ai, lpr, lpi);
                 fsv_relayout(ar, ai, t, cur, k, s_re, s_im);
                 cur = k;
             }
@@ -631,8 +670,9 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
             const bool on = lane_on;
             const float fr = on ? (tval ? d1r : d0r) : 1.f;
             const float fi = on ? (tval ? d1i : d0i) : 0.f;
-            cmul(lpr, lpi, fr, fi);
-            lp_pending = true;
+            const float pr = fmaf(fr, lpr, -fi * lpi), pi = fmaf(fr, lpi, fi * lpr);
+            lpr = pr;
+            lpi = pi;
         } else if (tp < 0) {
             // control on register bit cp: those registers times d_tval
             const float fr = tval ? d1r : d0r, fi = tval ? d1i : d0i;
@@ -655,7 +695,7 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
             }
         }
     }
-    fsv_flush(ar, ai, lpr, lpi, lp_pending);
+    fsv_flush(ar, ai, lpr, lpi);
     if (cur != 2) fsv_relayout(ar, ai, t, cur, 2, s_re, s_im);
 
     // The thread's offset again (recomputed rather than kept in two registers

@@ -16,7 +16,10 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kChains = 4;  // independent accumulators per wave
+// independent accumulators per wave: four for the 32x32 shapes; the 16x16x4
+// float64 MFMA needs eight to keep its pipeline full
+template <int KIND>
+constexpr int chains() { return KIND == 3 ? 8 : 4; }
 constexpr int kProbeBlocks = 2048;
 constexpr int kProbeThreads = 256;
 
@@ -38,6 +41,7 @@ __device__ __forceinline__ float probe_f32(bool rnd, uint32_t seed) {
 
 template <int KIND>
 __global__ __launch_bounds__(kProbeThreads) void mfma_probe_kernel(int iters, int rnd, float* __restrict__ sink) {
+    constexpr int kChains = chains<KIND>();
     const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
     float total = 0.f;
     if constexpr (KIND == 0) {  // v_mfma_f32_32x32x2f32
@@ -86,8 +90,8 @@ __global__ __launch_bounds__(kProbeThreads) void mfma_probe_kernel(int iters, in
         doublex4 acc[kChains];
 #pragma unroll
         for (int c = 0; c < kChains; ++c) {
-            a[c] = (double)probe_f32(rnd, gid * 8 + c);
-            b[c] = (double)probe_f32(rnd, gid * 8 + 4 + c);
+            a[c] = (double)probe_f32(rnd, gid * 16 + c);
+            b[c] = (double)probe_f32(rnd, gid * 16 + 8 + c);
             for (int e = 0; e < 4; ++e) acc[c][e] = 0.0;
         }
         for (int it = 0; it < iters; ++it)
@@ -100,7 +104,9 @@ __global__ __launch_bounds__(kProbeThreads) void mfma_probe_kernel(int iters, in
 }
 
 // Streaming copy, 16 bytes per load and store, grid-stride; each thread has
-// up to four loads in flight before it stores.
+// up to four loads in flight before it stores (non-temporal: the copy streams
+// through and should not displace cached data; measured fastest with 128
+// workgroups per CU).
 __global__ __launch_bounds__(256) void copy_probe_kernel(const floatx4* __restrict__ src, floatx4* __restrict__ dst,
                                                          size_t n16) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -151,7 +157,7 @@ qsim_status qsim_probe_mfma(qsim_ctx* ctx, int kind, int random_operands, double
     if (g.err != hipSuccess) return device_fail("hipSetDevice", g.err);
     hipStream_t st = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-    const int iters = kind == 0 ? 512 : 1024;
+    const int iters = kind == 0 ? 512 : kind == 3 ? 512 : 1024;
     const int rnd = random_operands ? 1 : 0;
     // one float per workgroup, in the context's scratch (far larger than kProbeBlocks floats)
     float* sink = reinterpret_cast<float*>(ctx->d_scratch);
@@ -171,7 +177,8 @@ qsim_status qsim_probe_mfma(qsim_ctx* ctx, int kind, int random_operands, double
     if (st) (void)hipStreamDestroy(st);
     if (e != hipSuccess) return device_fail("mfma probe", e);
     const double waves = (double)kProbeBlocks * kProbeThreads / 64.0;
-    *tflops_out = waves * iters * kChains * kMfmaFlops[kind] / (ms * 1e-3) / 1e12;
+    const int nchains = kind == 3 ? chains<3>() : chains<0>();
+    *tflops_out = waves * iters * nchains * kMfmaFlops[kind] / (ms * 1e-3) / 1e12;
     return ok();
 }
 
@@ -196,7 +203,7 @@ qsim_status qsim_probe_copy(qsim_ctx* ctx, const void* d_src, void* d_dst, size_
     float ms = 0.f;
     if (e == hipSuccess) {
         e = time_ms(st, 10, [&] {
-            hipLaunchKernelGGL(copy_probe_kernel, dim3(cus * 8), dim3(256), 0, st,
+            hipLaunchKernelGGL(copy_probe_kernel, dim3(cus * 128), dim3(256), 0, st,
                                static_cast<const floatx4*>(d_src), static_cast<floatx4*>(d_dst), n16);
             return hipGetLastError();
         }, &ms);
