@@ -424,8 +424,8 @@ def measure_peaks(B, ctx, torch, copy_mib: int):
             del a, b
     torch.cuda.empty_cache()
     out["library_gemm_tflops"] = lib
-    out["method"] = ("MFMA: 2048 workgroups x 256 threads, four independent accumulator chains per wave, "
-                     "flops = 2 x M x N x K per instruction; random operands toggle their mantissa bits. "
+    out["method"] = ("MFMA: 2048 workgroups x 256 threads, four independent accumulator chains per wave "
+                     "(eight for f64), flops = 2 x M x N x K per instruction; random operands toggle their mantissa bits. "
                      "library_gemm_tflops: torch.matmul (hipBLASLt) on random m x m operands, events over the calls")
     return out
 

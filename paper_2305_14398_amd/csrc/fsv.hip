@@ -99,6 +99,7 @@ struct FsvPass {
     int32_t L;   // local bits 0..L-1 are qubits 0..L-1
     int32_t nh;  // local bits L..L+nh-1 are qubits high[0..nh-1], ascending
     int32_t high[kFsvMaxHigh];
+    int32_t pos[kFsvLocal];  // the qubit of each local bit (bits beyond L + nh: the bit itself)
     int32_t g0, g1;  // the pass's records in the plan's table
     int32_t op0, op1;  // the operations the pass covers
 };
@@ -114,14 +115,6 @@ __device__ __forceinline__ int fsv_swz(int j) { return j ^ ((j >> 6) & 15) ^ (((
 __device__ __forceinline__ int fsv_thread_bits(int t, int k) {
     const int s = 4 * k;
     return (t & ((1 << s) - 1)) | ((t >> s) << (s + 4));
-}
-
-__device__ __forceinline__ int fsv_pos(const FsvPass& p, int b) {
-    int q = b;
-#pragma unroll
-    for (int h = 0; h < kFsvMaxHigh; ++h)
-        if (h < p.nh && b == p.L + h) q = p.high[h];
-    return q;
 }
 
 // Form of a float32 2x2 (row-major (re, im)); exact tests on the rounded entries.
@@ -548,28 +541,32 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
         }
     }
     // Load/store layout 2: local bits 0-7 = thread index, 8-11 = register.
-    uint64_t gt = 0;
+    // A thread's part of the global index is a 32-bit byte offset (local bits
+    // 0-7 map to qubits below 30 whenever n <= 34: they are qubits 0-7 or the
+    // smallest of the six highest local qubits); each register adds a uniform
+    // part, so every access is a scalar base plus this one vector offset.
+    uint32_t gt = 0;
 #pragma unroll
-    for (int b = 0; b < 8; ++b)
-        if ((t >> b) & 1) gt |= (uint64_t)1 << fsv_pos(p, b);
-    uint64_t gh[4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) gh[b] = (uint64_t)1 << fsv_pos(p, 8 + b);
+    for (int b = 0; b < 8; ++b) gt |= (uint32_t)((t >> b) & 1) << p.pos[b];
+    const uint32_t off4 = gt << 2;
     const bool full = n >= kFsvLocal;
     const int nloc = full ? (1 << kFsvLocal) : (1 << n);
+    auto reg_base = [&](int r) {
+        uint64_t u = base;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            if ((r >> b) & 1) u |= (uint64_t)1 << p.pos[8 + b];
+        return u;
+    };
 
     f32x16 ar, ai;
     fsv_for16([&](auto I_) {
         constexpr int r = decltype(I_)::value;
-        const int j = t | (r << 8);
-        uint64_t g = base | gt;
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-            if ((r >> b) & 1) g |= gh[b];
-        float vr = 0.f, vi = 0.f;  // loaded into scalars: a conditional vector-element write would go to scratch
-        if (full || j < nloc) {
-            vr = re[g];
-            vi = im[g];
+        const uint64_t u = reg_base(r);
+        float vr = 0.f, vi = 0.f;
+        if (full || (t | (r << 8)) < nloc) {
+            vr = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(re + u) + off4);
+            vi = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(im + u) + off4);
         }
         ar[r] = vr;
         ai[r] = vi;
@@ -584,15 +581,14 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
     float lpr = 1.f, lpi = 0.f;
 
     // Operation records are read with scalar loads (uniform addresses), so
-    // every field and coefficient is an SGPR; the next record is requested
-    // while the current one executes.
+    // every field and coefficient is an SGPR.  (Requesting the next record
+    // ahead costs a 16-register copy per operation; the load latency is
+    // instead covered by the other waves on the SIMD.)
     const int nops = p.g1 - p.g0;
     const FsvGate* __restrict__ ops = gates + p.g0;
     int cur = 2;
-    FsvGate nxt = nops > 0 ? ops[0] : FsvGate{};
     for (int gi = 0; gi < nops; ++gi) {
-        FsvGate g = nxt;
-        if (gi + 1 < nops) nxt = ops[gi + 1];
+        FsvGate g = ops[gi];
         if (g.cglob >= 0 && !((base >> g.cglob) & 1)) continue;  // non-local control is 0 here
         if (g.kind == FSV_PHASE) {
             // A grouped-diagonal record holds a table over some non-local
@@ -698,26 +694,13 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
     fsv_flush(ar, ai, lpr, lpi);
     if (cur != 2) fsv_relayout(ar, ai, t, cur, 2, s_re, s_im);
 
-    // The thread's offset again (recomputed rather than kept in two registers
-    // through the operation loop; the empty asm keeps the compiler from reusing
-    // the first computation).
-    int t2 = t;
-    asm volatile("" : "+v"(t2));
-    uint64_t gt2 = 0;
-#pragma unroll
-    for (int b = 0; b < 8; ++b)
-        if ((t2 >> b) & 1) gt2 |= (uint64_t)1 << fsv_pos(p, b);
     fsv_for16([&](auto I_) {
         constexpr int r = decltype(I_)::value;
-        const int j = t | (r << 8);
-        uint64_t g = base | gt2;
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-            if ((r >> b) & 1) g |= gh[b];
+        const uint64_t u = reg_base(r);
         const float vr = ar[r], vi = ai[r];
-        if (full || j < nloc) {
-            re[g] = vr;
-            im[g] = vi;
+        if (full || (t | (r << 8)) < nloc) {
+            *reinterpret_cast<float*>(reinterpret_cast<char*>(re + u) + off4) = vr;
+            *reinterpret_cast<float*>(reinterpret_cast<char*>(im + u) + off4) = vi;
         }
     });
 }
@@ -1063,6 +1046,10 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
             std::sort(hs.begin(), hs.end());
             for (int h = 0; h < p.nh; ++h) p.high[h] = hs[h];
         }
+        // Local bits 6 and 7 are qubits 6, 7 or the two smallest of at least five
+        // ascending high qubits below n <= 34, so pos[0..7] < 30 and the kernel's
+        // per-thread byte offset fits 32 bits.
+        for (int b = 0; b < kFsvLocal; ++b) p.pos[b] = b < p.L ? b : (b < p.L + p.nh ? p.high[b - p.L] : b);
         p.op0 = executed;
         executed += (int)pass_ops.size();
         p.op1 = executed;

@@ -272,12 +272,23 @@ def _check_schedule(n, gates):
             assert 6 <= low <= 12 and len(highs) == 12 - low
             assert list(highs) == sorted(set(highs)) and all(low <= q < n for q in highs)
         local = set(range(low)) | set(highs)
+        # the pass kernel's per-thread byte offset is 32 bits: local bits 0-7 map to qubits below 30
+        bit_qubit = list(range(low)) + list(highs)
+        assert all(q < 30 for q in bit_qubit[:8]), (low, highs)
         for gi in order[first:first + cnt]:
             nm, qs, _ = gates[gi]
             need = () if nm in DIAGONAL else (qs if nm == "SWAP" or len(qs) == 1 else qs[1:])
             assert set(need) <= local, (nm, qs, low, highs)
     assert nxt == len(gates)
     return sched
+
+
+def test_fsv_schedule_high_local_bits():
+    # targets on the six highest qubits of 34 force them local with only the six low qubits: local bits 6
+    # and 7 are then qubits 28 and 29, the largest a thread index bit can map to
+    n = 34
+    sched = _check_schedule(n, [("H", (q,), None) for q in range(28, 34)])
+    assert sched[0][0] == 6 and sched[0][1] == tuple(range(28, 34))
 
 
 @pytest.mark.parametrize("n", [1, 5, 12, 13, 20, 34])
