@@ -100,6 +100,7 @@ struct FsvPass {
     int32_t nh;  // local bits L..L+nh-1 are qubits high[0..nh-1], ascending
     int32_t high[kFsvMaxHigh];
     int32_t pos[kFsvLocal];  // the qubit of each local bit (bits beyond L + nh: the bit itself)
+    int32_t wide;            // the pass holds a dense operation (both planes staged in LDS)
     int32_t g0, g1;  // the pass's records in the plan's table
     int32_t op0, op1;  // the operations the pass covers
 };
@@ -470,42 +471,36 @@ __device__ __forceinline__ void fsv_dense(f32x16& ar_out, f32x16& ai_out, int t,
     ai_out = ai;
 }
 
-// Layout change cur -> k through LDS.
-__device__ __forceinline__ void fsv_relayout(f32x16& ar_out, f32x16& ai_out, int t, int cur, int k, float* s_re,
-                                             float* s_im) {
-    f32x16 ar = ar_out, ai = ai_out;  // value copies: the caller sees whole-vector accesses only
+// Layout change cur -> k of one plane through the LDS buffer s (one plane,
+// 16 KiB: the two planes go through it in turn, which keeps a workgroup's LDS
+// at 16 KiB and lets seven workgroups share a CU).
+__device__ __forceinline__ void fsv_relayout_plane(f32x16& x, int t, int cur, int k, float* s) {
     __syncthreads();  // earlier readers of the buffer are done
     const int jt = fsv_thread_bits(t, cur), sh = 4 * cur;
     fsv_for16([&](auto I_) {
         constexpr int r = decltype(I_)::value;
-        const int a = fsv_swz(jt | (r << sh));
-        s_re[a] = ar[r];
-        s_im[a] = ai[r];
+        s[fsv_swz(jt | (r << sh))] = x[r];
     });
     __syncthreads();
     const int jn = fsv_thread_bits(t, k), shn = 4 * k;
     fsv_for16([&](auto I_) {
         constexpr int r = decltype(I_)::value;
-        const int a = fsv_swz(jn | (r << shn));
-        ar[r] = s_re[a];
-        ai[r] = s_im[a];
+        x[r] = s[fsv_swz(jn | (r << shn))];
     });
-    ar_out = ar;
-    ai_out = ai;
+}
+__device__ __forceinline__ void fsv_relayout(f32x16& ar, f32x16& ai, int t, int cur, int k, float* s) {
+    fsv_relayout_plane(ar, t, cur, k, s);
+    fsv_relayout_plane(ai, t, cur, k, s);
 }
 
-// SWAP of local bits a and b: one LDS round trip in the current layout, each
-// amplitude read back from the index with those two bits exchanged.
-__device__ __forceinline__ void fsv_swap_bits(f32x16& ar_out, f32x16& ai_out, int t, int cur, int a, int b,
-                                              float* s_re, float* s_im) {
-    f32x16 ar = ar_out, ai = ai_out;  // value copies: the caller sees whole-vector accesses only
+// SWAP of local bits a and b: per plane one LDS round trip in the current
+// layout, each amplitude read back from the index with those two bits exchanged.
+__device__ __forceinline__ void fsv_swap_plane(f32x16& x, int t, int cur, int a, int b, float* s) {
     __syncthreads();  // earlier readers of the buffer are done
     const int jt = fsv_thread_bits(t, cur), sh = 4 * cur;
     fsv_for16([&](auto I_) {
         constexpr int r = decltype(I_)::value;
-        const int a_ = fsv_swz(jt | (r << sh));
-        s_re[a_] = ar[r];
-        s_im[a_] = ai[r];
+        s[fsv_swz(jt | (r << sh))] = x[r];
     });
     __syncthreads();
     const int both = (1 << a) | (1 << b);
@@ -513,18 +508,21 @@ __device__ __forceinline__ void fsv_swap_bits(f32x16& ar_out, f32x16& ai_out, in
         constexpr int r = decltype(I_)::value;
         int j = jt | (r << sh);
         if (((j >> a) ^ (j >> b)) & 1) j ^= both;
-        const int a_ = fsv_swz(j);
-        ar[r] = s_re[a_];
-        ai[r] = s_im[a_];
+        x[r] = s[fsv_swz(j)];
     });
-    ar_out = ar;
-    ai_out = ai;
+}
+__device__ __forceinline__ void fsv_swap_bits(f32x16& ar, f32x16& ai, int t, int cur, int a, int b, float* s) {
+    fsv_swap_plane(ar, t, cur, a, b, s);
+    fsv_swap_plane(ai, t, cur, a, b, s);
 }
 
+// WIDE: the pass holds a dense operation, whose products need both planes in
+// LDS at once (32 KiB); other passes use one 16 KiB plane buffer.
+template <bool WIDE>
 __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const FsvGate* __restrict__ gates,
                                                       const float* __restrict__ pool, float* __restrict__ re,
                                                       float* __restrict__ im) {
-    __shared__ float s_re[1 << kFsvLocal], s_im[1 << kFsvLocal];
+    __shared__ float s_buf[(WIDE ? 2 : 1) << kFsvLocal];
     const int t = threadIdx.x;
 
     // Global index of local index 0: the workgroup number with zero bits
@@ -611,21 +609,23 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
             fsv_table(ar, ai, pool + g.moff, fsv_thread_bits(t, cur), 4 * cur);
             continue;
         }
-        if (g.kind == FSV_DENSE) {
-            fsv_flush(ar, ai, lpr, lpi);
-            fsv_dense(ar, ai, t, cur, g, pool, s_re, s_im);
+        if (g.kind == FSV_DENSE) {  // only in WIDE passes
+            if constexpr (WIDE) {
+                fsv_flush(ar, ai, lpr, lpi);
+                fsv_dense(ar, ai, t, cur, g, pool, s_buf, s_buf + (1 << kFsvLocal));
+            }
             continue;
         }
         if (g.kind == FSV_SWAP) {
             fsv_flush(ar, ai, lpr, lpi);
-            fsv_swap_bits(ar, ai, t, cur, g.tloc, g.cloc, s_re, s_im);
+            fsv_swap_bits(ar, ai, t, cur, g.tloc, g.cloc, s_buf);
             continue;
         }
         if (g.kind == FSV_GENERAL) {
             const int k = g.tloc >> 2;
             if (k != cur) {
                 fsv_flush(ar, ai, lpr, lpi);
-                fsv_relayout(ar, ai, t, cur, k, s_re, s_im);
+                fsv_relayout(ar, ai, t, cur, k, s_buf);
                 cur = k;
             }
         }
@@ -692,7 +692,7 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
         }
     }
     fsv_flush(ar, ai, lpr, lpi);
-    if (cur != 2) fsv_relayout(ar, ai, t, cur, 2, s_re, s_im);
+    if (cur != 2) fsv_relayout(ar, ai, t, cur, 2, s_buf);
 
     fsv_for16([&](auto I_) {
         constexpr int r = decltype(I_)::value;
@@ -1265,6 +1265,9 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
             k = e;
         }
         p.g1 = (int)table.size();
+        p.wide = 0;
+        for (int i = p.g0; i < p.g1; ++i)
+            if (table[i].kind == FSV_DENSE) p.wide = 1;
         passes.push_back(p);
     }
 }
@@ -1397,8 +1400,12 @@ qsim_status qsim_fsv_run(qsim_ctx* ctx, const qsim_fsv_plan* plan, void* d_psi, 
     const unsigned blocks = n > kFsvLocal ? 1u << (n - kFsvLocal) : 1u;
     for (const FsvPass& p : plan->passes) {
         hipError_t e = timed(ctx->prof, QSIM_PROFILE_FSV, hs, [&] {
-            hipLaunchKernelGGL(fsv_pass_kernel, dim3(blocks), dim3(256), 0, hs, n, p, plan->d_gates, plan->d_pool, re,
-                               im);
+            if (p.wide)
+                hipLaunchKernelGGL(fsv_pass_kernel<true>, dim3(blocks), dim3(256), 0, hs, n, p, plan->d_gates,
+                                   plan->d_pool, re, im);
+            else
+                hipLaunchKernelGGL(fsv_pass_kernel<false>, dim3(blocks), dim3(256), 0, hs, n, p, plan->d_gates,
+                                   plan->d_pool, re, im);
             return hipGetLastError();
         });
         if (e != hipSuccess) return device_fail("full-state pass launch", e);
