@@ -82,7 +82,7 @@ struct FsvGate {
     int32_t cglob;  // a non-local control qubit, or -1
     int32_t width;  // dense: qubits in the range; phase: non-local qubits of its table
     int32_t moff;   // dense / table / phase: offset of its float32 data in the plan's pool
-    int32_t real;   // general: the matrix's form (FSV_COMPLEX .. FSV_IMAGOFF), which fixes its arithmetic
+    int32_t real;   // general: the matrix's form (FSV_COMPLEX .. FSV_IPERM), which fixes its arithmetic
     float m[8];  // row-major 2x2 (re, im); a diagonal gate uses m[0..1] and m[6..7]
 };
 
@@ -92,8 +92,9 @@ struct FsvGate {
 //   FSV_REAL     every entry real (H, RY): 8;
 //   FSV_XSWAP    [[0, 1], [1, 0]] (X, the target of CNOT): an exact exchange;
 //   FSV_ANTI     [[0, b], [c, 0]] (Y, phases times X): 8;
-//   FSV_IMAGOFF  real diagonal, imaginary off-diagonal (RX): 8.
-enum : int32_t { FSV_COMPLEX = 0, FSV_REAL = 1, FSV_XSWAP = 2, FSV_ANTI = 3, FSV_IMAGOFF = 4 };
+//   FSV_IMAGOFF  real diagonal, imaginary off-diagonal (RX): 8;
+//   FSV_IPERM    [[0, -i], [i, 0]] (Y): exchanges and sign flips only, exact.
+enum : int32_t { FSV_COMPLEX = 0, FSV_REAL = 1, FSV_XSWAP = 2, FSV_ANTI = 3, FSV_IMAGOFF = 4, FSV_IPERM = 5 };
 
 struct FsvPass {
     int32_t L;   // local bits 0..L-1 are qubits 0..L-1
@@ -109,7 +110,22 @@ namespace {
 
 // Bank-spreading map of a local index to its LDS slot (a bijection on 0..4095
 // that only changes bits 0-5).
-__device__ __forceinline__ int fsv_swz(int j) { return j ^ ((j >> 6) & 15) ^ (((j >> 8) & 3) << 4); }
+__host__ __device__ constexpr int fsv_swz(int j) { return j ^ ((j >> 6) & 15) ^ (((j >> 8) & 3) << 4); }
+
+// The map is linear over XOR and register bits never overlap a thread's bits,
+// so a slot is the thread's part XOR a per-register constant: the byte offset
+// 4 fsv_swz(r << 4k) of register r in layout k, read from this table with
+// scalar loads (one XOR per LDS access instead of the whole map per access).
+struct FsvSwzTable {
+    int32_t v[3][16];
+};
+constexpr FsvSwzTable fsv_make_swz_table() {
+    FsvSwzTable t{};
+    for (int k = 0; k < 3; ++k)
+        for (int r = 0; r < 16; ++r) t.v[k][r] = 4 * fsv_swz(r << (4 * k));
+    return t;
+}
+__constant__ FsvSwzTable kFsvSwzReg = fsv_make_swz_table();
 
 // The local index bits a thread contributes in layout k (its 8 index bits
 // around the register nibble 4k..4k+3).
@@ -123,6 +139,7 @@ inline int fsv_form(const float m[8]) {
     const bool real = m[1] == 0.f && m[3] == 0.f && m[5] == 0.f && m[7] == 0.f;
     const bool anti = m[0] == 0.f && m[1] == 0.f && m[6] == 0.f && m[7] == 0.f;
     if (anti && real && m[2] == 1.f && m[4] == 1.f) return FSV_XSWAP;
+    if (anti && m[2] == 0.f && m[3] == -1.f && m[4] == 0.f && m[5] == 1.f) return FSV_IPERM;
     if (anti) return FSV_ANTI;
     if (real) return FSV_REAL;
     if (m[1] == 0.f && m[7] == 0.f && m[2] == 0.f && m[4] == 0.f) return FSV_IMAGOFF;
@@ -239,6 +256,8 @@ __device__ __forceinline__ void fsv_cplx(float& x0r, float& x0i, float& x1r, flo
 
 // Exact exchanges: always, or in the lanes whose bit is set in a uniform mask.
 __device__ __forceinline__ void fsv_swap(float& x0, float& x1) { asm("v_swap_b32 %0, %1" : "+v"(x0), "+v"(x1)); }
+// Exact sign flip.
+__device__ __forceinline__ void fsv_neg(float& x) { asm("v_xor_b32 %0, 0x80000000, %0" : "+v"(x)); }
 __device__ __forceinline__ void fsv_cswap(float& x0, float& x1, uint64_t mask) {
     float t;
     asm("v_mov_b32 %0, %1\n\t"
@@ -270,6 +289,12 @@ __device__ __forceinline__ void fsv_pairs(f32x16& ar, f32x16& ai, const Mat2& M)
             } else if constexpr (FORM == FSV_XSWAP) {
                 fsv_swap(x0r, x1r);
                 fsv_swap(x0i, x1i);
+            } else if constexpr (FORM == FSV_IPERM) {
+                // y0 = -i x1 = (x1i, -x1r),  y1 = i x0 = (-x0i, x0r)
+                fsv_swap(x0r, x1i);
+                fsv_swap(x0i, x1r);
+                fsv_neg(x0i);
+                fsv_neg(x1r);
             } else {
                 fsv_cplx<VC>(x0r, x0i, x1r, x1i, M);
             }
@@ -317,7 +342,7 @@ template <int RB>
 __device__ __forceinline__ void fsv_general_rb(f32x16& ar, f32x16& ai, const Mat2& M, int form, int cp,
                                                bool lane_ctrl, bool lane_on) {
     if (cp >= 0) {
-        // ANTI and IMAGOFF under a register control take the general arithmetic
+        // ANTI, IPERM and IMAGOFF under a register control take the general arithmetic
         if (form == FSV_XSWAP)
             fsv_pairs_cp<RB, FSV_XSWAP>(ar, ai, M, cp);
         else if (form == FSV_REAL)
@@ -332,7 +357,7 @@ __device__ __forceinline__ void fsv_general_rb(f32x16& ar, f32x16& ai, const Mat
             return;
         }
         // lanes whose control bit is 0 apply the identity (exact: products
-        // with 1 and 0); the identity is REAL and IMAGOFF, not ANTI
+        // with 1 and 0); the identity is REAL and IMAGOFF, not ANTI or IPERM
         Mat2 L;
         L.m0r = lane_on ? M.m0r : 1.f;
         L.m0i = lane_on ? M.m0i : 0.f;
@@ -354,6 +379,7 @@ __device__ __forceinline__ void fsv_general_rb(f32x16& ar, f32x16& ai, const Mat
         case FSV_XSWAP: fsv_pairs<RB, -1, FSV_XSWAP, false>(ar, ai, M); break;
         case FSV_REAL: fsv_pairs<RB, -1, FSV_REAL, false>(ar, ai, M); break;
         case FSV_ANTI: fsv_pairs<RB, -1, FSV_ANTI, false>(ar, ai, M); break;
+        case FSV_IPERM: fsv_pairs<RB, -1, FSV_IPERM, false>(ar, ai, M); break;
         case FSV_IMAGOFF: fsv_pairs<RB, -1, FSV_IMAGOFF, false>(ar, ai, M); break;
         default: fsv_pairs<RB, -1, FSV_COMPLEX, false>(ar, ai, M); break;
     }
@@ -361,11 +387,13 @@ __device__ __forceinline__ void fsv_general_rb(f32x16& ar, f32x16& ai, const Mat
 
 // A run of diagonal operations on local qubits, multiplied out on the host:
 // amplitude j (local index) times tab[j].
+// (Each entry's address is a scalar base for the register bits plus the
+// thread's byte offset.)
 __device__ __forceinline__ void fsv_table(f32x16& ar, f32x16& ai, const float* __restrict__ tab, int jt, int sh) {
+    const uint32_t off8 = (uint32_t)jt << 3;
     fsv_for16([&](auto I_) {
         constexpr int r = decltype(I_)::value;
-        const int j = jt | (r << sh);
-        const float2 f = *reinterpret_cast<const float2*>(tab + 2 * j);
+        const float2 f = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(tab + 2 * (r << sh)) + off8);
         float xr = ar[r], xi = ai[r];
         fsv_cmul<true>(xr, xi, f.x, f.y);
         ar[r] = xr;
@@ -475,17 +503,20 @@ __device__ __forceinline__ void fsv_dense(f32x16& ar_out, f32x16& ai_out, int t,
 // 16 KiB: the two planes go through it in turn, which keeps a workgroup's LDS
 // at 16 KiB and lets seven workgroups share a CU).
 __device__ __forceinline__ void fsv_relayout_plane(f32x16& x, int t, int cur, int k, float* s) {
+    char* sb = reinterpret_cast<char*>(s);
     __syncthreads();  // earlier readers of the buffer are done
-    const int jt = fsv_thread_bits(t, cur), sh = 4 * cur;
+    const uint32_t aw = 4 * fsv_swz(fsv_thread_bits(t, cur));
+    const int32_t* cw = kFsvSwzReg.v[cur];
     fsv_for16([&](auto I_) {
         constexpr int r = decltype(I_)::value;
-        s[fsv_swz(jt | (r << sh))] = x[r];
+        *reinterpret_cast<float*>(sb + (aw ^ cw[r])) = x[r];
     });
     __syncthreads();
-    const int jn = fsv_thread_bits(t, k), shn = 4 * k;
+    const uint32_t ar_ = 4 * fsv_swz(fsv_thread_bits(t, k));
+    const int32_t* cr = kFsvSwzReg.v[k];
     fsv_for16([&](auto I_) {
         constexpr int r = decltype(I_)::value;
-        x[r] = s[fsv_swz(jn | (r << shn))];
+        x[r] = *reinterpret_cast<const float*>(sb + (ar_ ^ cr[r]));
     });
 }
 __device__ __forceinline__ void fsv_relayout(f32x16& ar, f32x16& ai, int t, int cur, int k, float* s) {
@@ -498,9 +529,11 @@ __device__ __forceinline__ void fsv_relayout(f32x16& ar, f32x16& ai, int t, int 
 __device__ __forceinline__ void fsv_swap_plane(f32x16& x, int t, int cur, int a, int b, float* s) {
     __syncthreads();  // earlier readers of the buffer are done
     const int jt = fsv_thread_bits(t, cur), sh = 4 * cur;
+    const uint32_t aw = 4 * fsv_swz(jt);
+    const int32_t* cw = kFsvSwzReg.v[cur];
     fsv_for16([&](auto I_) {
         constexpr int r = decltype(I_)::value;
-        s[fsv_swz(jt | (r << sh))] = x[r];
+        *reinterpret_cast<float*>(reinterpret_cast<char*>(s) + (aw ^ cw[r])) = x[r];
     });
     __syncthreads();
     const int both = (1 << a) | (1 << b);
