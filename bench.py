@@ -381,7 +381,58 @@ def bench_fsv(B, ctx, torch, n: int, reps: int, which=("qft", "random_layers_20"
     out["workload"] = f"full-state-vector simulation of {n} qubits (planar complex64, {8 * N / 2**30:g} GiB), " \
                       f"in place from |0...0>; {reps} runs each"
     out["roofline"] = {"bound": "hbm", "peak": 8000.0, "unit": "GB/s",
-                       "traffic_model": "16 bytes per amplitude per pass (read + write of the state)"}
+                       "traffic_model": "16 bytes per amplitude per pass (read + write of the state)",
+                       "traffic": counted_traffic("fsv_pass_qft30_random30.md", "paper_2305_14398_amd/csrc/fsv.hip")
+                       if n == 30 else None,
+                       "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                       "note": "the pass streams exactly its algorithmic bytes; above the streaming floor its time "
+                               "is the issue of the per-operation VALU arithmetic and the scalar dispatch "
+                               "(rocprofv3 SQ counters per wave: see the full-state profile summary)"}
+    return out
+
+
+FSV_OP_CASES = {  # one pass of K copies of each (targets on local bits; the pass itself is fixed cost)
+    "H": lambda K: [("H", (0,), None)] * K,
+    "X": lambda K: [("X", (0,), None)] * K,
+    "Y": lambda K: [("Y", (0,), None)] * K,
+    "RX": lambda K: [("RX", (0,), 0.3)] * K,
+    "RY": lambda K: [("RY", (0,), 0.3)] * K,
+    "CNOT_register_control": lambda K: [("CNOT", (1, 0), None)] * K,
+    "CNOT_lane_control": lambda K: [("CNOT", (6, 0), None)] * K,
+    "CNOT_nonlocal_control": lambda K: [("CNOT", (20, 0), None)] * K,
+    "CY_lane_control": lambda K: [("CY", (6, 0), None)] * K,
+    "CNOT_alternating_layouts": lambda K: [("CNOT", (0, 4), None) if i % 2 == 0 else ("CNOT", (4, 0), None)
+                                           for i in range(K)],
+}
+
+
+def bench_fsv_op_costs(B, ctx, torch, n: int, K: int = 64, reps: int = 3):
+    """Marginal time of one full-state operation: a pass of K copies minus a pass of one, over K - 1.  Each case is
+    a single pass (its targets are local), so the difference is the operations' own cost (the layout changes
+    included for CNOT_alternating_layouts, whose consecutive targets sit in different register groups)."""
+    N = 1 << n
+    psi = torch.empty(2 * N, dtype=torch.float32, device=torch.device("cuda:0"))
+
+    def time_pass(gates):
+        with B.FsvPlan(ctx, n, gates) as plan:
+            assert plan.info()["passes"] == 1
+            B.qsim_fsv_init_basis(ctx, n, 0, psi)
+            plan.run(psi)
+            torch.cuda.synchronize()
+            B.qsim_profile_enable(ctx, 1)
+            for _ in range(reps):
+                plan.run(psi)
+            torch.cuda.synchronize()
+            launches, kernel_ms = B.qsim_profile_read(ctx)["fsv"]
+            B.qsim_profile_enable(ctx, 0)
+        return kernel_ms / launches
+
+    base = time_pass([("H", (0,), None)])
+    out = {"qubits": n, "copies": K, "one_op_pass_us": round(base * 1e3, 2)}
+    for name, make in FSV_OP_CASES.items():
+        out[name + "_us"] = round((time_pass(make(K)) - base) / (K - 1) * 1e3, 3)
+    del psi
+    torch.cuda.empty_cache()
     return out
 
 
@@ -547,6 +598,8 @@ def main() -> int:
     ap.add_argument("--fsv", type=int, default=30, help="qubits of the full-state-vector workload (0: skip)")
     ap.add_argument("--fsv-circuits", default="qft,random_layers_20")
     ap.add_argument("--fsv-reps", type=int, default=3)
+    ap.add_argument("--fsv-op-costs", type=int, default=26,
+                    help="qubits of the per-operation full-state cost cases (0: skip)")
     ap.add_argument("--sweep-qubits", default="12,13", help="qubit counts of the precision sweep ('' to skip)")
     ap.add_argument("--sweep-seeds", default="0,1,2,3,4", help="seeds of the precision sweep's random circuits")
     ap.add_argument("--sweep-precisions", default="fp32_4m,fp32_3m,split_bf16,split_fp16,split_bf16_3m,split_fp16_3m")
@@ -779,6 +832,15 @@ def main() -> int:
         out["full_state"] = bench_fsv(B, ctx, torch, args.fsv, reps=args.fsv_reps,
                                       which=[x for x in args.fsv_circuits.split(",") if x])
         progress("full-state done")
+    if "full_state" in out and "peaks" in out:
+        copy = out["peaks"]["hbm_copy"]["gb_per_s"]
+        for name in [x for x in args.fsv_circuits.split(",") if x]:
+            if name in out["full_state"]:
+                out["full_state"][name]["frac_of_measured_copy"] = round(
+                    out["full_state"][name]["hbm_gb_per_s"] / copy, 4)
+    if args.fsv_op_costs:
+        out.setdefault("full_state", {})["op_costs"] = bench_fsv_op_costs(B, ctx, torch, args.fsv_op_costs)
+        progress("full-state operation costs done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_seconds)
         progress("cpu baseline done")
