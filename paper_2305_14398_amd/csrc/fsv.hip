@@ -50,6 +50,7 @@ constexpr int kFsvMinLow = 6;     // low qubits always local: 64 lanes x 4 B con
 constexpr int kFsvMaxHigh = kFsvLocal - kFsvMinLow;
 constexpr int kFsvNormBlocks = 1024;
 constexpr int kFsvMaxOps = 256;   // operations per pass (a planning cap)
+constexpr int kFsvLaneRun = 5;    // longest run of operations applied across lanes instead of a layout change
 
 // A thread's 16 values of one plane: 16 scalars (every index is a compile-time
 // constant), so that each register is coalesced on its own.
@@ -80,8 +81,11 @@ struct FsvGate {
     int32_t tglob;  // the target qubit when it is not local (phase: up to 5 non-local qubits, 6 bits each)
     int32_t cloc;   // local bit of the control, or -1
     int32_t cglob;  // a non-local control qubit, or -1
-    int32_t width;  // dense: qubits in the range; phase: non-local qubits of its table
-    int32_t moff;   // dense / table / phase: offset of its float32 data in the plan's pool
+    int32_t width;  // dense: qubits in the range; phase: non-local qubits of its table;
+                    // general: 1 + the lane bit its target occupies when it is applied across
+                    // lanes in the current layout (0: its target is in the register group)
+    int32_t moff;   // dense / table / phase: offset of its float32 data in the plan's pool; general: 1 when the
+                    // pending per-lane phase must be applied first (a lane operation or a layout change)
     int32_t real;   // general: the matrix's form (FSV_COMPLEX .. FSV_IPERM), which fixes its arithmetic
     float m[8];  // row-major 2x2 (re, im); a diagonal gate uses m[0..1] and m[6..7]
 };
@@ -385,6 +389,120 @@ __device__ __forceinline__ void fsv_general_rb(f32x16& ar, f32x16& ai, const Mat
     }
 }
 
+// ---- Operations on a lane bit ----
+// A non-diagonal 2x2 whose target is one of the six lane bits of the current
+// layout is applied across lanes instead of after a layout change: each lane
+// holds one amplitude of every pair (its own) and reads the other from the
+// partner lane (lane id XOR 2^B), then forms its row of the product with
+// per-lane coefficients: lane bit s = 0 keeps y0 = m0 x + m1 p, s = 1 keeps
+// y1 = m3 x + m2 p (a lane whose control bit is 0 takes the identity row).
+
+// x in the partner lane: DPP inside a row of 16 lanes (bits 0-3; two moves for
+// bits 2 and 3: a mirror composed with a smaller one), ds_swizzle for bit 4,
+// ds_bpermute for bit 5.
+template <int B>
+__device__ __forceinline__ float fsv_partner(float x, int lane) {
+    const int v = __builtin_bit_cast(int, x);
+    int p;
+    if constexpr (B == 0)
+        p = __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);  // quad_perm [1,0,3,2]: lane ^ 1
+    else if constexpr (B == 1)
+        p = __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);  // quad_perm [2,3,0,1]: lane ^ 2
+    else if constexpr (B == 2)  // row_half_mirror (lane ^ 7), then quad_perm [3,2,1,0] (lane ^ 3)
+        p = __builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true), 0x1B, 0xF, 0xF, true);
+    else if constexpr (B == 3)  // row_mirror (lane ^ 15), then row_half_mirror (lane ^ 7)
+        p = __builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, true), 0x141, 0xF, 0xF, true);
+    else if constexpr (B == 4)
+        p = __builtin_amdgcn_ds_swizzle(v, 0x401F);  // bit-mask mode: and 0x1f, or 0, xor 0x10
+    else
+        p = __builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, v);
+    return __builtin_bit_cast(float, p);
+}
+
+// x <- a x + b p on one plane, a and b real per lane: x' = fma(a, x, b p)
+__device__ __forceinline__ void fsv_axbp(float& x, float p, float a, float b) {
+    float t;
+    asm("v_mul_f32 %0, %3, %2\n\t"
+        "v_fma_f32 %1, %4, %1, %0"
+        : "=&v"(t), "+v"(x)
+        : "v"(p), "v"(b), "v"(a));
+}
+
+// (xr, xi) <- a x + b p, complex a and b per lane:
+//   xr' = fma(ar, xr, fma(-ai, xi, fma(-bi, pi, br pr)))
+//   xi' = fma(ar, xi, fma( ai, xr, fma( bi, pr, br pi)))
+#define FSV_AXBP_C_ASM                 \
+    "v_mul_f32 %0, %8, %4\n\t"        \
+    "v_fma_f32 %0, -%9, %5, %0\n\t"   \
+    "v_fma_f32 %0, -%7, %3, %0\n\t"   \
+    "v_mul_f32 %1, %8, %5\n\t"        \
+    "v_fmac_f32 %1, %9, %4\n\t"       \
+    "v_fmac_f32 %1, %7, %2\n\t"       \
+    "v_fma_f32 %2, %6, %2, %0\n\t"    \
+    "v_fma_f32 %3, %6, %3, %1"
+__device__ __forceinline__ void fsv_axbp_c(float& xr, float& xi, float pr, float pi, const Mat2& c) {
+    float t1, t2;
+    asm(FSV_AXBP_C_ASM
+        : "=&v"(t1), "=&v"(t2), "+v"(xr), "+v"(xi)
+        : "v"(pr), "v"(pi), "v"(c.m0r), "v"(c.m0i), "v"(c.m1r), "v"(c.m1i));
+}
+
+// FORM FSV_XSWAP: an uncontrolled X (every lane takes its partner's value);
+// FSV_REAL: real per-lane coefficients (c.m0r, c.m1r); otherwise complex.
+template <int B, int FORM>
+__device__ __forceinline__ void fsv_lane_op(f32x16& ar, f32x16& ai, const Mat2& c, int lane) {
+    fsv_for16([&](auto I_) {
+        constexpr int r = decltype(I_)::value;
+        float xr = ar[r], xi = ai[r];
+        const float pr = fsv_partner<B>(xr, lane), pi = fsv_partner<B>(xi, lane);
+        if constexpr (FORM == FSV_XSWAP) {
+            xr = pr;
+            xi = pi;
+        } else if constexpr (FORM == FSV_REAL) {
+            fsv_axbp(xr, pr, c.m0r, c.m1r);
+            fsv_axbp(xi, pi, c.m0r, c.m1r);
+        } else {
+            fsv_axbp_c(xr, xi, pr, pi, c);
+        }
+        ar[r] = xr;
+        ai[r] = xi;
+    });
+}
+
+template <int FORM>
+__device__ __forceinline__ void fsv_lane_op_b(f32x16& ar, f32x16& ai, const Mat2& c, int lb, int lane) {
+    switch (lb) {
+        case 0: fsv_lane_op<0, FORM>(ar, ai, c, lane); break;
+        case 1: fsv_lane_op<1, FORM>(ar, ai, c, lane); break;
+        case 2: fsv_lane_op<2, FORM>(ar, ai, c, lane); break;
+        case 3: fsv_lane_op<3, FORM>(ar, ai, c, lane); break;
+        case 4: fsv_lane_op<4, FORM>(ar, ai, c, lane); break;
+        default: fsv_lane_op<5, FORM>(ar, ai, c, lane); break;
+    }
+}
+
+// A non-diagonal 2x2 M on lane bit lb; a control on a thread bit that is 0 in
+// this lane makes it the identity (exact: products with 1 and 0).
+__device__ __forceinline__ void fsv_lane_general(f32x16& ar, f32x16& ai, const Mat2& M, int form, int lb,
+                                                 bool lane_ctrl, bool lane_on, int lane) {
+    if (form == FSV_XSWAP && !lane_ctrl) {
+        fsv_lane_op_b<FSV_XSWAP>(ar, ai, M, lb, lane);
+        return;
+    }
+    const bool hi = (lane >> lb) & 1;  // this lane holds index bit 1 of the pair
+    const bool on = !lane_ctrl || lane_on;
+    Mat2 c;  // m0: the coefficient of the lane's own value, m1: of its partner's
+    c.m0r = on ? (hi ? M.m3r : M.m0r) : 1.f;
+    c.m0i = on ? (hi ? M.m3i : M.m0i) : 0.f;
+    c.m1r = on ? (hi ? M.m2r : M.m1r) : 0.f;
+    c.m1i = on ? (hi ? M.m2i : M.m1i) : 0.f;
+    c.m2r = c.m2i = c.m3r = c.m3i = 0.f;
+    if (form == FSV_REAL || form == FSV_XSWAP)
+        fsv_lane_op_b<FSV_REAL>(ar, ai, c, lb, lane);
+    else
+        fsv_lane_op_b<FSV_COMPLEX>(ar, ai, c, lb, lane);
+}
+
 // A run of diagonal operations on local qubits, multiplied out on the host:
 // amplitude j (local index) times tab[j].
 // (Each entry's address is a scalar base for the register bits plus the
@@ -654,10 +772,18 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
             fsv_swap_bits(ar, ai, t, cur, g.tloc, g.cloc, s_buf);
             continue;
         }
+        if (g.kind == FSV_GENERAL && g.width > 0) {  // target on a lane bit of the current layout
+            if (g.moff) fsv_flush(ar, ai, lpr, lpi);
+            const bool lane_ctrl = g.cloc >= 0;
+            const bool lane_on = lane_ctrl ? (fsv_thread_bits(t, cur) >> g.cloc) & 1 : true;
+            const Mat2 M = {g.m[0], g.m[1], g.m[2], g.m[3], g.m[4], g.m[5], g.m[6], g.m[7]};
+            fsv_lane_general(ar, ai, M, g.real, g.width - 1, lane_ctrl, lane_on, t & 63);
+            continue;
+        }
         if (g.kind == FSV_GENERAL) {
             const int k = g.tloc >> 2;
             if (k != cur) {
-                fsv_flush(ar, ai, lpr, lpi);
+                if (g.moff) fsv_flush(ar, ai, lpr, lpi);
                 fsv_relayout(ar, ai, t, cur, k, s_buf);
                 cur = k;
             }
@@ -1109,10 +1235,24 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
             std::copy(l.m, l.m + 8, d.m);
             return d;
         };
+        // The thread bit (0-5: a lane bit) that local bit lb occupies in register
+        // layout c, or -1 when lb is in the register group or a wave bit.
+        auto lane_bit = [](int lb, int c) {
+            const int tb = lb < 4 * c ? lb : (lb >= 4 * c + 4 ? lb - 4 : -1);
+            return tb >= 0 && tb < 6 ? tb : -1;
+        };
+        // A non-diagonal operation can run in layout c without a layout change
+        // when its target is in the register group, or on a lane bit and its
+        // control (if local) is not a register bit.
+        auto in_layout = [&](const LoweredGate& l, int c) {
+            const int tb = local_bit(l.tq), cb = local_bit(l.cq);
+            if ((tb >> 2) == c) return true;
+            return lane_bit(tb, c) >= 0 && !(cb >= 0 && (cb >> 2) == c);
+        };
         // Reorder the pass's operations where they commute (disjoint qubits, or
         // both diagonal) so that fewer layout changes are needed: ready
-        // diagonal and custom operations first, then non-diagonal ones in the
-        // current register layout, else the earliest ready one.
+        // diagonal and custom operations first, then non-diagonal ones that can
+        // run in the current register layout, else the earliest ready one.
         std::vector<size_t> order;
         {
             const size_t m = pass_ops.size();
@@ -1142,7 +1282,7 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
                         pick = (int)a;
                         break;
                     }
-                    if ((local_bit(l.tq) >> 2) == cur) {
+                    if (in_layout(l, cur)) {
                         if (pick < 0) pick = (int)a;
                     } else if (pick_general < 0) {
                         pick_general = (int)a;
@@ -1298,6 +1438,59 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
             k = e;
         }
         p.g1 = (int)table.size();
+        // Follow the kernel's register layout through the pass.  The order above
+        // groups operations into runs whose targets share a register group; a
+        // run of at most kFsvLaneRun operations that can all be applied across
+        // lanes in the current layout (targets on lane bits, no control in the
+        // register group) is, and keeps the layout, since a layout change costs
+        // about as much as five such operations; a longer run changes the layout.
+        {
+            int c = 2;
+            int i = p.g0;
+            while (i < p.g1) {
+                FsvGate& d = table[i];
+                if (d.kind != FSV_GENERAL || (d.tloc >> 2) == c) {
+                    ++i;
+                    continue;
+                }
+                const int k = d.tloc >> 2;
+                int e = i, count = 0;
+                bool lanes = true;
+                for (; e < p.g1; ++e) {
+                    const FsvGate& x = table[e];
+                    if (x.kind != FSV_GENERAL) continue;
+                    if ((x.tloc >> 2) != k) break;
+                    ++count;
+                    if (lane_bit(x.tloc, c) < 0 || (x.cloc >= 0 && (x.cloc >> 2) == c)) lanes = false;
+                }
+                if (lanes && count <= kFsvLaneRun) {
+                    for (int x = i; x < e; ++x)
+                        if (table[x].kind == FSV_GENERAL) table[x].width = lane_bit(table[x].tloc, c) + 1;
+                } else {
+                    c = k;
+                }
+                i = e;
+            }
+            // Which lane operations and layout changes must first apply the
+            // pending per-lane phase (moff = 1): those after a diagonal
+            // operation that the kernel folds into it (no register-group bit).
+            c = 2;
+            bool dirty = false;
+            for (int x = p.g0; x < p.g1; ++x) {
+                FsvGate& d = table[x];
+                if (d.kind == FSV_DIAG || d.kind == FSV_PHASE) {
+                    const bool tp = d.tloc >= 0 && (d.tloc >> 2) == c;
+                    const bool cr = d.cloc >= 0 && (d.cloc >> 2) == c;
+                    if (!tp && !cr) dirty = true;
+                } else if (d.kind == FSV_SWAP || d.kind == FSV_DENSE) {
+                    dirty = false;  // always applied before these
+                } else if (d.kind == FSV_GENERAL && (d.width > 0 || (d.tloc >> 2) != c)) {
+                    d.moff = dirty ? 1 : 0;
+                    dirty = false;
+                    if (d.width == 0) c = d.tloc >> 2;
+                }
+            }
+        }
         p.wide = 0;
         for (int i = p.g0; i < p.g1; ++i)
             if (table[i].kind == FSV_DENSE) p.wide = 1;
