@@ -738,7 +738,21 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
     int cur = 2;
     for (int gi = 0; gi < nops; ++gi) {
         FsvGate g = ops[gi];
-        if (g.cglob >= 0 && !((base >> g.cglob) & 1)) continue;  // non-local control is 0 here
+        const bool off = g.cglob >= 0 && !((base >> g.cglob) & 1);  // a non-local control is 0 here
+        if (g.kind == FSV_GENERAL) {
+            // The host planned the pass's layout changes and pending-phase
+            // applications for every workgroup alike, so they happen here even
+            // where a non-local control switches the operation itself off.
+            const int k = g.tloc >> 2;
+            if (g.width == 0 && k != cur) {
+                if (g.moff) fsv_flush(ar, ai, lpr, lpi);
+                fsv_relayout(ar, ai, t, cur, k, s_buf);
+                cur = k;
+            } else if (g.width > 0 && g.moff) {
+                fsv_flush(ar, ai, lpr, lpi);
+            }
+        }
+        if (off) continue;
         if (g.kind == FSV_PHASE) {
             // A grouped-diagonal record holds a table over some non-local
             // qubits: this workgroup's entry makes it a plain diagonal on its
@@ -773,20 +787,11 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
             continue;
         }
         if (g.kind == FSV_GENERAL && g.width > 0) {  // target on a lane bit of the current layout
-            if (g.moff) fsv_flush(ar, ai, lpr, lpi);
             const bool lane_ctrl = g.cloc >= 0;
             const bool lane_on = lane_ctrl ? (fsv_thread_bits(t, cur) >> g.cloc) & 1 : true;
             const Mat2 M = {g.m[0], g.m[1], g.m[2], g.m[3], g.m[4], g.m[5], g.m[6], g.m[7]};
             fsv_lane_general(ar, ai, M, g.real, g.width - 1, lane_ctrl, lane_on, t & 63);
             continue;
-        }
-        if (g.kind == FSV_GENERAL) {
-            const int k = g.tloc >> 2;
-            if (k != cur) {
-                if (g.moff) fsv_flush(ar, ai, lpr, lpi);
-                fsv_relayout(ar, ai, t, cur, k, s_buf);
-                cur = k;
-            }
         }
         const int jt = fsv_thread_bits(t, cur);
         // control: a register bit (cp >= 0), a lane bit, or none

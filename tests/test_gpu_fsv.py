@@ -299,3 +299,39 @@ def test_fsv_diagonal_runs_across_local_and_non_local_qubits(ctx, n):
     got, info = run_fsv(ctx, n, g, psi0)
     ref = fsv.final_state(n, g, psi0)
     assert np.linalg.norm(got - ref) <= bound(g), (np.linalg.norm(got - ref), bound(g), info)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_fsv_lane_operations_and_layout_runs(ctx, seed):
+    """Runs of one to seven non-diagonal operations aimed at one register group of the 12 local qubits, so that
+    the planner applies the short ones across lanes (every lane bit, DPP, swizzle and bpermute exchanges) and
+    changes the layout for the long ones; the real, exchange, Y and imaginary off-diagonal forms (the last two take
+    the general complex arithmetic across lanes), controls on a lane bit, a wave bit, a register bit and a
+    non-local qubit, and diagonal operations between and inside the runs (per-lane phase, register and table
+    forms), so pending phases meet both lane operations and layout changes."""
+    n = 14
+    rng = np.random.default_rng(1300 + seed)
+    forms = ("H", "X", "Y", "RX", "RY")
+    g = [("H", (q,), None) for q in range(n)]
+    for _ in range(40):
+        group = int(rng.integers(0, 3))
+        for _ in range(int(rng.integers(1, 8))):
+            t = 4 * group + int(rng.integers(0, 4))
+            nm = forms[int(rng.integers(0, len(forms)))]
+            kind = int(rng.integers(0, 5))
+            if kind == 0:  # uncontrolled
+                g.append((nm, (t,), float(rng.uniform(0, 2 * math.pi)) if nm in W.ANGLED else None))
+            else:
+                c = int(rng.choice([q for q in range(n) if q != t]))
+                two = {"X": "CNOT", "Y": "CY", "H": "CNOT", "RX": "CNOT", "RY": "CY"}[nm]
+                g.append((two, (c, t), None))
+            if rng.random() < 0.3:  # a phase on the target, then H on it again
+                g.append(("R", (t,), float(rng.uniform(0, 2 * math.pi))))
+                g.append(("H", (t,), None))
+        for _ in range(int(rng.integers(0, 3))):  # diagonals between runs (per-lane phase, register, table)
+            a, b = (int(x) for x in rng.choice(n, 2, replace=False))
+            g.append(("CR", (a, b), float(rng.uniform(0, 2 * math.pi))) if rng.random() < 0.5 else ("T", (a,), None))
+    psi0 = W.random_state(n, 40 + seed)
+    got, info = run_fsv(ctx, n, g, psi0)
+    ref = fsv.final_state(n, g, psi0)
+    assert np.linalg.norm(got - ref) <= bound(g), (np.linalg.norm(got - ref), bound(g), info)
