@@ -751,6 +751,33 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
             } else if (g.width > 0 && g.moff) {
                 fsv_flush(ar, ai, lpr, lpi);
             }
+            if (off) continue;
+            const Mat2 M = {g.m[0], g.m[1], g.m[2], g.m[3], g.m[4], g.m[5], g.m[6], g.m[7]};
+            const int jt = fsv_thread_bits(t, cur);
+            if (g.width > 0) {  // target on a lane bit of the current layout
+                const bool lane_ctrl = g.cloc >= 0;
+                const bool lane_on = lane_ctrl ? (jt >> g.cloc) & 1 : true;
+                fsv_lane_general(ar, ai, M, g.real, g.width - 1, lane_ctrl, lane_on, t & 63);
+                continue;
+            }
+            // control: a register bit (cp >= 0), a lane bit, or none
+            int cp = -1;
+            bool lane_ctrl = false, lane_on = true;
+            if (g.cloc >= 0) {
+                if ((g.cloc >> 2) == cur) {
+                    cp = g.cloc & 3;
+                } else {
+                    lane_ctrl = true;
+                    lane_on = (jt >> g.cloc) & 1;
+                }
+            }
+            switch (g.tloc & 3) {
+                case 0: fsv_general_rb<0>(ar, ai, M, g.real, cp, lane_ctrl, lane_on); break;
+                case 1: fsv_general_rb<1>(ar, ai, M, g.real, cp, lane_ctrl, lane_on); break;
+                case 2: fsv_general_rb<2>(ar, ai, M, g.real, cp, lane_ctrl, lane_on); break;
+                default: fsv_general_rb<3>(ar, ai, M, g.real, cp, lane_ctrl, lane_on); break;
+            }
+            continue;
         }
         if (off) continue;
         if (g.kind == FSV_PHASE) {
@@ -786,13 +813,6 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
             fsv_swap_bits(ar, ai, t, cur, g.tloc, g.cloc, s_buf);
             continue;
         }
-        if (g.kind == FSV_GENERAL && g.width > 0) {  // target on a lane bit of the current layout
-            const bool lane_ctrl = g.cloc >= 0;
-            const bool lane_on = lane_ctrl ? (fsv_thread_bits(t, cur) >> g.cloc) & 1 : true;
-            const Mat2 M = {g.m[0], g.m[1], g.m[2], g.m[3], g.m[4], g.m[5], g.m[6], g.m[7]};
-            fsv_lane_general(ar, ai, M, g.real, g.width - 1, lane_ctrl, lane_on, t & 63);
-            continue;
-        }
         const int jt = fsv_thread_bits(t, cur);
         // control: a register bit (cp >= 0), a lane bit, or none
         int cp = -1;
@@ -804,17 +824,6 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
                 lane_ctrl = true;
                 lane_on = (jt >> g.cloc) & 1;
             }
-        }
-        if (g.kind == FSV_GENERAL) {
-            const Mat2 M = {g.m[0], g.m[1], g.m[2], g.m[3], g.m[4], g.m[5], g.m[6], g.m[7]};
-            const int form = g.real;
-            switch (g.tloc & 3) {
-                case 0: fsv_general_rb<0>(ar, ai, M, form, cp, lane_ctrl, lane_on); break;
-                case 1: fsv_general_rb<1>(ar, ai, M, form, cp, lane_ctrl, lane_on); break;
-                case 2: fsv_general_rb<2>(ar, ai, M, form, cp, lane_ctrl, lane_on); break;
-                default: fsv_general_rb<3>(ar, ai, M, form, cp, lane_ctrl, lane_on); break;
-            }
-            continue;
         }
         // diagonal: target a register bit (tp >= 0), a lane bit or a workgroup bit
         const float d0r = g.m[0], d0i = g.m[1], d1r = g.m[6], d1i = g.m[7];
