@@ -78,15 +78,17 @@ constexpr int kFsvPhaseBits = 5;  // non-local qubits per FSV_PHASE table (2^5 e
 struct FsvGate {
     int32_t kind;
     int32_t tloc;   // local bit of the target (dense: of the range's lowest qubit), or -1 (diagonal only)
-    int32_t tglob;  // the target qubit when it is not local (phase: up to 5 non-local qubits, 6 bits each)
+    int32_t tglob;  // the target qubit when it is not local (phase: up to 5 non-local qubits, 6 bits each);
+                    // general: planned actions before it (bit 0: apply the pending per-lane phase,
+                    // bit 1: change to the target's register layout)
     int32_t cloc;   // local bit of the control, or -1
     int32_t cglob;  // a non-local control qubit, or -1
     int32_t width;  // dense: qubits in the range; phase: non-local qubits of its table;
                     // general: 1 + the lane bit its target occupies when it is applied across
                     // lanes in the current layout (0: its target is in the register group)
-    int32_t moff;   // dense / table / phase: offset of its float32 data in the plan's pool; general: 1 when the
-                    // pending per-lane phase must be applied first (a lane operation or a layout change)
-    int32_t real;   // general: the matrix's form (FSV_COMPLEX .. FSV_IPERM), which fixes its arithmetic
+    int32_t moff;   // dense / table / phase: offset of its float32 data in the plan's pool
+    int32_t real;   // general and diagonal: the leaf code of its update (see the host-planned dispatch);
+                    // while the host plans, a general record's form (FSV_COMPLEX .. FSV_IPERM)
     float m[8];  // row-major 2x2 (re, im); a diagonal gate uses m[0..1] and m[6..7]
 };
 
@@ -329,66 +331,6 @@ __device__ __forceinline__ void fsv_xswap_lanes(f32x16& ar, f32x16& ai, uint64_t
     });
 }
 
-// Register control cp (compile-time cases) for the forms that allow it.
-template <int RB, int FORM>
-__device__ __forceinline__ void fsv_pairs_cp(f32x16& ar, f32x16& ai, const Mat2& M, int cp) {
-    switch (cp) {
-        case 0: if constexpr (RB != 0) fsv_pairs<RB, 0, FORM, false>(ar, ai, M); break;
-        case 1: if constexpr (RB != 1) fsv_pairs<RB, 1, FORM, false>(ar, ai, M); break;
-        case 2: if constexpr (RB != 2) fsv_pairs<RB, 2, FORM, false>(ar, ai, M); break;
-        default: if constexpr (RB != 3) fsv_pairs<RB, 3, FORM, false>(ar, ai, M); break;
-    }
-}
-
-// A non-diagonal 2x2 on register bit RB: control on register bit cp (>= 0),
-// on a lane bit (lane_ctrl, on in this lane when lane_on), or none.
-template <int RB>
-__device__ __forceinline__ void fsv_general_rb(f32x16& ar, f32x16& ai, const Mat2& M, int form, int cp,
-                                               bool lane_ctrl, bool lane_on) {
-    if (cp >= 0) {
-        // ANTI, IPERM and IMAGOFF under a register control take the general arithmetic
-        if (form == FSV_XSWAP)
-            fsv_pairs_cp<RB, FSV_XSWAP>(ar, ai, M, cp);
-        else if (form == FSV_REAL)
-            fsv_pairs_cp<RB, FSV_REAL>(ar, ai, M, cp);
-        else
-            fsv_pairs_cp<RB, FSV_COMPLEX>(ar, ai, M, cp);
-        return;
-    }
-    if (lane_ctrl) {
-        if (form == FSV_XSWAP) {
-            fsv_xswap_lanes<RB>(ar, ai, __builtin_amdgcn_ballot_w64(lane_on));
-            return;
-        }
-        // lanes whose control bit is 0 apply the identity (exact: products
-        // with 1 and 0); the identity is REAL and IMAGOFF, not ANTI or IPERM
-        Mat2 L;
-        L.m0r = lane_on ? M.m0r : 1.f;
-        L.m0i = lane_on ? M.m0i : 0.f;
-        L.m1r = lane_on ? M.m1r : 0.f;
-        L.m1i = lane_on ? M.m1i : 0.f;
-        L.m2r = lane_on ? M.m2r : 0.f;
-        L.m2i = lane_on ? M.m2i : 0.f;
-        L.m3r = lane_on ? M.m3r : 1.f;
-        L.m3i = lane_on ? M.m3i : 0.f;
-        if (form == FSV_REAL)
-            fsv_pairs<RB, -1, FSV_REAL, true>(ar, ai, L);
-        else if (form == FSV_IMAGOFF)
-            fsv_pairs<RB, -1, FSV_IMAGOFF, true>(ar, ai, L);
-        else
-            fsv_pairs<RB, -1, FSV_COMPLEX, true>(ar, ai, L);
-        return;
-    }
-    switch (form) {
-        case FSV_XSWAP: fsv_pairs<RB, -1, FSV_XSWAP, false>(ar, ai, M); break;
-        case FSV_REAL: fsv_pairs<RB, -1, FSV_REAL, false>(ar, ai, M); break;
-        case FSV_ANTI: fsv_pairs<RB, -1, FSV_ANTI, false>(ar, ai, M); break;
-        case FSV_IPERM: fsv_pairs<RB, -1, FSV_IPERM, false>(ar, ai, M); break;
-        case FSV_IMAGOFF: fsv_pairs<RB, -1, FSV_IMAGOFF, false>(ar, ai, M); break;
-        default: fsv_pairs<RB, -1, FSV_COMPLEX, false>(ar, ai, M); break;
-    }
-}
-
 // ---- Operations on a lane bit ----
 // A non-diagonal 2x2 whose target is one of the six lane bits of the current
 // layout is applied across lanes instead of after a layout change: each lane
@@ -469,40 +411,6 @@ __device__ __forceinline__ void fsv_lane_op(f32x16& ar, f32x16& ai, const Mat2& 
     });
 }
 
-template <int FORM>
-__device__ __forceinline__ void fsv_lane_op_b(f32x16& ar, f32x16& ai, const Mat2& c, int lb, int lane) {
-    switch (lb) {
-        case 0: fsv_lane_op<0, FORM>(ar, ai, c, lane); break;
-        case 1: fsv_lane_op<1, FORM>(ar, ai, c, lane); break;
-        case 2: fsv_lane_op<2, FORM>(ar, ai, c, lane); break;
-        case 3: fsv_lane_op<3, FORM>(ar, ai, c, lane); break;
-        case 4: fsv_lane_op<4, FORM>(ar, ai, c, lane); break;
-        default: fsv_lane_op<5, FORM>(ar, ai, c, lane); break;
-    }
-}
-
-// A non-diagonal 2x2 M on lane bit lb; a control on a thread bit that is 0 in
-// this lane makes it the identity (exact: products with 1 and 0).
-__device__ __forceinline__ void fsv_lane_general(f32x16& ar, f32x16& ai, const Mat2& M, int form, int lb,
-                                                 bool lane_ctrl, bool lane_on, int lane) {
-    if (form == FSV_XSWAP && !lane_ctrl) {
-        fsv_lane_op_b<FSV_XSWAP>(ar, ai, M, lb, lane);
-        return;
-    }
-    const bool hi = (lane >> lb) & 1;  // this lane holds index bit 1 of the pair
-    const bool on = !lane_ctrl || lane_on;
-    Mat2 c;  // m0: the coefficient of the lane's own value, m1: of its partner's
-    c.m0r = on ? (hi ? M.m3r : M.m0r) : 1.f;
-    c.m0i = on ? (hi ? M.m3i : M.m0i) : 0.f;
-    c.m1r = on ? (hi ? M.m2r : M.m1r) : 0.f;
-    c.m1i = on ? (hi ? M.m2i : M.m1i) : 0.f;
-    c.m2r = c.m2i = c.m3r = c.m3i = 0.f;
-    if (form == FSV_REAL || form == FSV_XSWAP)
-        fsv_lane_op_b<FSV_REAL>(ar, ai, c, lb, lane);
-    else
-        fsv_lane_op_b<FSV_COMPLEX>(ar, ai, c, lb, lane);
-}
-
 // A run of diagonal operations on local qubits, multiplied out on the host:
 // amplitude j (local index) times tab[j].
 // (Each entry's address is a scalar base for the register bits plus the
@@ -559,25 +467,111 @@ __device__ __forceinline__ void fsv_flush(f32x16& ar, f32x16& ai, float& lpr, fl
     lpi = 0.f;
 }
 
-template <int TP, bool D0>
-__device__ __forceinline__ void fsv_diag_tp_d(f32x16& ar, f32x16& ai, int cp, float d0r, float d0i, float d1r,
-                                              float d1i) {
-    switch (cp) {
-        case 0: if constexpr (TP != 0) fsv_diag_reg<TP, 0, D0>(ar, ai, d0r, d0i, d1r, d1i); break;
-        case 1: if constexpr (TP != 1) fsv_diag_reg<TP, 1, D0>(ar, ai, d0r, d0i, d1r, d1i); break;
-        case 2: if constexpr (TP != 2) fsv_diag_reg<TP, 2, D0>(ar, ai, d0r, d0i, d1r, d1i); break;
-        case 3: if constexpr (TP != 3) fsv_diag_reg<TP, 3, D0>(ar, ai, d0r, d0i, d1r, d1i); break;
-        default: fsv_diag_reg<TP, -1, D0>(ar, ai, d0r, d0i, d1r, d1i); break;
+// ---- Host-planned dispatch ----
+// The host follows the register layout through each pass and gives every
+// general and diagonal record a leaf code (in `real`) that names the exact
+// update to run, so the kernel's per-record work is one switch.  General
+// leaves:
+//   kLeafNC   + form * 4 + RB            no local control (form FSV_COMPLEX .. FSV_IPERM)
+//   kLeafCP   + fc * 16 + RB * 4 + cp    control on register bit cp (fc: exchange, real, complex)
+//   kLeafLC   + fc * 4 + RB              control on a thread bit (fc: exchange, real, imaginary
+//                                        off-diagonal, complex)
+//   kLeafLane + fc * 6 + lane bit        target on a lane bit (fc: plain exchange, real, complex)
+// Diagonal leaves (factors d0, d1 on the target's bit values):
+//   kDiagLP   + ts                       target and control off the register group: one factor
+//                                        per lane (ts: 0 the target is a workgroup bit, 1 a thread bit)
+//   kDiagCP   + ts * 4 + cp              control on register bit cp, target off the group
+//   kDiagTP   + (TP * 5 + cp + 1) * 2 + d0   target on register bit TP (cp -1: none or a thread bit);
+//                                        d0 = 0 when d0 is exactly 1
+constexpr int kLeafNC = 0, kLeafCP = 24, kLeafLC = 72, kLeafLane = 88, kLeafEnd = 106;
+constexpr int kDiagLP = 0, kDiagCP = 2, kDiagTP = 10, kDiagEnd = 50;
+
+template <int C>
+__device__ __forceinline__ void fsv_general_leaf(f32x16& ar, f32x16& ai, const Mat2& M, int jt, int cloc,
+                                                 int lane) {
+    if constexpr (C < kLeafCP) {
+        constexpr int form = (C - kLeafNC) / 4, rb = (C - kLeafNC) % 4;
+        fsv_pairs<rb, -1, form, false>(ar, ai, M);
+    } else if constexpr (C < kLeafLC) {
+        constexpr int x = C - kLeafCP, fc = x / 16, rb = (x / 4) % 4, cp = x % 4;
+        constexpr int form = fc == 0 ? FSV_XSWAP : (fc == 1 ? FSV_REAL : FSV_COMPLEX);
+        if constexpr (cp != rb) fsv_pairs<rb, cp, form, false>(ar, ai, M);
+    } else if constexpr (C < kLeafLane) {
+        constexpr int x = C - kLeafLC, fc = x / 4, rb = x % 4;
+        const bool on = (jt >> cloc) & 1;
+        if constexpr (fc == 0) {
+            fsv_xswap_lanes<rb>(ar, ai, __builtin_amdgcn_ballot_w64(on));
+        } else {
+            // lanes whose control bit is 0 apply the identity (exact: products
+            // with 1 and 0); the identity is REAL and IMAGOFF, not ANTI or IPERM
+            Mat2 L;
+            L.m0r = on ? M.m0r : 1.f;
+            L.m0i = on ? M.m0i : 0.f;
+            L.m1r = on ? M.m1r : 0.f;
+            L.m1i = on ? M.m1i : 0.f;
+            L.m2r = on ? M.m2r : 0.f;
+            L.m2i = on ? M.m2i : 0.f;
+            L.m3r = on ? M.m3r : 1.f;
+            L.m3i = on ? M.m3i : 0.f;
+            constexpr int form = fc == 1 ? FSV_REAL : (fc == 2 ? FSV_IMAGOFF : FSV_COMPLEX);
+            fsv_pairs<rb, -1, form, true>(ar, ai, L);
+        }
+    } else {
+        constexpr int x = C - kLeafLane, fc = x / 6, lb = x % 6;
+        if constexpr (fc == 0) {
+            fsv_lane_op<lb, FSV_XSWAP>(ar, ai, M, lane);
+        } else {
+            const bool hi = (lane >> lb) & 1;  // this lane holds index bit 1 of the pair
+            const bool on = cloc < 0 || ((jt >> cloc) & 1);
+            Mat2 c;  // m0: the coefficient of the lane's own value, m1: of its partner's
+            c.m0r = on ? (hi ? M.m3r : M.m0r) : 1.f;
+            c.m0i = on ? (hi ? M.m3i : M.m0i) : 0.f;
+            c.m1r = on ? (hi ? M.m2r : M.m1r) : 0.f;
+            c.m1i = on ? (hi ? M.m2i : M.m1i) : 0.f;
+            c.m2r = c.m2i = c.m3r = c.m3i = 0.f;
+            fsv_lane_op<lb, fc == 1 ? FSV_REAL : FSV_COMPLEX>(ar, ai, c, lane);
+        }
     }
 }
-template <int TP>
-__device__ __forceinline__ void fsv_diag_tp(f32x16& ar, f32x16& ai, int cp, float d0r, float d0i, float d1r,
-                                            float d1i, bool d0_one) {
-    if (d0_one)
-        fsv_diag_tp_d<TP, false>(ar, ai, cp, d0r, d0i, d1r, d1i);
-    else
-        fsv_diag_tp_d<TP, true>(ar, ai, cp, d0r, d0i, d1r, d1i);
+
+// d0 = (d0r, d0i) on the target's value 0, d1 on 1; tval: the target bit
+// when it is off the register group; on: the thread-bit control holds.
+template <int C>
+__device__ __forceinline__ void fsv_diag_leaf(f32x16& ar, f32x16& ai, float& lpr, float& lpi, float d0r,
+                                              float d0i, float d1r, float d1i, int tval, bool on) {
+    if constexpr (C < kDiagCP) {
+        // one factor per lane: d_tval where the control holds, else 1
+        const float fr = on ? (tval ? d1r : d0r) : 1.f;
+        const float fi = on ? (tval ? d1i : d0i) : 0.f;
+        const float pr = fmaf(fr, lpr, -fi * lpi), pi = fmaf(fr, lpi, fi * lpr);
+        lpr = pr;
+        lpi = pi;
+    } else if constexpr (C < kDiagTP) {
+        // control on register bit cp: those registers times d_tval
+        constexpr int cp = (C - kDiagCP) % 4;
+        fsv_scale<cp>(ar, ai, tval ? d1r : d0r, tval ? d1i : d0i);
+    } else {
+        // target on register bit TP; a thread-bit control folds into the factors
+        constexpr int x = C - kDiagTP, d0 = x % 2, tp = (x / 2) / 5, cp = (x / 2) % 5 - 1;
+        if constexpr (cp != tp) {
+            if constexpr (cp >= 0)
+                fsv_diag_reg<tp, cp, d0 == 1>(ar, ai, d0r, d0i, d1r, d1i);
+            else
+                fsv_diag_reg<tp, -1, d0 == 1>(ar, ai, on ? d0r : 1.f, on ? d0i : 0.f, on ? d1r : 1.f,
+                                              on ? d1i : 0.f);
+        }
+    }
 }
+
+#define FSV_GEN_LEAF(C) \
+    case C: fsv_general_leaf<C>(ar, ai, M, jt, g.cloc, lane); break;
+#define FSV_GEN_LEAF2(C) FSV_GEN_LEAF(C) FSV_GEN_LEAF(C + 1)
+#define FSV_GEN_LEAF8(C) FSV_GEN_LEAF2(C) FSV_GEN_LEAF2(C + 2) FSV_GEN_LEAF2(C + 4) FSV_GEN_LEAF2(C + 6)
+#define FSV_DIAG_LEAF(C) \
+    case C: fsv_diag_leaf<C>(ar, ai, lpr, lpi, d0r, d0i, d1r, d1i, tval, on); break;
+#define FSV_DIAG_LEAF2(C) FSV_DIAG_LEAF(C) FSV_DIAG_LEAF(C + 1)
+#define FSV_DIAG_LEAF10(C) \
+    FSV_DIAG_LEAF2(C) FSV_DIAG_LEAF2(C + 2) FSV_DIAG_LEAF2(C + 4) FSV_DIAG_LEAF2(C + 6) FSV_DIAG_LEAF2(C + 8)
 
 // A dense operation on local bits lb .. lb+w-1: out[j] = sum_s M[row(j)][s] in[j with
 // those bits = s], through LDS; the register layout is unchanged.
@@ -738,48 +732,31 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
     int cur = 2;
     for (int gi = 0; gi < nops; ++gi) {
         FsvGate g = ops[gi];
-        const bool off = g.cglob >= 0 && !((base >> g.cglob) & 1);  // a non-local control is 0 here
         if (g.kind == FSV_GENERAL) {
-            // The host planned the pass's layout changes and pending-phase
-            // applications for every workgroup alike, so they happen here even
-            // where a non-local control switches the operation itself off.
-            const int k = g.tloc >> 2;
-            if (g.width == 0 && k != cur) {
-                if (g.moff) fsv_flush(ar, ai, lpr, lpi);
-                fsv_relayout(ar, ai, t, cur, k, s_buf);
-                cur = k;
-            } else if (g.width > 0 && g.moff) {
-                fsv_flush(ar, ai, lpr, lpi);
-            }
-            if (off) continue;
-            const Mat2 M = {g.m[0], g.m[1], g.m[2], g.m[3], g.m[4], g.m[5], g.m[6], g.m[7]};
-            const int jt = fsv_thread_bits(t, cur);
-            if (g.width > 0) {  // target on a lane bit of the current layout
-                const bool lane_ctrl = g.cloc >= 0;
-                const bool lane_on = lane_ctrl ? (jt >> g.cloc) & 1 : true;
-                fsv_lane_general(ar, ai, M, g.real, g.width - 1, lane_ctrl, lane_on, t & 63);
-                continue;
-            }
-            // control: a register bit (cp >= 0), a lane bit, or none
-            int cp = -1;
-            bool lane_ctrl = false, lane_on = true;
-            if (g.cloc >= 0) {
-                if ((g.cloc >> 2) == cur) {
-                    cp = g.cloc & 3;
-                } else {
-                    lane_ctrl = true;
-                    lane_on = (jt >> g.cloc) & 1;
+            // Planned by the host for every workgroup alike (tglob bit 0: apply
+            // the pending per-lane phase; bit 1: change to the target's layout),
+            // so they happen even where a non-local control is 0.
+            if (g.tglob != 0) {
+                if (g.tglob & 1) fsv_flush(ar, ai, lpr, lpi);
+                if (g.tglob & 2) {
+                    const int k = g.tloc >> 2;
+                    fsv_relayout(ar, ai, t, cur, k, s_buf);
+                    cur = k;
                 }
             }
-            switch (g.tloc & 3) {
-                case 0: fsv_general_rb<0>(ar, ai, M, g.real, cp, lane_ctrl, lane_on); break;
-                case 1: fsv_general_rb<1>(ar, ai, M, g.real, cp, lane_ctrl, lane_on); break;
-                case 2: fsv_general_rb<2>(ar, ai, M, g.real, cp, lane_ctrl, lane_on); break;
-                default: fsv_general_rb<3>(ar, ai, M, g.real, cp, lane_ctrl, lane_on); break;
+            if (g.cglob >= 0 && !((base >> g.cglob) & 1)) continue;  // a non-local control is 0 here
+            const Mat2 M = {g.m[0], g.m[1], g.m[2], g.m[3], g.m[4], g.m[5], g.m[6], g.m[7]};
+            const int jt = fsv_thread_bits(t, cur);  // the thread's local index bits in this layout
+            const int lane = t & 63;
+            switch (g.real) {
+                FSV_GEN_LEAF8(0) FSV_GEN_LEAF8(8) FSV_GEN_LEAF8(16) FSV_GEN_LEAF8(24) FSV_GEN_LEAF8(32)
+                FSV_GEN_LEAF8(40) FSV_GEN_LEAF8(48) FSV_GEN_LEAF8(56) FSV_GEN_LEAF8(64) FSV_GEN_LEAF8(72)
+                FSV_GEN_LEAF8(80) FSV_GEN_LEAF8(88) FSV_GEN_LEAF8(96) FSV_GEN_LEAF2(104)
+                default: break;
             }
             continue;
         }
-        if (off) continue;
+        if (g.cglob >= 0 && !((base >> g.cglob) & 1)) continue;  // a non-local control is 0 here
         if (g.kind == FSV_PHASE) {
             // A grouped-diagonal record holds a table over some non-local
             // qubits: this workgroup's entry makes it a plain diagonal on its
@@ -797,8 +774,9 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
             g.kind = FSV_DIAG;
             if (g.tloc < 0) g.tglob = 0;
         }
+        const int jt = fsv_thread_bits(t, cur);
         if (g.kind == FSV_TABLE) {
-            fsv_table(ar, ai, pool + g.moff, fsv_thread_bits(t, cur), 4 * cur);
+            fsv_table(ar, ai, pool + g.moff, jt, 4 * cur);
             continue;
         }
         if (g.kind == FSV_DENSE) {  // only in WIDE passes
@@ -813,55 +791,13 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
             fsv_swap_bits(ar, ai, t, cur, g.tloc, g.cloc, s_buf);
             continue;
         }
-        const int jt = fsv_thread_bits(t, cur);
-        // control: a register bit (cp >= 0), a lane bit, or none
-        int cp = -1;
-        bool lane_ctrl = false, lane_on = true;
-        if (g.cloc >= 0) {
-            if ((g.cloc >> 2) == cur) {
-                cp = g.cloc & 3;
-            } else {
-                lane_ctrl = true;
-                lane_on = (jt >> g.cloc) & 1;
-            }
-        }
-        // diagonal: target a register bit (tp >= 0), a lane bit or a workgroup bit
+        // diagonal
         const float d0r = g.m[0], d0i = g.m[1], d1r = g.m[6], d1i = g.m[7];
-        int tp = -1, tval = 0;
-        if (g.tloc < 0)
-            tval = (int)((base >> g.tglob) & 1);
-        else if ((g.tloc >> 2) == cur)
-            tp = g.tloc & 3;
-        else
-            tval = (jt >> g.tloc) & 1;
-        if (tp < 0 && cp < 0) {
-            // one factor per lane: d_tval where the control holds, else 1
-            const bool on = lane_on;
-            const float fr = on ? (tval ? d1r : d0r) : 1.f;
-            const float fi = on ? (tval ? d1i : d0i) : 0.f;
-            const float pr = fmaf(fr, lpr, -fi * lpi), pi = fmaf(fr, lpi, fi * lpr);
-            lpr = pr;
-            lpi = pi;
-        } else if (tp < 0) {
-            // control on register bit cp: those registers times d_tval
-            const float fr = tval ? d1r : d0r, fi = tval ? d1i : d0i;
-            switch (cp) {
-                case 0: fsv_scale<0>(ar, ai, fr, fi); break;
-                case 1: fsv_scale<1>(ar, ai, fr, fi); break;
-                case 2: fsv_scale<2>(ar, ai, fr, fi); break;
-                default: fsv_scale<3>(ar, ai, fr, fi); break;
-            }
-        } else {
-            // target on register bit tp; a lane control folds into the factors
-            const bool d0_one = d0r == 1.f && d0i == 0.f;
-            const float e0r = lane_on ? d0r : 1.f, e0i = lane_on ? d0i : 0.f;
-            const float e1r = lane_on ? d1r : 1.f, e1i = lane_on ? d1i : 0.f;
-            switch (tp) {
-                case 0: fsv_diag_tp<0>(ar, ai, cp, e0r, e0i, e1r, e1i, d0_one); break;
-                case 1: fsv_diag_tp<1>(ar, ai, cp, e0r, e0i, e1r, e1i, d0_one); break;
-                case 2: fsv_diag_tp<2>(ar, ai, cp, e0r, e0i, e1r, e1i, d0_one); break;
-                default: fsv_diag_tp<3>(ar, ai, cp, e0r, e0i, e1r, e1i, d0_one); break;
-            }
+        const int tval = g.tloc < 0 ? (int)((base >> g.tglob) & 1) : (jt >> g.tloc) & 1;
+        const bool on = g.cloc < 0 || ((jt >> g.cloc) & 1);  // used by leaves whose control is a thread bit
+        switch (g.real) {
+            FSV_DIAG_LEAF10(0) FSV_DIAG_LEAF10(10) FSV_DIAG_LEAF10(20) FSV_DIAG_LEAF10(30) FSV_DIAG_LEAF10(40)
+            default: break;
         }
     }
     fsv_flush(ar, ai, lpr, lpi);
@@ -1485,23 +1421,59 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
                 }
                 i = e;
             }
-            // Which lane operations and layout changes must first apply the
-            // pending per-lane phase (moff = 1): those after a diagonal
-            // operation that the kernel folds into it (no register-group bit).
+            // Leaf codes and planned actions.  A general record changes the
+            // layout (tglob bit 1) when its target is outside the register
+            // group and it is not applied across lanes; it and a lane operation
+            // first apply the pending per-lane phase (bit 0) when a diagonal
+            // that the kernel folds into it (target and control off the register
+            // group) came since the last application.
             c = 2;
             bool dirty = false;
             for (int x = p.g0; x < p.g1; ++x) {
                 FsvGate& d = table[x];
                 if (d.kind == FSV_DIAG || d.kind == FSV_PHASE) {
-                    const bool tp = d.tloc >= 0 && (d.tloc >> 2) == c;
-                    const bool cr = d.cloc >= 0 && (d.cloc >> 2) == c;
-                    if (!tp && !cr) dirty = true;
+                    const int tp = d.tloc >= 0 && (d.tloc >> 2) == c ? d.tloc & 3 : -1;
+                    const int cp = d.cloc >= 0 && (d.cloc >> 2) == c ? d.cloc & 3 : -1;
+                    const int ts = d.tloc >= 0 ? 1 : 0;
+                    if (tp < 0 && cp < 0) {
+                        dirty = true;
+                        d.real = kDiagLP + ts;
+                    } else if (tp < 0) {
+                        d.real = kDiagCP + ts * 4 + cp;
+                    } else {
+                        // a grouped record's factors are known per workgroup only
+                        const bool d0 = d.kind == FSV_PHASE || !(d.m[0] == 1.f && d.m[1] == 0.f);
+                        d.real = kDiagTP + (tp * 5 + cp + 1) * 2 + (d0 ? 1 : 0);
+                    }
                 } else if (d.kind == FSV_SWAP || d.kind == FSV_DENSE) {
                     dirty = false;  // always applied before these
-                } else if (d.kind == FSV_GENERAL && (d.width > 0 || (d.tloc >> 2) != c)) {
-                    d.moff = dirty ? 1 : 0;
-                    dirty = false;
-                    if (d.width == 0) c = d.tloc >> 2;
+                } else if (d.kind == FSV_GENERAL) {
+                    const int form = d.real;
+                    int flags = 0;
+                    if (d.width > 0 || (d.tloc >> 2) != c) {
+                        if (dirty) flags |= 1;
+                        dirty = false;
+                        if (d.width == 0) {
+                            flags |= 2;
+                            c = d.tloc >> 2;
+                        }
+                    }
+                    d.tglob = flags;
+                    d.moff = 0;
+                    const int rb = d.tloc & 3;
+                    if (d.width > 0) {
+                        const int fc = (form == FSV_XSWAP && d.cloc < 0) ? 0
+                                       : (form == FSV_REAL || form == FSV_XSWAP) ? 1 : 2;
+                        d.real = kLeafLane + fc * 6 + (d.width - 1);
+                    } else if (d.cloc >= 0 && (d.cloc >> 2) == c) {
+                        const int fc = form == FSV_XSWAP ? 0 : (form == FSV_REAL ? 1 : 2);
+                        d.real = kLeafCP + fc * 16 + rb * 4 + (d.cloc & 3);
+                    } else if (d.cloc >= 0) {
+                        const int fc = form == FSV_XSWAP ? 0 : form == FSV_REAL ? 1 : form == FSV_IMAGOFF ? 2 : 3;
+                        d.real = kLeafLC + fc * 4 + rb;
+                    } else {
+                        d.real = kLeafNC + form * 4 + rb;
+                    }
                 }
             }
         }
