@@ -1441,8 +1441,14 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
                     } else if (tp < 0) {
                         d.real = kDiagCP + ts * 4 + cp;
                     } else {
-                        // a grouped record's factors are known per workgroup only
-                        const bool d0 = d.kind == FSV_PHASE || !(d.m[0] == 1.f && d.m[1] == 0.f);
+                        // d0 is applied unless it is exactly 1 (for a grouped record: in
+                        // every workgroup's entry of its table)
+                        bool d0 = !(d.m[0] == 1.f && d.m[1] == 0.f);
+                        if (d.kind == FSV_PHASE) {
+                            d0 = false;
+                            for (int e = 0; e < (1 << d.width); ++e)
+                                if (pool[d.moff + 4 * e] != 1.f || pool[d.moff + 4 * e + 1] != 0.f) d0 = true;
+                        }
                         d.real = kDiagTP + (tp * 5 + cp + 1) * 2 + (d0 ? 1 : 0);
                     }
                 } else if (d.kind == FSV_SWAP || d.kind == FSV_DENSE) {
