@@ -510,11 +510,14 @@ qsim_status qsim_profile_read(qsim_ctx* ctx, qsim_kernel_stats* out);
 #define QSIM_FSV_MAX_HIGH 6
 typedef struct qsim_fsv_plan qsim_fsv_plan;
 typedef struct qsim_fsv_pass_info {
-    int32_t low_qubits;             /* qubits 0..low_qubits-1 are local */
+    int32_t low_qubits;             /* qubits 0..low_qubits-1 are local (0 in a permutation pass) */
     int32_t n_high;                 /* further local qubits, ascending in high[] */
     int32_t high[QSIM_FSV_MAX_HIGH]; /* -1 past n_high */
     int32_t first_op;               /* the pass's gates: order[first_op .. first_op + n_ops) */
     int32_t n_ops;
+    int32_t permutation;            /* 1: a pass of pairwise disjoint SWAPs on any qubits, applied as one
+                                       permutation of the state (states of more than 12 qubits, when only
+                                       SWAPs are ready); 0: a pass over 12 local qubits */
 } qsim_fsv_pass_info;
 
 /* Host only (no device, no context): the pass schedule of a gate list.

@@ -55,7 +55,7 @@ QSIM_FSV_MAX_HIGH = 6
 class qsim_fsv_pass_info(ctypes.Structure):
     _fields_ = [("low_qubits", ctypes.c_int32), ("n_high", ctypes.c_int32),
                 ("high", ctypes.c_int32 * QSIM_FSV_MAX_HIGH), ("first_op", ctypes.c_int32),
-                ("n_ops", ctypes.c_int32)]
+                ("n_ops", ctypes.c_int32), ("permutation", ctypes.c_int32)]
 
 
 class qsim_circuit_desc(ctypes.Structure):
@@ -566,7 +566,8 @@ def qsim_sample(ctx, n_qubits: int, d_prob, d_uniform, shots: int, d_out, stream
 
 def qsim_fsv_schedule(n_qubits: int, gates, with_order: bool = False):
     """Pass schedule of a gate list (host only): [(low_qubits, high_qubits, first_op, n_ops), ...], and with
-    with_order the execution order (gate indices; pass p runs order[first_op:first_op + n_ops])."""
+    with_order the execution order (gate indices; pass p runs order[first_op:first_op + n_ops]).
+    low_qubits == 0 marks a permutation pass (pairwise disjoint SWAPs on any qubits)."""
     arr, count = gate_array(gates)
     n = ctypes.c_int32(0)
     _check(lib().qsim_fsv_schedule(n_qubits, arr, count, None, 0, ctypes.byref(n), None), "qsim_fsv_schedule")

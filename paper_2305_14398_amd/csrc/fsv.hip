@@ -102,6 +102,26 @@ struct FsvGate {
 //   FSV_IPERM    [[0, -i], [i, 0]] (Y): exchanges and sign flips only, exact.
 enum : int32_t { FSV_COMPLEX = 0, FSV_REAL = 1, FSV_XSWAP = 2, FSV_ANTI = 3, FSV_IMAGOFF = 4, FSV_IPERM = 5 };
 
+// A pass of pairwise disjoint SWAPs is one permutation sigma of qubit
+// positions (an involution): the amplitude at index i moves to sigma(i), the
+// index with its bits moved by sigma.  Positions 0-5 (a row of 64 contiguous
+// amplitudes) and the h positions that sigma exchanges with them form a tile of
+// 64 * 2^h amplitudes; the other positions name a group, and sigma maps group
+// g's tile onto group sigma(g)'s with the tile bits permuted.  One workgroup per
+// pair {g, sigma(g)} reads both tiles (rows of 64 contiguous amplitudes), and
+// writes both through LDS in the permuted order, again in contiguous rows: one
+// read and one write of every amplitude, in place, with no workgroup writing
+// where another reads.
+struct FsvPerm {
+    int32_t h;           // tile bits 6 .. 5 + h are positions hpos[0 .. h)
+    int32_t ng;          // group bits 0 .. ng - 1 are positions gpos[0 .. ng), in the order of max(x, sigma(x))
+    int32_t hpos[6];
+    int32_t fold[6];     // LDS slot of a tile element: e ^ (fold[j] for each set row bit 6 + j)
+    int32_t gpos[QSIM_FSV_MAX_QUBITS];
+    int32_t sig_tile[12];                  // tile bit -> tile bit under sigma
+    int32_t sig_group[QSIM_FSV_MAX_QUBITS];  // group bit -> group bit under sigma
+};
+
 struct FsvPass {
     int32_t L;   // local bits 0..L-1 are qubits 0..L-1
     int32_t nh;  // local bits L..L+nh-1 are qubits high[0..nh-1], ascending
@@ -110,7 +130,10 @@ struct FsvPass {
     int32_t wide;            // the pass holds a dense operation (both planes staged in LDS)
     int32_t g0, g1;  // the pass's records in the plan's table
     int32_t op0, op1;  // the operations the pass covers
+    int32_t perm;    // a permutation pass (disjoint SWAPs on any qubits), described by pm
+    FsvPerm pm;
 };
+
 
 namespace {
 
@@ -814,6 +837,110 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
     });
 }
 
+// Permutation pass (see FsvPerm): one workgroup per tile pair, planes in turn
+// through a 32 KiB LDS buffer (two tiles of 1024 to 4096 floats).  A tile
+// element's address, LDS slot and permuted index are linear over XOR in its
+// bits, so each splits into a per-thread part and parts uniform over the
+// workgroup.
+__device__ __forceinline__ uint32_t fsv_tile_perm(uint32_t e, const FsvPerm& q, int tbits) {
+    uint32_t o = 0;
+    for (int b = 0; b < tbits; ++b) o |= ((e >> b) & 1u) << q.sig_tile[b];
+    return o;
+}
+__device__ __forceinline__ uint64_t fsv_tile_addr(uint32_t e, const FsvPerm& q) {
+    uint64_t a = e & 63u;
+    for (int j = 0; j < q.h; ++j) a |= (uint64_t)((e >> (6 + j)) & 1u) << q.hpos[j];
+    return a;
+}
+// LDS slot of tile element e: its row bits folded onto its column bits (a
+// bijection, linear over XOR), so that a wave reading a permuted row spreads
+// over the banks.
+__device__ __forceinline__ uint32_t fsv_perm_slot(uint32_t e, const FsvPerm& q) {
+    uint32_t s = e;
+    for (int j = 0; j < q.h; ++j)
+        if ((e >> (6 + j)) & 1u) s ^= (uint32_t)q.fold[j];
+    return s;
+}
+
+__global__ __launch_bounds__(256) void fsv_perm_kernel(FsvPerm q, float* __restrict__ re, float* __restrict__ im) {
+    __shared__ float sa[1 << kFsvLocal], sb[1 << kFsvLocal];
+    const uint32_t g = blockIdx.x;
+    uint32_t g2 = 0;
+    uint64_t base_a = 0, base_b = 0;
+    for (int b = 0; b < q.ng; ++b) {
+        const uint32_t bit = (g >> b) & 1u;
+        g2 |= bit << q.sig_group[b];
+        base_a |= (uint64_t)bit << q.gpos[b];
+    }
+    if (g2 < g) return;  // the pair's other workgroup moves it (uniform exit)
+    for (int b = 0; b < q.ng; ++b) base_b |= (uint64_t)((g2 >> b) & 1u) << q.gpos[b];
+    const bool pair = g2 != g;
+    const int tbits = 6 + q.h;  // 10 to 12
+    const int nj = 1 << (tbits - 10);
+    // thread t holds elements e0 + c + 1024 j (c < 4): four contiguous
+    // amplitudes, 16 threads to a row
+    const uint32_t e0 = 4 * threadIdx.x;
+    const uint64_t at = fsv_tile_addr(e0, q);
+    const uint32_t lt = fsv_perm_slot(e0, q);
+    const uint32_t st = fsv_perm_slot(fsv_tile_perm(e0, q, tbits), q);
+    uint64_t aj[4];
+    uint32_t lj[4], sj[4], sc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t k = (uint32_t)j << 10;
+        aj[j] = fsv_tile_addr(k, q) >> 2;
+        lj[j] = fsv_perm_slot(k, q);
+        sj[j] = fsv_perm_slot(fsv_tile_perm(k, q, tbits), q);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sc[c] = fsv_perm_slot(fsv_tile_perm((uint32_t)c, q, tbits), q);
+    float4 va[4], vb[4];
+#pragma unroll
+    for (int pl = 0; pl < 2; ++pl) {
+        float* __restrict__ P = pl ? im : re;
+        float4* pa = reinterpret_cast<float4*>(P + (base_a | at));
+        float4* pb = reinterpret_cast<float4*>(P + (base_b | at));
+        // every load of the plane in flight before the first LDS write
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (j < nj) {
+                va[j] = pa[aj[j]];
+                if (pair) vb[j] = pb[aj[j]];
+            }
+        __syncthreads();  // the previous plane's readers of the buffer are done
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (j < nj) {
+                const uint32_t s0 = lt ^ lj[j];  // slot(e0 + c + 1024 j) = s0 ^ c
+                sa[s0] = va[j].x;
+                sa[s0 ^ 1] = va[j].y;
+                sa[s0 ^ 2] = va[j].z;
+                sa[s0 ^ 3] = va[j].w;
+                if (pair) {
+                    sb[s0] = vb[j].x;
+                    sb[s0 ^ 1] = vb[j].y;
+                    sb[s0 ^ 2] = vb[j].z;
+                    sb[s0 ^ 3] = vb[j].w;
+                }
+            }
+        __syncthreads();
+        // output element e of group sigma(g) is input element sigma(e) of group g
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (j < nj) {
+                const uint32_t s0 = st ^ sj[j];
+                va[j] = make_float4(sa[s0 ^ sc[0]], sa[s0 ^ sc[1]], sa[s0 ^ sc[2]], sa[s0 ^ sc[3]]);
+                if (pair) vb[j] = make_float4(sb[s0 ^ sc[0]], sb[s0 ^ sc[1]], sb[s0 ^ sc[2]], sb[s0 ^ sc[3]]);
+            }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (j < nj) {
+                pb[aj[j]] = va[j];
+                if (pair) pa[aj[j]] = vb[j];
+            }
+    }
+}
+
 // |basis> in planar complex64, written as float4 (2N floats, N >= 2).
 __global__ __launch_bounds__(256) void fsv_basis_kernel(uint64_t n4, uint64_t basis, float4* __restrict__ psi) {
     for (uint64_t v = (uint64_t)blockIdx.x * 256 + threadIdx.x; v < n4; v += (uint64_t)gridDim.x * 256) {
@@ -1074,6 +1201,77 @@ uint64_t op_qubits(const LoweredGate& l) {
 // take gates from later layers on its local qubits while a gate on a qubit that
 // is not local waits for a later pass.  exec_order (optional) receives the
 // operations pass by pass, each pass in the order its launch applies them.
+// Permutation pass over the ready SWAPs (pairwise disjoint), which it takes
+// out of the ready set.  Tile bits: positions 0-5, then the positions sigma
+// exchanges with them, then whole orbits of sigma (fixed points first, lowest
+// first) up to twelve bits: 10 to 12 bits for any n > 12 (orbits have one or
+// two positions, and at least seven positions lie above 5).
+FsvPass perm_pass(int n, const std::vector<LoweredGate>& gs, std::set<int>& ready,
+                  const std::vector<std::vector<int>>& succ_all, std::vector<int>& indeg_all,
+                  std::vector<int>* exec_order, const std::vector<FsvGate>& table, int& executed) {
+    FsvPass p{};
+    p.perm = 1;
+    int sigma[64];
+    for (int x = 0; x < n; ++x) sigma[x] = x;
+    const std::vector<int> ops(ready.begin(), ready.end());
+    for (int b : ops) {
+        sigma[gs[b].tq] = gs[b].cq;
+        sigma[gs[b].cq] = gs[b].tq;
+    }
+    for (int b : ops) {
+        ready.erase(b);
+        for (int c : succ_all[b])
+            if (--indeg_all[c] == 0) ready.insert(c);
+        if (exec_order) exec_order->push_back(b);
+    }
+    FsvPerm& q = p.pm;
+    int tile_bit[64];
+    for (int x = 0; x < n; ++x) tile_bit[x] = x < 6 ? x : -1;
+    q.h = 0;
+    auto add = [&](int x, int fold) {
+        q.hpos[q.h] = x;
+        q.fold[q.h] = fold;
+        tile_bit[x] = 6 + q.h++;
+    };
+    // an exchanged row bit folds onto the column bit it came from, so the 64
+    // lanes reading a permuted row hit 64 distinct LDS banks
+    for (int l = 0; l < 6; ++l)
+        if (sigma[l] >= 6) add(sigma[l], 1 << l);
+    for (int pairs = 0; pairs < 2; ++pairs)
+        for (int x = 6; x < n && q.h < 6; ++x) {
+            if (tile_bit[x] >= 0) continue;
+            if (sigma[x] == x) {
+                add(x, 0);
+            } else if (pairs && q.h + 2 <= 6) {  // sigma[x] >= 6 is outside the tile too
+                add(x, 0);
+                add(sigma[x], 0);
+            }
+        }
+    // Group bits in the order of max(x, sigma(x)): the workgroups resident at
+    // once (consecutive indices) then read and write both tiles of their pairs
+    // inside one window of the state, not one of them spread over all of it.
+    int group_bit[64];
+    q.ng = 0;
+    for (int x = 6; x < n; ++x)
+        if (tile_bit[x] < 0) q.gpos[q.ng++] = x;
+    std::sort(q.gpos, q.gpos + q.ng, [&](int a, int b) {
+        const int ka = std::max(a, sigma[a]), kb = std::max(b, sigma[b]);
+        return ka != kb ? ka < kb : a < b;
+    });
+    for (int i = 0; i < q.ng; ++i) group_bit[q.gpos[i]] = i;
+    for (int x = 0; x < n; ++x) {
+        if (tile_bit[x] >= 0)
+            q.sig_tile[tile_bit[x]] = tile_bit[sigma[x]];
+        else
+            q.sig_group[group_bit[x]] = group_bit[sigma[x]];
+    }
+    p.g0 = p.g1 = (int)table.size();
+    p.op0 = executed;
+    executed += (int)ops.size();
+    p.op1 = executed;
+    return p;
+}
+
 void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass>& passes,
                   std::vector<FsvGate>& table, std::vector<float>& pool, std::vector<int>* exec_order = nullptr) {
     passes.clear();
@@ -1118,7 +1316,25 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
     for (int b = 0; b < m_all; ++b)
         if (indeg_all[b] == 0) ready.insert(b);
     int executed = 0;
+    int nonswap_left = 0;
+    for (const LoweredGate& l : gs) nonswap_left += l.kind != FSV_SWAP;
     while (!ready.empty()) {
+        // Only SWAPs ready (pairwise disjoint: a later SWAP sharing a qubit
+        // waits for the earlier), and either more qubits than one pass holds
+        // locally or nothing but SWAPs left: one permutation pass takes them
+        // all, whatever their qubits, for one read and write of the state.
+        if (n > kFsvLocal) {
+            bool swaps = true;
+            uint64_t touched = 0;
+            for (int b : ready) {
+                if (gs[b].kind != FSV_SWAP) swaps = false;
+                touched |= op_qubits(gs[b]);
+            }
+            if (swaps && (__builtin_popcountll(touched) > kFsvLocal || nonswap_left == 0)) {
+                passes.push_back(perm_pass(n, gs, ready, succ_all, indeg_all, exec_order, table, executed));
+                continue;
+            }
+        }
         FsvPass p{};
         uint64_t T = 0;
         int L = n <= kFsvLocal ? n : kFsvLocal;
@@ -1162,6 +1378,7 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
         p.op0 = executed;
         executed += (int)pass_ops.size();
         p.op1 = executed;
+        for (int b : pass_ops) nonswap_left -= gs[b].kind != FSV_SWAP;
         auto local_bit = [&](int q) {
             if (q < 0) return -1;
             if (q < p.L) return q;
@@ -1541,6 +1758,7 @@ qsim_status qsim_fsv_schedule(int n_qubits, const qsim_gate* gates, int n_gates,
         for (int h = 0; h < QSIM_FSV_MAX_HIGH; ++h) o.high[h] = h < ps[i].nh ? ps[i].high[h] : -1;
         o.first_op = ps[i].op0;
         o.n_ops = ps[i].op1 - ps[i].op0;
+        o.permutation = ps[i].perm;
     }
     return ok();
 }
@@ -1562,6 +1780,11 @@ qsim_status qsim_fsv_plan_create(qsim_ctx* ctx, int n_qubits, const qsim_gate* g
     std::vector<float> pool;
     fsv_schedule(n_qubits, gs, plan->passes, table, pool);
     plan->n_ops = (int)gs.size();
+    for (const FsvPass& p : plan->passes)
+        if (p.perm && (p.pm.h < 4 || p.pm.h > 6)) {  // the permutation kernel's tiles are 2^10 to 2^12
+            delete plan;
+            return fail(QSIM_E_INVALID, "permutation pass with a %d-bit tile", 6 + p.pm.h);
+        }
     if (!table.empty()) {
         DeviceGuard g(ctx->device);
         hipError_t e = g.err;
@@ -1618,7 +1841,9 @@ qsim_status qsim_fsv_run(qsim_ctx* ctx, const qsim_fsv_plan* plan, void* d_psi, 
     const unsigned blocks = n > kFsvLocal ? 1u << (n - kFsvLocal) : 1u;
     for (const FsvPass& p : plan->passes) {
         hipError_t e = timed(ctx->prof, QSIM_PROFILE_FSV, hs, [&] {
-            if (p.wide)
+            if (p.perm)
+                hipLaunchKernelGGL(fsv_perm_kernel, dim3(1u << p.pm.ng), dim3(256), 0, hs, p.pm, re, im);
+            else if (p.wide)
                 hipLaunchKernelGGL(fsv_pass_kernel<true>, dim3(blocks), dim3(256), 0, hs, n, p, plan->d_gates,
                                    plan->d_pool, re, im);
             else

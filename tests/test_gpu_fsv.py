@@ -335,3 +335,48 @@ def test_fsv_lane_operations_and_layout_runs(ctx, seed):
     got, info = run_fsv(ctx, n, g, psi0)
     ref = fsv.final_state(n, g, psi0)
     assert np.linalg.norm(got - ref) <= bound(g), (np.linalg.norm(got - ref), bound(g), info)
+
+
+def swap_layers(n, rng, layers):
+    """Layers of pairwise disjoint SWAPs on random qubits (a layer of 1 to n/2 pairs)."""
+    out = []
+    for _ in range(layers):
+        qs = [int(x) for x in rng.permutation(n)]
+        m = int(rng.integers(1, n // 2 + 1))
+        out += [("SWAP", (qs[2 * i], qs[2 * i + 1]), None) for i in range(m)]
+    return out
+
+
+@pytest.mark.parametrize("n,case", [(13, "random"), (14, "random"), (16, "random"), (20, "random"),
+                                    (16, "reverse"), (18, "low_only"), (18, "high_only"), (17, "low_high")])
+def test_fsv_permutation_passes_are_exact(ctx, n, case):
+    """SWAP-only circuits run as permutation passes: the amplitudes move unchanged, so the result equals the
+    oracle's exactly (the float32 input permuted)."""
+    rng = np.random.default_rng(900 + n)
+    g = {"random": lambda: swap_layers(n, rng, 4),
+         "reverse": lambda: [("SWAP", (q, n - 1 - q), None) for q in range(n // 2)],
+         "low_only": lambda: [("SWAP", (0, 5), None), ("SWAP", (1, 3), None)],  # no row bit exchanged
+         "high_only": lambda: [("SWAP", (6, 17), None), ("SWAP", (8, 12), None), ("SWAP", (9, 10), None)],
+         "low_high": lambda: [("SWAP", (q, 16 - q), None) for q in range(6)] + [("SWAP", (7, 9), None)]}[case]()
+    sched = B.qsim_fsv_schedule(n, g)
+    assert any(p[0] == 0 for p in sched)
+    psi0 = W.random_state(n, 3 * n).astype(np.complex64)
+    got, info = run_fsv(ctx, n, g, psi0)
+    ref = fsv.final_state(n, g, psi0.astype(np.complex128))
+    np.testing.assert_array_equal(got, ref.astype(np.complex64))
+    assert info["passes"] == len(sched)
+
+
+@pytest.mark.parametrize("n", [16, 20])
+def test_fsv_qft_with_permutation_pass(ctx, n):
+    """A QFT whose closing reversal runs as a permutation pass, and SWAP layers between rotation layers."""
+    rng = np.random.default_rng(40 + n)
+    g = W.gate_tuples(W.qft(n))
+    assert B.qsim_fsv_schedule(n, g)[-1][0] == 0
+    layers = [("SWAP", (q, q + n // 2), None) for q in range(n // 2)]
+    g2 = W.gate_tuples(W.random_layers(n, 2, rng)) + layers + W.gate_tuples(W.random_layers(n, 2, rng))
+    for gates in (g, g2):
+        psi0 = W.random_state(n, 7 + n)
+        got, _ = run_fsv(ctx, n, gates, psi0)
+        ref = fsv.final_state(n, gates, psi0)
+        assert np.linalg.norm(got - ref) <= bound(gates)

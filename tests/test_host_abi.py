@@ -266,6 +266,13 @@ def _check_schedule(n, gates):
     for low, highs, first, cnt in sched:
         assert first == nxt and cnt >= 1
         nxt += cnt
+        if low == 0:  # a permutation pass: pairwise disjoint SWAPs on any qubits
+            assert n > 12 and highs == ()
+            ops = [gates[gi] for gi in order[first:first + cnt]]
+            assert all(nm == "SWAP" for nm, _, _ in ops)
+            qs = [q for _, pair, _ in ops for q in pair]
+            assert len(qs) == len(set(qs))
+            continue
         if n <= 12:
             assert low == n and highs == ()
         else:
@@ -313,6 +320,30 @@ def test_fsv_schedule_runs_ahead_on_local_qubits():
     sched, order = B.qsim_fsv_schedule(n, gates, with_order=True)
     assert order.index(12) < order.index(13) < order.index(14)
     _check_schedule(n, gates)
+
+
+def test_fsv_schedule_permutation_passes():
+    # the reversal closing a QFT on 30 qubits: 15 disjoint SWAPs over all 30 qubits.  The three on qubits
+    # 12-17 ride along in an ordinary pass; the other 12 take one permutation pass (as 12-qubit passes they
+    # would take two more): 5 passes in all
+    n = 30
+    sched = _check_schedule(n, W.gate_tuples(W.qft(n)))
+    assert len(sched) == 5 and sched[-1][0] == 0 and sched[-1][3] == 12
+    assert all(p[0] != 0 for p in sched[:-1])
+    # when only SWAPs are ready and they span more than 12 qubits, they are one permutation pass; two
+    # layers sharing qubits are two (a SWAP waits for the earlier one on its qubits)
+    layer = [("SWAP", (q, q + 10), None) for q in range(8)]
+    swapped = [q for _, pair, _ in layer for q in pair]
+    gates = layer + layer + [("H", (q,), None) for q in swapped]
+    sched = _check_schedule(n, gates)
+    perms = [p for p in sched if p[0] == 0]
+    assert len(perms) == 2 and all(p[3] == 8 for p in perms)
+    # SWAPs on at most 12 qubits with other gates still to come stay in the ordinary passes
+    gates = [("H", (q,), None) for q in range(n)] + [("SWAP", (0, 20), None), ("SWAP", (1, 25), None)] + \
+        [("H", (q,), None) for q in range(n)]
+    assert all(p[0] != 0 for p in _check_schedule(n, gates))
+    # up to 12 qubits there are no permutation passes
+    assert all(p[0] != 0 for p in _check_schedule(12, W.gate_tuples(W.qft(12))))
 
 
 def test_fsv_schedule_counts():
