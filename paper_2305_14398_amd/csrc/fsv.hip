@@ -73,17 +73,18 @@ __device__ __forceinline__ void fsv_for16(F&& f) {
 }
 
 enum : int32_t { FSV_GENERAL = 0, FSV_DIAG = 1, FSV_DENSE = 2, FSV_TABLE = 3, FSV_PHASE = 4, FSV_SWAP = 5 };
-constexpr int kFsvPhaseBits = 5;  // non-local qubits per FSV_PHASE table (2^5 entries)
+constexpr int kFsvPhaseBits = 10;    // workgroup-number bits per FSV_PHASE window (up to 2^10 entries)
+constexpr int kFsvPhaseWindows = 3;  // windows per FSV_PHASE record
 
 struct FsvGate {
     int32_t kind;
     int32_t tloc;   // local bit of the target (dense: of the range's lowest qubit), or -1 (diagonal only)
-    int32_t tglob;  // the target qubit when it is not local (phase: up to 5 non-local qubits, 6 bits each);
+    int32_t tglob;  // the target qubit when it is not local (phase: its windows, 10 bits each: lo | w << 5);
                     // general: planned actions before it (bit 0: apply the pending per-lane phase,
                     // bit 1: change to the target's register layout)
     int32_t cloc;   // local bit of the control, or -1
     int32_t cglob;  // a non-local control qubit, or -1
-    int32_t width;  // dense: qubits in the range; phase: non-local qubits of its table;
+    int32_t width;  // dense: qubits in the range; phase: windows (tables) it multiplies;
                     // general: 1 + the lane bit its target occupies when it is applied across
                     // lanes in the current layout (0: its target is in the register group)
     int32_t moff;   // dense / table / phase: offset of its float32 data in the plan's pool
@@ -784,12 +785,23 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
             // A grouped-diagonal record holds a table over some non-local
             // qubits: this workgroup's entry makes it a plain diagonal on its
             // local bit (no local bit: d0 = d1, the same factor whatever bit it reads).
-            int idx = 0;
-            for (int b = 0; b < g.width; ++b) {
-                const int q = (g.tglob >> (6 * b)) & 63;
-                idx |= (int)((base >> q) & 1) << b;
+            // Entries of its windows (bits lo .. lo + w - 1 of the workgroup
+            // number, each window's table after the previous one) multiply.
+            const uint32_t wg = blockIdx.x;
+            int off = g.moff;
+            float4 e = make_float4(1.f, 0.f, 1.f, 0.f);
+            for (int k = 0; k < g.width; ++k) {
+                const int f = (g.tglob >> (10 * k)) & 1023;
+                const int lo = f & 31, w = f >> 5;
+                const float4 v = *reinterpret_cast<const float4*>(pool + off + 4 * ((wg >> lo) & ((1u << w) - 1)));
+                if (k == 0) {
+                    e = v;
+                } else {
+                    e = make_float4(e.x * v.x - e.y * v.y, e.x * v.y + e.y * v.x,
+                                    e.z * v.z - e.w * v.w, e.z * v.w + e.w * v.z);
+                }
+                off += 4 << w;
             }
-            const float4 e = *reinterpret_cast<const float4*>(pool + g.moff + 4 * idx);
             g.m[0] = e.x;
             g.m[1] = e.y;
             g.m[6] = e.z;
@@ -1514,8 +1526,9 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
             }
             // In a workgroup the non-local qubits are fixed, so each remaining operation is a diagonal on one
             // local bit (one local and one non-local qubit) or a single factor (no local qubit).  They are
-            // grouped by that local bit and multiplied out on the host in float64 for every combination of up
-            // to 5 of their non-local qubits: one table lookup replaces a record per operation.
+            // grouped by that local bit and multiplied out on the host in float64 for every value of the
+            // non-local qubits they read (tables over windows of the workgroup number): a few table lookups
+            // and one update of the amplitudes replace a record per operation.
             std::vector<std::pair<int, std::vector<size_t>>> groups;  // local bit (-1: none), operations
             for (size_t q : other_ops) {
                 const LoweredGate& l = gs[q];
@@ -1536,70 +1549,96 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
                 if (gi == groups.size()) groups.push_back({a, {}});
                 groups[gi].second.push_back(q);
             }
+            // The workgroup number holds the non-local qubits in ascending order;
+            // a table is indexed by a window of at most kFsvPhaseBits of its bits,
+            // and one record multiplies the entries of up to kFsvPhaseWindows
+            // windows before it touches the amplitudes.
+            auto wg_bit = [&](int q) {
+                int below = std::min(q, p.L);
+                for (int h = 0; h < p.nh; ++h) below += p.high[h] < q;
+                return q - below;
+            };
             for (auto& grp : groups) {
                 const int a = grp.first;
-                size_t x = 0;
-                while (x < grp.second.size()) {
-                    // the next chunk: operations in order while their non-local qubits number <= 5
-                    std::vector<int> qs;
-                    size_t y = x;
-                    for (; y < grp.second.size(); ++y) {
-                        const LoweredGate& l = gs[grp.second[y]];
-                        std::vector<int> need;
-                        if (local_bit(l.tq) < 0) need.push_back(l.tq);
-                        if (l.cq >= 0 && local_bit(l.cq) < 0) need.push_back(l.cq);
-                        std::vector<int> merged = qs;
-                        for (int qq : need)
-                            if (std::find(merged.begin(), merged.end(), qq) == merged.end()) merged.push_back(qq);
-                        if ((int)merged.size() > kFsvPhaseBits) break;
-                        qs = merged;
-                    }
+                auto nonlocal = [&](const LoweredGate& l) {
+                    std::vector<int> v;
+                    if (local_bit(l.tq) < 0) v.push_back(wg_bit(l.tq));
+                    if (l.cq >= 0 && local_bit(l.cq) < 0) v.push_back(wg_bit(l.cq));
+                    return v;
+                };
+                std::vector<int> bits;
+                for (size_t q : grp.second)
+                    for (int bb : nonlocal(gs[q])) bits.push_back(bb);
+                std::sort(bits.begin(), bits.end());
+                bits.erase(std::unique(bits.begin(), bits.end()), bits.end());
+                std::vector<std::pair<int, int>> wins;  // [lo, hi] over workgroup-number bits
+                for (size_t i = 0; i < bits.size();) {
+                    size_t j = i;
+                    while (j + 1 < bits.size() && bits[j + 1] - bits[i] < kFsvPhaseBits) ++j;
+                    wins.push_back({bits[i], bits[j]});
+                    i = j + 1;
+                }
+                std::vector<std::vector<size_t>> in_win(wins.size());
+                for (size_t q : grp.second) {
+                    const std::vector<int> v = nonlocal(gs[q]);
+                    size_t w = 0;
+                    while (w < wins.size() && !(v[0] >= wins[w].first && v[0] <= wins[w].second)) ++w;
+                    bool fits = true;
+                    for (int bb : v) fits = fits && bb >= wins[w].first && bb <= wins[w].second;
+                    if (fits)
+                        in_win[w].push_back(q);
+                    else
+                        table.push_back(record(gs[q]));  // two non-local qubits in different windows
+                }
+                std::vector<size_t> used;
+                for (size_t w = 0; w < wins.size(); ++w)
+                    if (!in_win[w].empty()) used.push_back(w);
+                for (size_t r0 = 0; r0 < used.size(); r0 += kFsvPhaseWindows) {
                     FsvGate d{};
                     d.kind = FSV_PHASE;
                     d.tloc = a;
                     d.tglob = 0;
-                    for (size_t b = 0; b < qs.size(); ++b) d.tglob |= qs[b] << (6 * b);
                     d.cloc = d.cglob = -1;
-                    d.width = (int)qs.size();
+                    d.width = 0;
                     d.moff = (int)pool.size();
-                    for (int idx = 0; idx < (1 << qs.size()); ++idx) {
-                        auto bit_of = [&](int q) {
-                            const size_t b = std::find(qs.begin(), qs.end(), q) - qs.begin();
-                            return (idx >> b) & 1;
-                        };
-                        double u0r = 1.0, u0i = 0.0, u1r = 1.0, u1i = 0.0;  // diag(u0, u1) on bit a
-                        auto mul = [](double& xr, double& xi, double fr, double fi) {
-                            const double t = xr * fr - xi * fi;
-                            xi = xr * fi + xi * fr;
-                            xr = t;
-                        };
-                        for (size_t z = x; z < y; ++z) {
-                            const LoweredGate& l = gs[grp.second[z]];
-                            const double d0r = l.md[0], d0i = l.md[1], d1r = l.md[6], d1i = l.md[7];
-                            const bool tl = local_bit(l.tq) >= 0;
-                            if (tl) {  // local target, non-local control: diag(d0, d1) where the control is 1
-                                if (bit_of(l.cq)) {
-                                    mul(u0r, u0i, d0r, d0i);
-                                    mul(u1r, u1i, d1r, d1i);
-                                }
-                            } else {
-                                const int tv = bit_of(l.tq);
-                                const double fr = tv ? d1r : d0r, fi = tv ? d1i : d0i;
-                                if (l.cq >= 0 && local_bit(l.cq) >= 0) {  // local control: factor where it is 1
-                                    mul(u1r, u1i, fr, fi);
-                                } else if (l.cq < 0 || bit_of(l.cq)) {  // no local qubit: one factor
-                                    mul(u0r, u0i, fr, fi);
-                                    mul(u1r, u1i, fr, fi);
+                    for (size_t r = r0; r < used.size() && r < r0 + kFsvPhaseWindows; ++r) {
+                        const int lo = wins[used[r]].first, w = wins[used[r]].second - lo + 1;
+                        d.tglob |= (lo | (w << 5)) << (10 * d.width);
+                        ++d.width;
+                        for (int idx = 0; idx < (1 << w); ++idx) {
+                            auto bit_of = [&](int q) { return (idx >> (wg_bit(q) - lo)) & 1; };
+                            double u0r = 1.0, u0i = 0.0, u1r = 1.0, u1i = 0.0;  // diag(u0, u1) on bit a
+                            auto mul = [](double& xr, double& xi, double fr, double fi) {
+                                const double t = xr * fr - xi * fi;
+                                xi = xr * fi + xi * fr;
+                                xr = t;
+                            };
+                            for (size_t q : in_win[used[r]]) {
+                                const LoweredGate& l = gs[q];
+                                const double d0r = l.md[0], d0i = l.md[1], d1r = l.md[6], d1i = l.md[7];
+                                if (local_bit(l.tq) >= 0) {  // local target, non-local control: where it is 1
+                                    if (bit_of(l.cq)) {
+                                        mul(u0r, u0i, d0r, d0i);
+                                        mul(u1r, u1i, d1r, d1i);
+                                    }
+                                } else {
+                                    const int tv = bit_of(l.tq);
+                                    const double fr = tv ? d1r : d0r, fi = tv ? d1i : d0i;
+                                    if (l.cq >= 0 && local_bit(l.cq) >= 0) {  // local control: where it is 1
+                                        mul(u1r, u1i, fr, fi);
+                                    } else if (l.cq < 0 || bit_of(l.cq)) {  // no local qubit: one factor
+                                        mul(u0r, u0i, fr, fi);
+                                        mul(u1r, u1i, fr, fi);
+                                    }
                                 }
                             }
+                            pool.push_back((float)u0r);
+                            pool.push_back((float)u0i);
+                            pool.push_back((float)u1r);
+                            pool.push_back((float)u1i);
                         }
-                        pool.push_back((float)u0r);
-                        pool.push_back((float)u0i);
-                        pool.push_back((float)u1r);
-                        pool.push_back((float)u1i);
                     }
                     table.push_back(d);
-                    x = y;
                 }
             }
             k = e;
@@ -1663,8 +1702,12 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
                         bool d0 = !(d.m[0] == 1.f && d.m[1] == 0.f);
                         if (d.kind == FSV_PHASE) {
                             d0 = false;
-                            for (int e = 0; e < (1 << d.width); ++e)
-                                if (pool[d.moff + 4 * e] != 1.f || pool[d.moff + 4 * e + 1] != 0.f) d0 = true;
+                            int off = d.moff;
+                            for (int w = 0; w < d.width; ++w) {
+                                const int entries = 1 << ((d.tglob >> (10 * w + 5)) & 15);
+                                for (int e = 0; e < entries; ++e, off += 4)
+                                    if (pool[off] != 1.f || pool[off + 1] != 0.f) d0 = true;
+                            }
                         }
                         d.real = kDiagTP + (tp * 5 + cp + 1) * 2 + (d0 ? 1 : 0);
                     }

@@ -162,6 +162,52 @@ def test_fsv_qft_28_of_basis_state_is_the_dft_column(ctx):
     assert abs(B.qsim_fsv_norm2(ctx, n, psi) - 1.0) <= bound(g)
 
 
+def test_fsv_diagonals_then_qft_28_closed_form(ctx):
+    """Diagonal gates on a basis state only multiply it by a phase (the product of the diagonal entries its bits
+    select), and the QFT then gives that phase times the DFT column.  The 80 diagonals draw their qubits from the
+    whole register, so in a 12-qubit pass of 28 qubits many read non-local qubits spread over 16 workgroup-number
+    bits: grouped records with several table windows, for a local target, a local control and no local qubit.
+    The QFT's controlled phases are written with control and target exchanged (the gate is symmetric), so its
+    grouped records read a non-local target."""
+    from oracle import gates as OG
+    n, x = 28, 0b1011_0110_1110_0101_1010_0111_0110
+    N = 1 << n
+    rng = np.random.default_rng(2828)
+    diag, phase = [], 1.0 + 0.0j
+    bit = lambda q: (x >> q) & 1
+    for _ in range(80):
+        nm = str(rng.choice(["CR", "CZ", "T", "S", "RZ", "Z", "R"]))
+        th = float(rng.uniform(0, 2 * math.pi)) if nm in W.ANGLED else None
+        if nm in ("CR", "CZ"):
+            c, t = (int(v) for v in rng.choice(n, 2, replace=False))
+            diag.append((nm, (c, t), th))
+            if bit(c):
+                phase *= OG.controlled_target(nm, th)[bit(t), bit(t)]
+        else:
+            q = int(rng.integers(0, n))
+            diag.append((nm, (q,), th))
+            phase *= OG.one_qubit(nm, th)[bit(q), bit(q)]
+    qft = []
+    for j in range(n - 1, -1, -1):
+        qft.append(("H", (j,), None))
+        qft += [("CR", (j, i), math.pi / (1 << (j - i))) for i in range(j)]
+    qft += [("SWAP", (i, n - 1 - i), None) for i in range(n // 2)]
+    g = diag + qft
+    assert any(p[0] == 0 for p in B.qsim_fsv_schedule(n, g))
+    psi = torch.empty(2 * N, dtype=torch.float32, device=G.DEV)
+    B.qsim_fsv_init_basis(ctx, n, x, psi)
+    with B.FsvPlan(ctx, n, g) as plan:
+        plan.run(psi)
+        G.sync()
+    k = torch.arange(N, dtype=torch.int64, device=G.DEV)
+    ph = ((k * x) % N).double() * (2 * math.pi / N)
+    del k
+    c, s = torch.cos(ph) / math.sqrt(N), torch.sin(ph) / math.sqrt(N)
+    del ph
+    err = _err_vs(psi, c * phase.real - s * phase.imag, c * phase.imag + s * phase.real)
+    assert err <= bound(g), (err, bound(g))
+
+
 def test_fsv_mirror_28_returns_to_zero_state(ctx):
     n = 28
     c = W.mirror(W.random_layers(n, 4, np.random.default_rng(28)))
