@@ -37,6 +37,7 @@
 // Gate entries are the float64 matrices of the unitary path rounded once to
 // float32; amplitude arithmetic is float32 with fused multiply-adds.
 #include <algorithm>
+#include <complex>
 #include <set>
 #include <utility>
 #include <vector>
@@ -71,6 +72,10 @@ template <class F>
 __device__ __forceinline__ void fsv_for16(F&& f) {
     fsv_for16_impl(f, std::make_integer_sequence<int, 16>{});
 }
+template <class F>
+__device__ __forceinline__ void fsv_for4(F&& f) {
+    fsv_for16_impl(f, std::make_integer_sequence<int, 4>{});
+}
 
 enum : int32_t { FSV_GENERAL = 0, FSV_DIAG = 1, FSV_DENSE = 2, FSV_TABLE = 3, FSV_PHASE = 4, FSV_SWAP = 5 };
 constexpr int kFsvPhaseBits = 10;    // workgroup-number bits per FSV_PHASE window (up to 2^10 entries)
@@ -79,12 +84,14 @@ constexpr int kFsvPhaseWindows = 3;  // windows per FSV_PHASE record
 struct FsvGate {
     int32_t kind;
     int32_t tloc;   // local bit of the target (dense: of the range's lowest qubit), or -1 (diagonal only)
-    int32_t tglob;  // the target qubit when it is not local (phase: its windows, 10 bits each: lo | w << 5);
+    int32_t tglob;  // the target qubit when it is not local (phase: its windows, 10 bits each: lo | w << 5;
+                    // table: 1 when it has a per-thread factor P);
                     // general: planned actions before it (bit 0: apply the pending per-lane phase,
                     // bit 1: change to the target's register layout)
-    int32_t cloc;   // local bit of the control, or -1
+    int32_t cloc;   // local bit of the control, or -1 (table: the register bits with a per-thread factor W)
     int32_t cglob;  // a non-local control qubit, or -1
     int32_t width;  // dense: qubits in the range; phase: windows (tables) it multiplies;
+                    // table: the registers its uniform factors F apply to (bit mask);
                     // general: 1 + the lane bit its target occupies when it is applied across
                     // lanes in the current layout (0: its target is in the register group)
     int32_t moff;   // dense / table / phase: offset of its float32 data in the plan's pool
@@ -430,22 +437,6 @@ __device__ __forceinline__ void fsv_lane_op(f32x16& ar, f32x16& ai, const Mat2& 
         } else {
             fsv_axbp_c(xr, xi, pr, pi, c);
         }
-        ar[r] = xr;
-        ai[r] = xi;
-    });
-}
-
-// A run of diagonal operations on local qubits, multiplied out on the host:
-// amplitude j (local index) times tab[j].
-// (Each entry's address is a scalar base for the register bits plus the
-// thread's byte offset.)
-__device__ __forceinline__ void fsv_table(f32x16& ar, f32x16& ai, const float* __restrict__ tab, int jt, int sh) {
-    const uint32_t off8 = (uint32_t)jt << 3;
-    fsv_for16([&](auto I_) {
-        constexpr int r = decltype(I_)::value;
-        const float2 f = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(tab + 2 * (r << sh)) + off8);
-        float xr = ar[r], xi = ai[r];
-        fsv_cmul<true>(xr, xi, f.x, f.y);
         ar[r] = xr;
         ai[r] = xi;
     });
@@ -809,11 +800,40 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
             g.kind = FSV_DIAG;
             if (g.tloc < 0) g.tglob = 0;
         }
-        const int jt = fsv_thread_bits(t, cur);
         if (g.kind == FSV_TABLE) {
-            fsv_table(ar, ai, pool + g.moff, jt, 4 * cur);
+            // Factored diagonal (see the planner): F on the registers named in
+            // width, P (tglob bit 0) into the per-lane phase, then W_i on the
+            // registers with bit i set for each i in cloc; P and each W_i are
+            // tables of 256 entries read at the thread index.
+            const float* __restrict__ tb = pool + g.moff;
+            fsv_for16([&](auto I_) {
+                constexpr int r = decltype(I_)::value;
+                if ((g.width >> r) & 1) {
+                    float xr = ar[r], xi = ai[r];
+                    fsv_cmul<false>(xr, xi, tb[2 * r], tb[2 * r + 1]);
+                    ar[r] = xr;
+                    ai[r] = xi;
+                }
+            });
+            const float* __restrict__ tt = tb + 32 + 2 * t;
+            if (g.tglob & 1) {
+                const float2 f = *reinterpret_cast<const float2*>(tt);
+                const float nr = lpr * f.x - lpi * f.y;
+                lpi = lpr * f.y + lpi * f.x;
+                lpr = nr;
+                tt += 512;
+            }
+            fsv_for4([&](auto I_) {
+                constexpr int i = decltype(I_)::value;
+                if ((g.cloc >> i) & 1) {
+                    const float2 w = *reinterpret_cast<const float2*>(tt);
+                    tt += 512;
+                    fsv_scale<i>(ar, ai, w.x, w.y);
+                }
+            });
             continue;
         }
+        const int jt = fsv_thread_bits(t, cur);
         if (g.kind == FSV_DENSE) {  // only in WIDE passes
             if constexpr (WIDE) {
                 fsv_flush(ar, ai, lpr, lpi);
@@ -1399,6 +1419,7 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
             return -1;
         };
         p.g0 = (int)table.size();
+        std::vector<std::vector<size_t>> tab_ops;  // the operations of each FSV_TABLE record
         auto record = [&](const LoweredGate& l) {
             FsvGate d{};
             d.kind = l.kind;
@@ -1487,8 +1508,8 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
                 continue;
             }
             // A run of diagonal operations (they commute): those whose qubits
-            // are all local become one table of 4096 float64 products rounded
-            // once; the others stay individual records after it.
+            // are all local become one factored table (float64 products
+            // rounded once; see the layout planning below); the others follow.
             size_t e = k;
             while (e < order.size() && gs[order[e]].kind == FSV_DIAG) ++e;
             std::vector<size_t> local_ops, other_ops;
@@ -1498,28 +1519,13 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
                 (local ? local_ops : other_ops).push_back(q);
             }
             if (local_ops.size() >= 2) {
+                // its factors are laid out once the pass's register layout at
+                // this point is known (below)
                 FsvGate d{};
                 d.kind = FSV_TABLE;
                 d.tloc = d.tglob = d.cloc = d.cglob = -1;
-                d.moff = (int)pool.size();
-                const int nl = std::min(n, kFsvLocal);
-                for (int jj = 0; jj < (1 << kFsvLocal); ++jj) {
-                    double fr = 1.0, fi = 0.0;
-                    if (jj < (1 << nl)) {
-                        for (size_t q : local_ops) {
-                            const LoweredGate& l = gs[q];
-                            const int tb = local_bit(l.tq), cb = local_bit(l.cq);
-                            if (l.cq >= 0 && !((jj >> cb) & 1)) continue;
-                            const int bit = (jj >> tb) & 1;
-                            const double dr = bit ? l.md[6] : l.md[0], di = bit ? l.md[7] : l.md[1];
-                            const double nr = fr * dr - fi * di;
-                            fi = fr * di + fi * dr;
-                            fr = nr;
-                        }
-                    }
-                    pool.push_back((float)fr);
-                    pool.push_back((float)fi);
-                }
+                d.moff = (int)tab_ops.size();
+                tab_ops.push_back(local_ops);
                 table.push_back(d);
             } else {
                 for (size_t q : local_ops) other_ops.push_back(q);
@@ -1687,7 +1693,71 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
             bool dirty = false;
             for (int x = p.g0; x < p.g1; ++x) {
                 FsvGate& d = table[x];
-                if (d.kind == FSV_DIAG || d.kind == FSV_PHASE) {
+                if (d.kind == FSV_TABLE) {
+                    // A run of diagonal operations on local qubits, factored for
+                    // register layout c: every factor reads at most two bits, so
+                    //   D(r, t) = P(t) * F[r] * prod over set bits i of r of W_i(t)
+                    // (r: register index, t: thread index).  A factor on thread
+                    // bits only goes to P, on register bits only to F; one on
+                    // register bit i and thread bit k, f(b_i, b_k), gives
+                    // f(0, b_k) to P and f(1, b_k) / f(0, b_k) to W_i.  The
+                    // kernel reads one entry of P and of each W_i per thread, and
+                    // P joins the per-lane phase.
+                    using cd = std::complex<double>;
+                    std::vector<cd> F(16, 1.0), Pt(256, 1.0), Wt(4 * 256, 1.0);
+                    int wmask = 0;
+                    auto reg_of = [&](int lb) { return (lb >> 2) == c ? (lb & 3) : -1; };
+                    auto tbit_of = [&](int lb) { return lb < 4 * c ? lb : lb - 4; };
+                    for (size_t q : tab_ops[d.moff]) {
+                        const LoweredGate& l = gs[q];
+                        const int tb = local_bit(l.tq), cb = l.cq >= 0 ? local_bit(l.cq) : -1;
+                        const cd d0(l.md[0], l.md[1]), d1(l.md[6], l.md[7]);
+                        auto f = [&](int bc, int bt) { return (cb < 0 || bc) ? (bt ? d1 : d0) : cd(1.0); };
+                        const int tr = reg_of(tb), cr = cb >= 0 ? reg_of(cb) : -1;
+                        if (cb < 0) {
+                            if (tr >= 0)
+                                for (int r = 0; r < 16; ++r) F[r] *= f(1, (r >> tr) & 1);
+                            else
+                                for (int t = 0; t < 256; ++t) Pt[t] *= f(1, (t >> tbit_of(tb)) & 1);
+                        } else if (tr >= 0 && cr >= 0) {
+                            for (int r = 0; r < 16; ++r) F[r] *= f((r >> cr) & 1, (r >> tr) & 1);
+                        } else if (tr < 0 && cr < 0) {
+                            for (int t = 0; t < 256; ++t) Pt[t] *= f((t >> tbit_of(cb)) & 1, (t >> tbit_of(tb)) & 1);
+                        } else {
+                            const int i = tr >= 0 ? tr : cr, k = tr >= 0 ? tbit_of(cb) : tbit_of(tb);
+                            for (int t = 0; t < 256; ++t) {
+                                const int bk = (t >> k) & 1;
+                                const cd a = tr >= 0 ? f(bk, 0) : f(0, bk), b = tr >= 0 ? f(bk, 1) : f(1, bk);
+                                Pt[t] *= a;
+                                Wt[i * 256 + t] *= b / a;
+                            }
+                            wmask |= 1 << i;
+                        }
+                    }
+                    auto one = [](cd z) { return (float)z.real() == 1.f && (float)z.imag() == 0.f; };
+                    int fmask = 0;
+                    bool pt = false;
+                    for (int r = 0; r < 16; ++r) fmask |= one(F[r]) ? 0 : 1 << r;
+                    for (int t = 0; t < 256; ++t) pt = pt || !one(Pt[t]);
+                    d.moff = (int)pool.size();
+                    for (int r = 0; r < 16; ++r) {
+                        pool.push_back((float)F[r].real());
+                        pool.push_back((float)F[r].imag());
+                    }
+                    auto push256 = [&](const cd* v) {
+                        for (int t = 0; t < 256; ++t) {
+                            pool.push_back((float)v[t].real());
+                            pool.push_back((float)v[t].imag());
+                        }
+                    };
+                    if (pt) push256(Pt.data());
+                    for (int i = 0; i < 4; ++i)
+                        if ((wmask >> i) & 1) push256(Wt.data() + i * 256);
+                    d.width = fmask;
+                    d.tglob = pt ? 1 : 0;
+                    d.cloc = wmask;
+                    if (pt) dirty = true;
+                } else if (d.kind == FSV_DIAG || d.kind == FSV_PHASE) {
                     const int tp = d.tloc >= 0 && (d.tloc >> 2) == c ? d.tloc & 3 : -1;
                     const int cp = d.cloc >= 0 && (d.cloc >> 2) == c ? d.cloc & 3 : -1;
                     const int ts = d.tloc >= 0 ? 1 : 0;
