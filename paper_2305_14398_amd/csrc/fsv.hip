@@ -37,6 +37,7 @@
 // Gate entries are the float64 matrices of the unitary path rounded once to
 // float32; amplitude arithmetic is float32 with fused multiply-adds.
 #include <algorithm>
+#include <cmath>
 #include <complex>
 #include <set>
 #include <utility>
@@ -138,6 +139,7 @@ struct FsvPass {
     int32_t wide;            // the pass holds a dense operation (both planes staged in LDS)
     int32_t g0, g1;  // the pass's records in the plan's table
     int32_t op0, op1;  // the operations the pass covers
+    float scale;     // the product of the factors the pass's scaled forms take out
     int32_t perm;    // a permutation pass (disjoint SWAPs on any qubits), described by pm
     FsvPerm pm;
 };
@@ -291,6 +293,40 @@ __device__ __forceinline__ void fsv_cplx(float& x0r, float& x0i, float& x1r, flo
             : "s"(M.m0r), "s"(M.m0i), "s"(M.m1r), "s"(M.m1i), "s"(M.m2r), "s"(M.m2i), "s"(M.m3r), "s"(M.m3i));
 }
 
+// Scaled forms of three common real-coefficient 2x2s, for operations without a
+// control, which act on every amplitude: the scalar factor a that is taken out
+// multiplies the pass's scale, applied once when the pass stores (a factor
+// common to all amplitudes commutes with every operation).
+//   FSV_HADA  a [[1, 1], [1, -1]] (H):  x1' = x0 - x1,  x0' = fma(2, x0, -x1')  (= x0 + x1)
+//   FSV_ROTR  a [[1, -t], [t, 1]] (RY with |t| <= 1, k = 1 + t^2):
+//             x1' = fma(t, x0, x1),  x0' = fma(-t, x1', k x0)  (= x0 - t x1)
+//   FSV_ROTI  a [[1, -i t], [-i t, 1]] (RX with |t| <= 1), per plane as FSV_ROTR
+//             with the planes crossed:  x1r' = fma(t, x0i, x1r),  x1i' = fma(-t, x0r, x1i),
+//             x0r' = fma(t, x1i', k x0r),  x0i' = fma(-t, x1r', k x0i)
+enum : int32_t { FSV_HADA = 0, FSV_ROTR = 1, FSV_ROTI = 2 };
+__device__ __forceinline__ void fsv_hada(float& x0, float& x1) {
+    asm("v_sub_f32 %1, %0, %1\n\t"
+        "v_fma_f32 %0, 2.0, %0, -%1"
+        : "+v"(x0), "+v"(x1));
+}
+__device__ __forceinline__ void fsv_rotr(float& x0, float& x1, float k, float t) {
+    asm("v_fmac_f32 %1, %3, %0\n\t"
+        "v_mul_f32 %0, %2, %0\n\t"
+        "v_fma_f32 %0, -%3, %1, %0"
+        : "+v"(x0), "+v"(x1)
+        : "s"(k), "s"(t));
+}
+__device__ __forceinline__ void fsv_roti(float& x0r, float& x0i, float& x1r, float& x1i, float k, float t) {
+    asm("v_fmac_f32 %2, %5, %1\n\t"
+        "v_fma_f32 %3, -%5, %0, %3\n\t"
+        "v_mul_f32 %0, %4, %0\n\t"
+        "v_fmac_f32 %0, %5, %3\n\t"
+        "v_mul_f32 %1, %4, %1\n\t"
+        "v_fma_f32 %1, -%5, %2, %1"
+        : "+v"(x0r), "+v"(x0i), "+v"(x1r), "+v"(x1i)
+        : "s"(k), "s"(t));
+}
+
 // Exact exchanges: always, or in the lanes whose bit is set in a uniform mask.
 __device__ __forceinline__ void fsv_swap(float& x0, float& x1) { asm("v_swap_b32 %0, %1" : "+v"(x0), "+v"(x1)); }
 // Exact sign flip.
@@ -334,6 +370,31 @@ __device__ __forceinline__ void fsv_pairs(f32x16& ar, f32x16& ai, const Mat2& M)
                 fsv_neg(x1r);
             } else {
                 fsv_cplx<VC>(x0r, x0i, x1r, x1i, M);
+            }
+            ar[r0] = x0r;
+            ai[r0] = x0i;
+            ar[r1] = x1r;
+            ai[r1] = x1i;
+        }
+    });
+}
+
+// A scaled form (FSV_HADA .. FSV_ROTI) on register bit RB; k and t as above.
+template <int RB, int KIND>
+__device__ __forceinline__ void fsv_scaled_pairs(f32x16& ar, f32x16& ai, float k, float t) {
+    fsv_for16([&](auto I_) {
+        constexpr int r0 = decltype(I_)::value;
+        if constexpr (((r0 >> RB) & 1) == 0) {
+            constexpr int r1 = r0 | (1 << RB);
+            float x0r = ar[r0], x0i = ai[r0], x1r = ar[r1], x1i = ai[r1];
+            if constexpr (KIND == FSV_HADA) {
+                fsv_hada(x0r, x1r);
+                fsv_hada(x0i, x1i);
+            } else if constexpr (KIND == FSV_ROTR) {
+                fsv_rotr(x0r, x1r, k, t);
+                fsv_rotr(x0i, x1i, k, t);
+            } else {
+                fsv_roti(x0r, x0i, x1r, x1i, k, t);
             }
             ar[r0] = x0r;
             ai[r0] = x0i;
@@ -492,13 +553,15 @@ __device__ __forceinline__ void fsv_flush(f32x16& ar, f32x16& ai, float& lpr, fl
 //   kLeafLC   + fc * 4 + RB              control on a thread bit (fc: exchange, real, imaginary
 //                                        off-diagonal, complex)
 //   kLeafLane + fc * 6 + lane bit        target on a lane bit (fc: plain exchange, real, complex)
+//   kLeafScl  + kind * 4 + RB            no control, a scaled form (kind FSV_HADA .. FSV_ROTI;
+//                                        m[0] = k, m[1] = t)
 // Diagonal leaves (factors d0, d1 on the target's bit values):
 //   kDiagLP   + ts                       target and control off the register group: one factor
 //                                        per lane (ts: 0 the target is a workgroup bit, 1 a thread bit)
 //   kDiagCP   + ts * 4 + cp              control on register bit cp, target off the group
 //   kDiagTP   + (TP * 5 + cp + 1) * 2 + d0   target on register bit TP (cp -1: none or a thread bit);
 //                                        d0 = 0 when d0 is exactly 1
-constexpr int kLeafNC = 0, kLeafCP = 24, kLeafLC = 72, kLeafLane = 88, kLeafEnd = 106;
+constexpr int kLeafNC = 0, kLeafCP = 24, kLeafLC = 72, kLeafLane = 88, kLeafScl = 106, kLeafEnd = 118;
 constexpr int kDiagLP = 0, kDiagCP = 2, kDiagTP = 10, kDiagEnd = 50;
 
 template <int C>
@@ -531,6 +594,9 @@ __device__ __forceinline__ void fsv_general_leaf(f32x16& ar, f32x16& ai, const M
             constexpr int form = fc == 1 ? FSV_REAL : (fc == 2 ? FSV_IMAGOFF : FSV_COMPLEX);
             fsv_pairs<rb, -1, form, true>(ar, ai, L);
         }
+    } else if constexpr (C >= kLeafScl) {
+        constexpr int x = C - kLeafScl;
+        fsv_scaled_pairs<x % 4, x / 4>(ar, ai, M.m0r, M.m0i);
     } else {
         constexpr int x = C - kLeafLane, fc = x / 6, lb = x % 6;
         if constexpr (fc == 0) {
@@ -766,7 +832,8 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
             switch (g.real) {
                 FSV_GEN_LEAF8(0) FSV_GEN_LEAF8(8) FSV_GEN_LEAF8(16) FSV_GEN_LEAF8(24) FSV_GEN_LEAF8(32)
                 FSV_GEN_LEAF8(40) FSV_GEN_LEAF8(48) FSV_GEN_LEAF8(56) FSV_GEN_LEAF8(64) FSV_GEN_LEAF8(72)
-                FSV_GEN_LEAF8(80) FSV_GEN_LEAF8(88) FSV_GEN_LEAF8(96) FSV_GEN_LEAF2(104)
+                FSV_GEN_LEAF8(80) FSV_GEN_LEAF8(88) FSV_GEN_LEAF8(96) FSV_GEN_LEAF8(104) FSV_GEN_LEAF2(112)
+                FSV_GEN_LEAF2(114) FSV_GEN_LEAF2(116)
                 default: break;
             }
             continue;
@@ -855,6 +922,8 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
             default: break;
         }
     }
+    lpr *= p.scale;  // the factors the scaled forms took out
+    lpi *= p.scale;
     fsv_flush(ar, ai, lpr, lpi);
     if (cur != 2) fsv_relayout(ar, ai, t, cur, 2, s_buf);
 
@@ -1691,6 +1760,7 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
             // group) came since the last application.
             c = 2;
             bool dirty = false;
+            double scale = 1.0, growth = 1.0;
             for (int x = p.g0; x < p.g1; ++x) {
                 FsvGate& d = table[x];
                 if (d.kind == FSV_TABLE) {
@@ -1808,10 +1878,42 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
                         const int fc = form == FSV_XSWAP ? 0 : form == FSV_REAL ? 1 : form == FSV_IMAGOFF ? 2 : 3;
                         d.real = kLeafLC + fc * 4 + rb;
                     } else {
-                        d.real = kLeafNC + form * 4 + rb;
+                        // H, and RX / RY whose cosine is at least their sine in size,
+                        // take a scaled form when no control gates them (the
+                        // factor then multiplies every amplitude), while the
+                        // values' growth by the factors taken out stays below 2^32
+                        int kind = -1;
+                        double a = 1.0, tt = 0.0;
+                        const float* m = d.m;
+                        if (d.cglob < 0 && form == FSV_REAL) {
+                            if (m[0] == m[2] && m[0] == m[4] && m[6] == -m[0]) {
+                                kind = FSV_HADA;
+                                a = m[0];
+                            } else if (m[0] == m[6] && m[4] == -m[2] && std::fabs(m[2]) <= std::fabs(m[0])) {
+                                kind = FSV_ROTR;
+                                a = m[0];
+                                tt = -(double)m[2] / m[0];
+                            }
+                        } else if (d.cglob < 0 && form == FSV_IMAGOFF) {
+                            if (m[0] == m[6] && m[3] == m[5] && std::fabs(m[3]) <= std::fabs(m[0])) {
+                                kind = FSV_ROTI;
+                                a = m[0];
+                                tt = -(double)m[3] / m[0];
+                            }
+                        }
+                        if (kind >= 0 && a != 0.0 && growth / std::fabs(a) <= 4294967296.0) {
+                            growth /= std::fabs(a);
+                            scale *= a;
+                            d.real = kLeafScl + kind * 4 + rb;
+                            d.m[0] = (float)(1.0 + tt * tt);
+                            d.m[1] = (float)tt;
+                        } else {
+                            d.real = kLeafNC + form * 4 + rb;
+                        }
                     }
                 }
             }
+            p.scale = (float)scale;
         }
         p.wide = 0;
         for (int i = p.g0; i < p.g1; ++i)

@@ -383,6 +383,33 @@ def test_fsv_lane_operations_and_layout_runs(ctx, seed):
     assert np.linalg.norm(got - ref) <= bound(g), (np.linalg.norm(got - ref), bound(g), info)
 
 
+@pytest.mark.parametrize("n", [12, 14])
+def test_fsv_scaled_forms_and_their_growth_limit(ctx, n):
+    """H, RX and RY without a control run in a scaled form whose factor (1/sqrt 2 for H) the pass applies when it
+    stores.  160 such operations in one pass would grow the values by about 2^80, so past 2^32 the planner keeps
+    the unscaled forms: the state still matches route B within the rounding bound, and its norm stays 1.  Angles
+    near pi (sine above cosine) keep the unscaled form too."""
+    rng = np.random.default_rng(77 + n)
+    g = []
+    for i in range(160):
+        q = int(rng.integers(0, min(n, 12)))
+        kind = i % 5
+        if kind < 2:
+            g.append(("H", (q,), None))
+        elif kind == 2:
+            g.append(("RX", (q,), float(rng.uniform(-1.5, 1.5))))
+        elif kind == 3:
+            g.append(("RY", (q,), float(rng.uniform(2.0, 4.2))))  # |sin| > |cos| of the half angle: unscaled
+        else:
+            g.append(("CNOT", (q, (q + 1) % min(n, 12)), None))
+    assert len(B.qsim_fsv_schedule(n, g)) == 1
+    psi0 = W.random_state(n, 5 * n)
+    got, _ = run_fsv(ctx, n, g, psi0)
+    ref = fsv.final_state(n, g, psi0)
+    assert np.linalg.norm(got - ref) <= bound(g), (np.linalg.norm(got - ref), bound(g))
+    assert abs(np.linalg.norm(got) - 1.0) <= bound(g)
+
+
 def swap_layers(n, rng, layers):
     """Layers of pairwise disjoint SWAPs on random qubits (a layer of 1 to n/2 pairs)."""
     out = []
