@@ -530,7 +530,10 @@ typedef struct qsim_fsv_pass_info {
  * indices, pass by pass, and within a pass in the order its launch applies
  * them (operations on disjoint qubits, and diagonal ones, commute, so the
  * pass is reordered to need fewer register-layout changes; a run of diagonal
- * operations is applied as one multiplied-out table, in any order equal). */
+ * operations is applied as multiplied-out tables, in any order equal; an
+ * operation without a control may run in a scaled form whose scalar factor the
+ * pass applies when it stores).  A pass with permutation = 1 applies its
+ * SWAPs, pairwise disjoint, as one permutation of the state. */
 qsim_status qsim_fsv_schedule(int n_qubits, const qsim_gate* gates, int n_gates, qsim_fsv_pass_info* passes,
                               int capacity, int* n_passes, int32_t* order);
 /* Validates the gates, schedules them and uploads the operation table to the
