@@ -314,6 +314,18 @@ def test_fsv_ghz_34_maximum_size(ctx):
     B.qsim_fsv_sample(ctx, n, psi, u, 4096, out, ws)
     shots = out.cpu().numpy()
     assert set(np.unique(shots)) <= {0, N - 1}
+    # X on four qubits, then the reversal SWAP(q, 33 - q): the two amplitudes move to sigma(m) and its
+    # complement, through a permutation pass whose addresses need all 34 bits
+    m = (1 << 0) | (1 << 7) | (1 << 20) | (1 << 33)
+    g = [("X", (q,), None) for q in (0, 7, 20, 33)] + [("SWAP", (q, n - 1 - q), None) for q in range(n // 2)]
+    assert any(p[0] == 0 for p in B.qsim_fsv_schedule(n, g))
+    with B.FsvPlan(ctx, n, g) as plan:
+        plan.run(psi)
+        G.sync()
+    sm = sum(((m >> q) & 1) << (n - 1 - q) for q in range(n))
+    got = psi[torch.tensor([sm, (N - 1) ^ sm, N + sm], device=G.DEV)].cpu().numpy()
+    assert got[0] == ends[0] and got[1] == ends[1] and got[2] == 0
+    assert abs(B.qsim_fsv_norm2(ctx, n, psi) - 2 * float(ends[0]) * float(ends[0])) <= 1e-6
     del psi
     torch.cuda.empty_cache()
 
