@@ -140,6 +140,7 @@ struct FsvPass {
     int32_t g0, g1;  // the pass's records in the plan's table
     int32_t op0, op1;  // the operations the pass covers
     float scale;     // the product of the factors the pass's scaled forms take out
+    int32_t tail;    // at the end: 2 apply the pending per-lane phase and the scale, 1 the scale, 0 nothing
     int32_t perm;    // a permutation pass (disjoint SWAPs on any qubits), described by pm
     FsvPerm pm;
 };
@@ -503,6 +504,42 @@ __device__ __forceinline__ void fsv_lane_op(f32x16& ar, f32x16& ai, const Mat2& 
     });
 }
 
+// A scaled form (FSV_HADA .. FSV_ROTI, no control) applied across lanes on lane
+// bit B; each lane keeps its row with its own value's coefficient 1:
+//   FSV_HADA  y = fma(s, x, p), s = t (lane bit 0: x0 + x1) or -t (bit 1: x0 - x1), t = 1
+//             (read from the record: a constant select would be hoisted out of the
+//             operation loop and hold a register per lane bit)
+//   FSV_ROTR  y = fma(c, p, x), c = -t (bit 0) or t (bit 1)
+//   FSV_ROTI  yr = fma(t, pi, xr),  yi = fma(-t, pr, xi)  (the same in both lanes)
+template <int B, int KIND>
+__device__ __forceinline__ void fsv_lane_scaled(f32x16& ar, f32x16& ai, float t, int lane) {
+    const bool hi = (lane >> B) & 1;
+    const float c = KIND == FSV_HADA ? (hi ? -t : t) : (hi ? t : -t);
+    fsv_for16([&](auto I_) {
+        constexpr int r = decltype(I_)::value;
+        float xr = ar[r], xi = ai[r];
+        const float pr = fsv_partner<B>(xr, lane), pi = fsv_partner<B>(xi, lane);
+        if constexpr (KIND == FSV_HADA) {
+            asm("v_fma_f32 %0, %2, %0, %3\n\t"
+                "v_fma_f32 %1, %2, %1, %4"
+                : "+v"(xr), "+v"(xi)
+                : "v"(c), "v"(pr), "v"(pi));
+        } else if constexpr (KIND == FSV_ROTR) {
+            asm("v_fmac_f32 %0, %2, %3\n\t"
+                "v_fmac_f32 %1, %2, %4"
+                : "+v"(xr), "+v"(xi)
+                : "v"(c), "v"(pr), "v"(pi));
+        } else {
+            asm("v_fmac_f32 %0, %2, %3\n\t"
+                "v_fma_f32 %1, -%2, %4, %1"
+                : "+v"(xr), "+v"(xi)
+                : "s"(t), "v"(pi), "v"(pr));
+        }
+        ar[r] = xr;
+        ai[r] = xi;
+    });
+}
+
 // Registers whose bit P is set (or all, P < 0) times the per-lane factor f.
 template <int P>
 __device__ __forceinline__ void fsv_scale(f32x16& ar, f32x16& ai, float fr, float fi) {
@@ -555,13 +592,15 @@ __device__ __forceinline__ void fsv_flush(f32x16& ar, f32x16& ai, float& lpr, fl
 //   kLeafLane + fc * 6 + lane bit        target on a lane bit (fc: plain exchange, real, complex)
 //   kLeafScl  + kind * 4 + RB            no control, a scaled form (kind FSV_HADA .. FSV_ROTI;
 //                                        m[0] = k, m[1] = t)
+//   kLeafLaneScl + kind * 6 + lane bit   the same across lanes (m[1] = t)
 // Diagonal leaves (factors d0, d1 on the target's bit values):
 //   kDiagLP   + ts                       target and control off the register group: one factor
 //                                        per lane (ts: 0 the target is a workgroup bit, 1 a thread bit)
 //   kDiagCP   + ts * 4 + cp              control on register bit cp, target off the group
 //   kDiagTP   + (TP * 5 + cp + 1) * 2 + d0   target on register bit TP (cp -1: none or a thread bit);
 //                                        d0 = 0 when d0 is exactly 1
-constexpr int kLeafNC = 0, kLeafCP = 24, kLeafLC = 72, kLeafLane = 88, kLeafScl = 106, kLeafEnd = 118;
+constexpr int kLeafNC = 0, kLeafCP = 24, kLeafLC = 72, kLeafLane = 88, kLeafScl = 106, kLeafLaneScl = 118,
+              kLeafEnd = 136;
 constexpr int kDiagLP = 0, kDiagCP = 2, kDiagTP = 10, kDiagEnd = 50;
 
 template <int C>
@@ -594,6 +633,9 @@ __device__ __forceinline__ void fsv_general_leaf(f32x16& ar, f32x16& ai, const M
             constexpr int form = fc == 1 ? FSV_REAL : (fc == 2 ? FSV_IMAGOFF : FSV_COMPLEX);
             fsv_pairs<rb, -1, form, true>(ar, ai, L);
         }
+    } else if constexpr (C >= kLeafLaneScl) {
+        constexpr int x = C - kLeafLaneScl;
+        fsv_lane_scaled<x % 6, x / 6>(ar, ai, M.m0i, lane);
     } else if constexpr (C >= kLeafScl) {
         constexpr int x = C - kLeafScl;
         fsv_scaled_pairs<x % 4, x / 4>(ar, ai, M.m0r, M.m0i);
@@ -833,7 +875,7 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
                 FSV_GEN_LEAF8(0) FSV_GEN_LEAF8(8) FSV_GEN_LEAF8(16) FSV_GEN_LEAF8(24) FSV_GEN_LEAF8(32)
                 FSV_GEN_LEAF8(40) FSV_GEN_LEAF8(48) FSV_GEN_LEAF8(56) FSV_GEN_LEAF8(64) FSV_GEN_LEAF8(72)
                 FSV_GEN_LEAF8(80) FSV_GEN_LEAF8(88) FSV_GEN_LEAF8(96) FSV_GEN_LEAF8(104) FSV_GEN_LEAF2(112)
-                FSV_GEN_LEAF2(114) FSV_GEN_LEAF2(116)
+                FSV_GEN_LEAF2(114) FSV_GEN_LEAF2(116) FSV_GEN_LEAF2(118) FSV_GEN_LEAF8(120) FSV_GEN_LEAF8(128)
                 default: break;
             }
             continue;
@@ -922,9 +964,25 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
             default: break;
         }
     }
-    lpr *= p.scale;  // the factors the scaled forms took out
-    lpi *= p.scale;
-    fsv_flush(ar, ai, lpr, lpi);
+    // The factors the scaled forms took out, and the per-lane phase when one is
+    // still pending (the host knows which: tail 2 both, 1 the scale only).
+    if (p.tail == 2) {
+        lpr *= p.scale;
+        lpi *= p.scale;
+        fsv_flush(ar, ai, lpr, lpi);
+    } else if (p.tail == 1) {
+        const float sc = p.scale;
+        fsv_for16([&](auto I_) {
+            constexpr int r = decltype(I_)::value;
+            float xr = ar[r], xi = ai[r];
+            asm("v_mul_f32 %0, %2, %0\n\t"
+                "v_mul_f32 %1, %2, %1"
+                : "+v"(xr), "+v"(xi)
+                : "s"(sc));
+            ar[r] = xr;
+            ai[r] = xi;
+        });
+    }
     if (cur != 2) fsv_relayout(ar, ai, t, cur, 2, s_buf);
 
     fsv_for16([&](auto I_) {
@@ -1867,7 +1925,40 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
                     d.tglob = flags;
                     d.moff = 0;
                     const int rb = d.tloc & 3;
-                    if (d.width > 0) {
+                    // H, and RX / RY whose cosine is at least their sine in size,
+                    // take a scaled form when no control gates them (the factor
+                    // then multiplies every amplitude), while the values' growth
+                    // by the factors taken out stays below 2^32
+                    int kind = -1;
+                    double a = 1.0, tt = 0.0;
+                    if (d.cloc < 0 && d.cglob < 0) {
+                        const float* m = d.m;
+                        if (form == FSV_REAL) {
+                            if (m[0] == m[2] && m[0] == m[4] && m[6] == -m[0]) {
+                                kind = FSV_HADA;
+                                a = m[0];
+                                tt = 1.0;
+                            } else if (m[0] == m[6] && m[4] == -m[2] && std::fabs(m[2]) <= std::fabs(m[0])) {
+                                kind = FSV_ROTR;
+                                a = m[0];
+                                tt = -(double)m[2] / m[0];
+                            }
+                        } else if (form == FSV_IMAGOFF) {
+                            if (m[0] == m[6] && m[3] == m[5] && std::fabs(m[3]) <= std::fabs(m[0])) {
+                                kind = FSV_ROTI;
+                                a = m[0];
+                                tt = -(double)m[3] / m[0];
+                            }
+                        }
+                        if (kind >= 0 && (a == 0.0 || growth / std::fabs(a) > 4294967296.0)) kind = -1;
+                    }
+                    if (kind >= 0) {
+                        growth /= std::fabs(a);
+                        scale *= a;
+                        d.real = d.width > 0 ? kLeafLaneScl + kind * 6 + (d.width - 1) : kLeafScl + kind * 4 + rb;
+                        d.m[0] = (float)(1.0 + tt * tt);
+                        d.m[1] = (float)tt;
+                    } else if (d.width > 0) {
                         const int fc = (form == FSV_XSWAP && d.cloc < 0) ? 0
                                        : (form == FSV_REAL || form == FSV_XSWAP) ? 1 : 2;
                         d.real = kLeafLane + fc * 6 + (d.width - 1);
@@ -1878,42 +1969,12 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
                         const int fc = form == FSV_XSWAP ? 0 : form == FSV_REAL ? 1 : form == FSV_IMAGOFF ? 2 : 3;
                         d.real = kLeafLC + fc * 4 + rb;
                     } else {
-                        // H, and RX / RY whose cosine is at least their sine in size,
-                        // take a scaled form when no control gates them (the
-                        // factor then multiplies every amplitude), while the
-                        // values' growth by the factors taken out stays below 2^32
-                        int kind = -1;
-                        double a = 1.0, tt = 0.0;
-                        const float* m = d.m;
-                        if (d.cglob < 0 && form == FSV_REAL) {
-                            if (m[0] == m[2] && m[0] == m[4] && m[6] == -m[0]) {
-                                kind = FSV_HADA;
-                                a = m[0];
-                            } else if (m[0] == m[6] && m[4] == -m[2] && std::fabs(m[2]) <= std::fabs(m[0])) {
-                                kind = FSV_ROTR;
-                                a = m[0];
-                                tt = -(double)m[2] / m[0];
-                            }
-                        } else if (d.cglob < 0 && form == FSV_IMAGOFF) {
-                            if (m[0] == m[6] && m[3] == m[5] && std::fabs(m[3]) <= std::fabs(m[0])) {
-                                kind = FSV_ROTI;
-                                a = m[0];
-                                tt = -(double)m[3] / m[0];
-                            }
-                        }
-                        if (kind >= 0 && a != 0.0 && growth / std::fabs(a) <= 4294967296.0) {
-                            growth /= std::fabs(a);
-                            scale *= a;
-                            d.real = kLeafScl + kind * 4 + rb;
-                            d.m[0] = (float)(1.0 + tt * tt);
-                            d.m[1] = (float)tt;
-                        } else {
-                            d.real = kLeafNC + form * 4 + rb;
-                        }
+                        d.real = kLeafNC + form * 4 + rb;
                     }
                 }
             }
             p.scale = (float)scale;
+            p.tail = dirty ? 2 : (p.scale != 1.f ? 1 : 0);
         }
         p.wide = 0;
         for (int i = p.g0; i < p.g1; ++i)
