@@ -114,9 +114,10 @@ enum : int32_t { FSV_COMPLEX = 0, FSV_REAL = 1, FSV_XSWAP = 2, FSV_ANTI = 3, FSV
 // A pass of pairwise disjoint SWAPs is one permutation sigma of qubit
 // positions (an involution): the amplitude at index i moves to sigma(i), the
 // index with its bits moved by sigma.  Positions 0-5 (a row of 64 contiguous
-// amplitudes) and the h positions that sigma exchanges with them form a tile of
-// 64 * 2^h amplitudes; the other positions name a group, and sigma maps group
-// g's tile onto group sigma(g)'s with the tile bits permuted.  One workgroup per
+// amplitudes), the positions that sigma exchanges with them and further whole
+// orbits of sigma, h positions above 5 in all, form a tile of 64 * 2^h
+// amplitudes (4 <= h <= 6); the other positions name a group, and sigma maps
+// group g's tile onto group sigma(g)'s with the tile bits permuted.  One workgroup per
 // pair {g, sigma(g)} reads both tiles (rows of 64 contiguous amplitudes), and
 // writes both through LDS in the permuted order, again in contiguous rows: one
 // read and one write of every amplitude, in place, with no workgroup writing
