@@ -395,7 +395,7 @@ def test_fsv_lane_operations_and_layout_runs(ctx, seed):
     assert np.linalg.norm(got - ref) <= bound(g), (np.linalg.norm(got - ref), bound(g), info)
 
 
-@pytest.mark.parametrize("n", [12, 14])
+@pytest.mark.parametrize("n", [7, 12, 14])
 def test_fsv_scaled_forms_and_their_growth_limit(ctx, n):
     """H, RX and RY without a control run in a scaled form whose factor (1/sqrt 2 for H) the pass applies when it
     stores.  160 such operations in one pass would grow the values by about 2^80, so past 2^32 the planner keeps
@@ -432,7 +432,7 @@ def swap_layers(n, rng, layers):
     return out
 
 
-@pytest.mark.parametrize("n,case", [(13, "random"), (14, "random"), (16, "random"), (20, "random"),
+@pytest.mark.parametrize("n,case", [(13, "random"), (14, "random"), (16, "random"), (20, "random"), (13, "reverse"),
                                     (16, "reverse"), (18, "low_only"), (18, "high_only"), (17, "low_high")])
 def test_fsv_permutation_passes_are_exact(ctx, n, case):
     """SWAP-only circuits run as permutation passes: the amplitudes move unchanged, so the result equals the
