@@ -52,6 +52,7 @@ constexpr int kFsvMinLow = 6;     // low qubits always local: 64 lanes x 4 B con
 constexpr int kFsvMaxHigh = kFsvLocal - kFsvMinLow;
 constexpr int kFsvNormBlocks = 1024;
 constexpr int kFsvMaxOps = 256;   // operations per pass (a planning cap)
+constexpr int kFsvSeeds = 16;      // alternative first operations tried when a pass is formed
 constexpr int kFsvLaneRun = 5;    // longest run of operations applied across lanes instead of a layout change
 
 // A thread's 16 values of one plane: 16 scalars (every index is a compile-time
@@ -1496,27 +1497,83 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
             }
         }
         FsvPass p{};
-        uint64_t T = 0;
-        int L = n <= kFsvLocal ? n : kFsvLocal;
-        std::vector<int> pass_ops;
-        for (auto it = ready.begin(); it != ready.end() && (int)pass_ops.size() < kFsvMaxOps;) {
-            const int b = *it;
-            const uint64_t T2 = T | local_need(gs[b]);
-            if (n > kFsvLocal) {
-                const int L2 = fit_low(T2);
-                if (L2 < 0) {
-                    ++it;
-                    continue;
+        // One sweep over the ready operations in circuit order, taking each one
+        // whose local qubits still fit (operations that become ready join the
+        // sweep); with seed >= 0 that operation goes first, so its qubits shape
+        // the pass.  Returns the operations taken and leaves rdy / indeg as
+        // after them (undo, when given, records the indegrees it changed).
+        auto sweep = [&](int seed, std::set<int>& rdy, std::vector<int>* undo, std::vector<int>& ops, uint64_t& T,
+                         int& L) {
+            T = 0;
+            L = n <= kFsvLocal ? n : kFsvLocal;
+            auto take = [&](int b) {
+                ops.push_back(b);
+                rdy.erase(b);
+                for (int c : succ_all[b]) {
+                    if (undo) undo->push_back(c);
+                    if (--indeg_all[c] == 0) rdy.insert(c);
                 }
-                L = L2;
+            };
+            if (seed >= 0) {
+                T = local_need(gs[seed]);
+                if (n > kFsvLocal) L = fit_low(T);
+                take(seed);
             }
-            T = T2;
-            pass_ops.push_back(b);
-            ready.erase(it);
-            for (int c : succ_all[b])
-                if (--indeg_all[c] == 0) ready.insert(c);
-            it = ready.upper_bound(b);  // successors (larger indices) join this sweep
+            for (auto it = rdy.begin(); it != rdy.end() && (int)ops.size() < kFsvMaxOps;) {
+                const int b = *it;
+                const uint64_t T2 = T | local_need(gs[b]);
+                if (n > kFsvLocal) {
+                    const int L2 = fit_low(T2);
+                    if (L2 < 0) {
+                        ++it;
+                        continue;
+                    }
+                    L = L2;
+                }
+                T = T2;
+                take(b);
+                it = rdy.upper_bound(b);  // successors (larger indices) join this sweep
+            }
+        };
+        // The plain sweep lets the earliest ready operations choose the local
+        // qubits; a sweep seeded with one of the next ready operations that
+        // needs a qubit above 5 may do better.  Each candidate is scored by the
+        // operations it takes plus those the plain sweep after it would take
+        // (one pass of look-ahead), and the best is kept (the plain sweep on
+        // ties).  20 random layers on 30 qubits: 23-26 passes instead of
+        // 25-30 over five seeds.
+        int best_seed = -1;
+        if (n > kFsvLocal) {
+            size_t best = 0;
+            std::vector<int> cand;
+            cand.push_back(-1);
+            for (int b : ready) {
+                if ((int)cand.size() > kFsvSeeds) break;
+                if (local_need(gs[b]) & ~(((uint64_t)1 << 6) - 1)) cand.push_back(b);
+            }
+            for (int seed : cand) {
+                std::set<int> rdy = ready;
+                std::vector<int> undo, ops;
+                uint64_t T0;
+                int L0;
+                sweep(seed, rdy, &undo, ops, T0, L0);
+                size_t score = ops.size();
+                {
+                    std::vector<int> ops2;
+                    sweep(-1, rdy, &undo, ops2, T0, L0);
+                    score += ops2.size();
+                }
+                for (int c : undo) ++indeg_all[c];
+                if (score > best) {
+                    best = score;
+                    best_seed = seed;
+                }
+            }
         }
+        uint64_t T = 0;
+        int L = 0;
+        std::vector<int> pass_ops;
+        sweep(best_seed, ready, nullptr, pass_ops, T, L);
         if (n <= kFsvLocal) {
             p.L = n;
             p.nh = 0;
