@@ -306,7 +306,12 @@ __device__ __forceinline__ void fsv_cplx(float& x0r, float& x0i, float& x1r, flo
 //   FSV_ROTI  a [[1, -i t], [-i t, 1]] (RX with |t| <= 1), per plane as FSV_ROTR
 //             with the planes crossed:  x1r' = fma(t, x0i, x1r),  x1i' = fma(-t, x0r, x1i),
 //             x0r' = fma(t, x1i', k x0r),  x0i' = fma(-t, x1r', k x0i)
-enum : int32_t { FSV_HADA = 0, FSV_ROTR = 1, FSV_ROTI = 2 };
+//   FSV_ROTR2 a [[k, -1], [1, k]] (RY whose sine is the larger, |k| < 1), with a temporary:
+//             y0 = fma(k, x0, -x1),  x1' = fma(k, x1, x0),  x0' = y0
+//   FSV_ROTI2 a [[k, i], [i, k]] (RX likewise):  y0r = fma(k, x0r, -x1i),  y0i = fma(k, x0i, x1r),
+//             x1r' = fma(k, x1r, -x0i),  x1i' = fma(k, x1i, x0r)
+//   (the last two on register bits only: across lanes they save nothing).
+enum : int32_t { FSV_HADA = 0, FSV_ROTR = 1, FSV_ROTI = 2, FSV_ROTR2 = 3, FSV_ROTI2 = 4 };
 __device__ __forceinline__ void fsv_hada(float& x0, float& x1) {
     asm("v_sub_f32 %1, %0, %1\n\t"
         "v_fma_f32 %0, 2.0, %0, -%1"
@@ -318,6 +323,25 @@ __device__ __forceinline__ void fsv_rotr(float& x0, float& x1, float k, float t)
         "v_fma_f32 %0, -%3, %1, %0"
         : "+v"(x0), "+v"(x1)
         : "s"(k), "s"(t));
+}
+__device__ __forceinline__ void fsv_rotr2(float& x0, float& x1, float k) {
+    float t;
+    asm("v_fma_f32 %2, %3, %0, -%1\n\t"
+        "v_fma_f32 %1, %3, %1, %0\n\t"
+        "v_mov_b32 %0, %2"
+        : "+v"(x0), "+v"(x1), "=&v"(t)
+        : "s"(k));
+}
+__device__ __forceinline__ void fsv_roti2(float& x0r, float& x0i, float& x1r, float& x1i, float k) {
+    float t0, t1;
+    asm("v_fma_f32 %4, %6, %0, -%3\n\t"
+        "v_fma_f32 %5, %6, %1, %2\n\t"
+        "v_fma_f32 %2, %6, %2, -%1\n\t"
+        "v_fma_f32 %3, %6, %3, %0\n\t"
+        "v_mov_b32 %0, %4\n\t"
+        "v_mov_b32 %1, %5"
+        : "+v"(x0r), "+v"(x0i), "+v"(x1r), "+v"(x1i), "=&v"(t0), "=&v"(t1)
+        : "s"(k));
 }
 __device__ __forceinline__ void fsv_roti(float& x0r, float& x0i, float& x1r, float& x1i, float k, float t) {
     asm("v_fmac_f32 %2, %5, %1\n\t"
@@ -396,8 +420,13 @@ __device__ __forceinline__ void fsv_scaled_pairs(f32x16& ar, f32x16& ai, float k
             } else if constexpr (KIND == FSV_ROTR) {
                 fsv_rotr(x0r, x1r, k, t);
                 fsv_rotr(x0i, x1i, k, t);
-            } else {
+            } else if constexpr (KIND == FSV_ROTI) {
                 fsv_roti(x0r, x0i, x1r, x1i, k, t);
+            } else if constexpr (KIND == FSV_ROTR2) {
+                fsv_rotr2(x0r, x1r, k);
+                fsv_rotr2(x0i, x1i, k);
+            } else {
+                fsv_roti2(x0r, x0i, x1r, x1i, k);
             }
             ar[r0] = x0r;
             ai[r0] = x0i;
@@ -592,17 +621,17 @@ __device__ __forceinline__ void fsv_flush(f32x16& ar, f32x16& ai, float& lpr, fl
 //   kLeafLC   + fc * 4 + RB              control on a thread bit (fc: exchange, real, imaginary
 //                                        off-diagonal, complex)
 //   kLeafLane + fc * 6 + lane bit        target on a lane bit (fc: plain exchange, real, complex)
-//   kLeafScl  + kind * 4 + RB            no control, a scaled form (kind FSV_HADA .. FSV_ROTI;
+//   kLeafScl  + kind * 4 + RB            no control, a scaled form (kind FSV_HADA .. FSV_ROTI2;
 //                                        m[0] = k, m[1] = t)
-//   kLeafLaneScl + kind * 6 + lane bit   the same across lanes (m[1] = t)
+//   kLeafLaneScl + kind * 6 + lane bit   the same across lanes (kind FSV_HADA .. FSV_ROTI; m[1] = t)
 // Diagonal leaves (factors d0, d1 on the target's bit values):
 //   kDiagLP   + ts                       target and control off the register group: one factor
 //                                        per lane (ts: 0 the target is a workgroup bit, 1 a thread bit)
 //   kDiagCP   + ts * 4 + cp              control on register bit cp, target off the group
 //   kDiagTP   + (TP * 5 + cp + 1) * 2 + d0   target on register bit TP (cp -1: none or a thread bit);
 //                                        d0 = 0 when d0 is exactly 1
-constexpr int kLeafNC = 0, kLeafCP = 24, kLeafLC = 72, kLeafLane = 88, kLeafScl = 106, kLeafLaneScl = 118,
-              kLeafEnd = 136;
+constexpr int kLeafNC = 0, kLeafCP = 24, kLeafLC = 72, kLeafLane = 88, kLeafScl = 106, kLeafLaneScl = 126,
+              kLeafEnd = 144;
 constexpr int kDiagLP = 0, kDiagCP = 2, kDiagTP = 10, kDiagEnd = 50;
 
 template <int C>
@@ -878,6 +907,7 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
                 FSV_GEN_LEAF8(40) FSV_GEN_LEAF8(48) FSV_GEN_LEAF8(56) FSV_GEN_LEAF8(64) FSV_GEN_LEAF8(72)
                 FSV_GEN_LEAF8(80) FSV_GEN_LEAF8(88) FSV_GEN_LEAF8(96) FSV_GEN_LEAF8(104) FSV_GEN_LEAF2(112)
                 FSV_GEN_LEAF2(114) FSV_GEN_LEAF2(116) FSV_GEN_LEAF2(118) FSV_GEN_LEAF8(120) FSV_GEN_LEAF8(128)
+                FSV_GEN_LEAF8(136)
                 default: break;
             }
             continue;
@@ -1983,10 +2013,10 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
                     d.tglob = flags;
                     d.moff = 0;
                     const int rb = d.tloc & 3;
-                    // H, and RX / RY whose cosine is at least their sine in size,
-                    // take a scaled form when no control gates them (the factor
-                    // then multiplies every amplitude), while the values' growth
-                    // by the factors taken out stays below 2^32
+                    // H, RX and RY take a scaled form when no control gates them
+                    // (the factor then multiplies every amplitude), while the
+                    // values' growth by the factors taken out stays below 2^32;
+                    // RX / RY whose sine is the larger only on register bits
                     int kind = -1;
                     double a = 1.0, tt = 0.0;
                     if (d.cloc < 0 && d.cglob < 0) {
@@ -2000,12 +2030,20 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
                                 kind = FSV_ROTR;
                                 a = m[0];
                                 tt = -(double)m[2] / m[0];
+                            } else if (m[0] == m[6] && m[4] == -m[2] && d.width == 0) {
+                                kind = FSV_ROTR2;
+                                a = m[4];
+                                tt = (double)m[0] / m[4];
                             }
                         } else if (form == FSV_IMAGOFF) {
                             if (m[0] == m[6] && m[3] == m[5] && std::fabs(m[3]) <= std::fabs(m[0])) {
                                 kind = FSV_ROTI;
                                 a = m[0];
                                 tt = -(double)m[3] / m[0];
+                            } else if (m[0] == m[6] && m[3] == m[5] && d.width == 0) {
+                                kind = FSV_ROTI2;
+                                a = m[3];
+                                tt = (double)m[0] / m[3];
                             }
                         }
                         if (kind >= 0 && (a == 0.0 || growth / std::fabs(a) > 4294967296.0)) kind = -1;
@@ -2014,8 +2052,8 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
                         growth /= std::fabs(a);
                         scale *= a;
                         d.real = d.width > 0 ? kLeafLaneScl + kind * 6 + (d.width - 1) : kLeafScl + kind * 4 + rb;
-                        d.m[0] = (float)(1.0 + tt * tt);
-                        d.m[1] = (float)tt;
+                        d.m[0] = kind >= FSV_ROTR2 ? (float)tt : (float)(1.0 + tt * tt);
+                        d.m[1] = kind >= FSV_ROTR2 ? 0.f : (float)tt;
                     } else if (d.width > 0) {
                         const int fc = (form == FSV_XSWAP && d.cloc < 0) ? 0
                                        : (form == FSV_REAL || form == FSV_XSWAP) ? 1 : 2;

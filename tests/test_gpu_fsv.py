@@ -400,7 +400,8 @@ def test_fsv_scaled_forms_and_their_growth_limit(ctx, n):
     """H, RX and RY without a control run in a scaled form whose factor (1/sqrt 2 for H) the pass applies when it
     stores.  160 such operations in one pass would grow the values by about 2^80, so past 2^32 the planner keeps
     the unscaled forms: the state still matches route B within the rounding bound, and its norm stays 1.  Angles
-    near pi (sine above cosine) keep the unscaled form too."""
+    near pi (sine above cosine) take the second rotation forms on register bits and the unscaled form across
+    lanes."""
     rng = np.random.default_rng(77 + n)
     g = []
     for i in range(160):
@@ -409,7 +410,7 @@ def test_fsv_scaled_forms_and_their_growth_limit(ctx, n):
         if kind < 2:
             g.append(("H", (q,), None))
         elif kind == 2:
-            g.append(("RX", (q,), float(rng.uniform(-1.5, 1.5))))
+            g.append(("RX", (q,), float(rng.uniform(-1.5, 1.5) if i % 2 else rng.uniform(2.0, 4.2))))
         elif kind == 3:
             g.append(("RY", (q,), float(rng.uniform(2.0, 4.2))))  # |sin| > |cos| of the half angle: unscaled
         else:
