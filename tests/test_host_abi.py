@@ -346,6 +346,33 @@ def test_fsv_schedule_permutation_passes():
     assert all(p[0] != 0 for p in _check_schedule(12, W.gate_tuples(W.qft(12))))
 
 
+def test_fsv_schedule_random_circuits_with_swap_layers():
+    """The planner's invariants on random circuits of every gate kind with bursts of disjoint SWAPs, 13 to 30
+    qubits: every gate once, dependency order kept, every target local to its pass, permutation passes made of
+    disjoint SWAPs only (the seeded sweeps and the permutation passes are host logic, checked here on the CPU)."""
+    rng = np.random.default_rng(2024)
+    one = ("H", "X", "Y", "Z", "S", "T", "R", "RX", "RY", "RZ")
+    two = ("CNOT", "CY", "CZ", "CR", "SWAP")
+    perms = 0
+    for _ in range(40):
+        n = int(rng.integers(13, 31))
+        g = []
+        for _ in range(int(rng.integers(1, 100))):
+            r = rng.random()
+            if r < 0.15:
+                qs = [int(x) for x in rng.permutation(n)]
+                g += [("SWAP", (qs[2 * i], qs[2 * i + 1]), None) for i in range(int(rng.integers(1, n // 2 + 1)))]
+            elif r < 0.55:
+                nm = two[int(rng.integers(0, len(two)))]
+                a, b = (int(x) for x in rng.choice(n, 2, replace=False))
+                g.append((nm, (a, b), float(rng.uniform(0, 2 * math.pi)) if nm in W.ANGLED else None))
+            else:
+                nm = one[int(rng.integers(0, len(one)))]
+                g.append((nm, (int(rng.integers(0, n)),), float(rng.uniform(0, 2 * math.pi)) if nm in W.ANGLED else None))
+        perms += sum(1 for p in _check_schedule(n, g) if p[0] == 0)
+    assert perms > 0
+
+
 def test_fsv_schedule_counts():
     # all targets inside 12 qubits: one pass; diagonal gates never split a pass
     assert len(B.qsim_fsv_schedule(30, [("H", (q,), None) for q in range(12)])) == 1
