@@ -278,6 +278,31 @@ def test_fsv_custom_ops_match_route_b(ctx, n):
     assert np.linalg.norm(got - ref) <= custom_bound(g), (np.linalg.norm(got - ref), custom_bound(g))
 
 
+@pytest.mark.parametrize("n", [14, 17])
+def test_fsv_custom_ops_with_swap_layers_and_scaled_forms(ctx, n):
+    """Custom operations (passes with a dense operation, the 32 KiB instantiation) among uncontrolled H, RX and RY
+    (scaled forms, on both sides of the sine/cosine divide) and layers of disjoint SWAPs over the whole register
+    (permutation passes), against route B."""
+    from tests.custom_ops import lib_gates
+    rng = np.random.default_rng(3100 + n)
+    g = []
+    for layer in range(3):
+        g += W.gate_tuples(W.random_layers(n, 1, rng))
+        g += [(("H", "RX", "RY")[int(rng.integers(0, 3))], (q,), None) for q in range(n)]
+        g = [(nm, qs, float(rng.uniform(0, 2 * math.pi)) if nm in W.ANGLED and th is None else th)
+             for nm, qs, th in g]
+        qs = [int(x) for x in rng.permutation(n)]
+        g += [("SWAP", (qs[2 * i], qs[2 * i + 1]), None) for i in range(n // 2)]
+    g = W.with_custom_ops(g, n, [1, 2, 3, 5], 900 + n)
+    g += [("SWAP", (q, n - 1 - q), None) for q in range(n // 2)]  # a closing reversal: one permutation pass
+    sched = B.qsim_fsv_schedule(n, lib_gates(g))
+    assert sched[-1][0] == 0
+    psi0 = W.random_state(n, 6 * n)
+    got, _ = run_fsv(ctx, n, lib_gates(g), psi0)
+    ref = fsv.final_state(n, g, psi0)
+    assert np.linalg.norm(got - ref) <= custom_bound(g), (np.linalg.norm(got - ref), custom_bound(g))
+
+
 def test_fsv_custom_dft_on_high_qubits_equals_qft_gates(ctx):
     """The 4-qubit DFT registered as one operation on qubits 20..23 of a 24-qubit state equals the
     QFT gates on those qubits (both on the GPU, compared with the bound of each)."""
