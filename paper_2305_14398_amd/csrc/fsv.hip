@@ -535,6 +535,23 @@ __device__ __forceinline__ void fsv_lane_op(f32x16& ar, f32x16& ai, const Mat2& 
     });
 }
 
+// An exchange across lanes on lane bit B in the lanes set in mask `on` (a
+// control on a thread bit): one select per value after the partner exchange.
+template <int B>
+__device__ __forceinline__ void fsv_lane_cswap(f32x16& ar, f32x16& ai, uint64_t on, int lane) {
+    fsv_for16([&](auto I_) {
+        constexpr int r = decltype(I_)::value;
+        float xr = ar[r], xi = ai[r];
+        const float pr = fsv_partner<B>(xr, lane), pi = fsv_partner<B>(xi, lane);
+        asm("v_cndmask_b32_e64 %0, %0, %2, %4\n\t"
+            "v_cndmask_b32_e64 %1, %1, %3, %4"
+            : "+v"(xr), "+v"(xi)
+            : "v"(pr), "v"(pi), "s"(on));
+        ar[r] = xr;
+        ai[r] = xi;
+    });
+}
+
 // A scaled form (FSV_HADA .. FSV_ROTI, no control) applied across lanes on lane
 // bit B; each lane keeps its row with its own value's coefficient 1:
 //   FSV_HADA  y = fma(s, x, p), s = t (lane bit 0: x0 + x1) or -t (bit 1: x0 - x1), t = 1
@@ -620,7 +637,8 @@ __device__ __forceinline__ void fsv_flush(f32x16& ar, f32x16& ai, float& lpr, fl
 //   kLeafCP   + fc * 16 + RB * 4 + cp    control on register bit cp (fc: exchange, real, complex)
 //   kLeafLC   + fc * 4 + RB              control on a thread bit (fc: exchange, real, imaginary
 //                                        off-diagonal, complex)
-//   kLeafLane + fc * 6 + lane bit        target on a lane bit (fc: plain exchange, real, complex)
+//   kLeafLane + fc * 6 + lane bit        target on a lane bit (fc: plain exchange, real, complex,
+//                                        exchange under a thread-bit control)
 //   kLeafScl  + kind * 4 + RB            no control, a scaled form (kind FSV_HADA .. FSV_ROTI2;
 //                                        m[0] = k, m[1] = t)
 //   kLeafLaneScl + kind * 6 + lane bit   the same across lanes (kind FSV_HADA .. FSV_ROTI; m[1] = t)
@@ -630,8 +648,8 @@ __device__ __forceinline__ void fsv_flush(f32x16& ar, f32x16& ai, float& lpr, fl
 //   kDiagCP   + ts * 4 + cp              control on register bit cp, target off the group
 //   kDiagTP   + (TP * 5 + cp + 1) * 2 + d0   target on register bit TP (cp -1: none or a thread bit);
 //                                        d0 = 0 when d0 is exactly 1
-constexpr int kLeafNC = 0, kLeafCP = 24, kLeafLC = 72, kLeafLane = 88, kLeafScl = 106, kLeafLaneScl = 126,
-              kLeafEnd = 144;
+constexpr int kLeafNC = 0, kLeafCP = 24, kLeafLC = 72, kLeafLane = 88, kLeafScl = 112, kLeafLaneScl = 132,
+              kLeafEnd = 150;
 constexpr int kDiagLP = 0, kDiagCP = 2, kDiagTP = 10, kDiagEnd = 50;
 
 template <int C>
@@ -674,6 +692,10 @@ __device__ __forceinline__ void fsv_general_leaf(f32x16& ar, f32x16& ai, const M
         constexpr int x = C - kLeafLane, fc = x / 6, lb = x % 6;
         if constexpr (fc == 0) {
             fsv_lane_op<lb, FSV_XSWAP>(ar, ai, M, lane);
+        } else if constexpr (fc == 3) {
+            // the lanes whose control bit is set take their partner's value
+            const uint64_t on = __builtin_amdgcn_ballot_w64(((jt >> cloc) & 1) != 0);
+            fsv_lane_cswap<lb>(ar, ai, on, lane);
         } else {
             const bool hi = (lane >> lb) & 1;  // this lane holds index bit 1 of the pair
             const bool on = cloc < 0 || ((jt >> cloc) & 1);
@@ -907,7 +929,7 @@ __global__ __launch_bounds__(256) void fsv_pass_kernel(int n, FsvPass p, const F
                 FSV_GEN_LEAF8(40) FSV_GEN_LEAF8(48) FSV_GEN_LEAF8(56) FSV_GEN_LEAF8(64) FSV_GEN_LEAF8(72)
                 FSV_GEN_LEAF8(80) FSV_GEN_LEAF8(88) FSV_GEN_LEAF8(96) FSV_GEN_LEAF8(104) FSV_GEN_LEAF2(112)
                 FSV_GEN_LEAF2(114) FSV_GEN_LEAF2(116) FSV_GEN_LEAF2(118) FSV_GEN_LEAF8(120) FSV_GEN_LEAF8(128)
-                FSV_GEN_LEAF8(136)
+                FSV_GEN_LEAF8(136) FSV_GEN_LEAF2(144) FSV_GEN_LEAF2(146) FSV_GEN_LEAF2(148)
                 default: break;
             }
             continue;
@@ -2055,8 +2077,7 @@ void fsv_schedule(int n, const std::vector<LoweredGate>& gs, std::vector<FsvPass
                         d.m[0] = kind >= FSV_ROTR2 ? (float)tt : (float)(1.0 + tt * tt);
                         d.m[1] = kind >= FSV_ROTR2 ? 0.f : (float)tt;
                     } else if (d.width > 0) {
-                        const int fc = (form == FSV_XSWAP && d.cloc < 0) ? 0
-                                       : (form == FSV_REAL || form == FSV_XSWAP) ? 1 : 2;
+                        const int fc = form == FSV_XSWAP ? (d.cloc < 0 ? 0 : 3) : form == FSV_REAL ? 1 : 2;
                         d.real = kLeafLane + fc * 6 + (d.width - 1);
                     } else if (d.cloc >= 0 && (d.cloc >> 2) == c) {
                         const int fc = form == FSV_XSWAP ? 0 : (form == FSV_REAL ? 1 : 2);
