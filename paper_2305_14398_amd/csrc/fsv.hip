@@ -296,10 +296,10 @@ __device__ __forceinline__ void fsv_cplx(float& x0r, float& x0i, float& x1r, flo
             : "s"(M.m0r), "s"(M.m0i), "s"(M.m1r), "s"(M.m1i), "s"(M.m2r), "s"(M.m2i), "s"(M.m3r), "s"(M.m3i));
 }
 
-// Scaled forms of three common real-coefficient 2x2s, for operations without a
-// control, which act on every amplitude: the scalar factor a that is taken out
-// multiplies the pass's scale, applied once when the pass stores (a factor
-// common to all amplitudes commutes with every operation).
+// Scaled forms of common 2x2s, for operations without a control, which act on
+// every amplitude: the real factor a that is taken out multiplies the pass's
+// scale, applied once when the pass stores (a factor common to all amplitudes
+// commutes with every operation).
 //   FSV_HADA  a [[1, 1], [1, -1]] (H):  x1' = x0 - x1,  x0' = fma(2, x0, -x1')  (= x0 + x1)
 //   FSV_ROTR  a [[1, -t], [t, 1]] (RY with |t| <= 1, k = 1 + t^2):
 //             x1' = fma(t, x0, x1),  x0' = fma(-t, x1', k x0)  (= x0 - t x1)
@@ -406,7 +406,7 @@ __device__ __forceinline__ void fsv_pairs(f32x16& ar, f32x16& ai, const Mat2& M)
     });
 }
 
-// A scaled form (FSV_HADA .. FSV_ROTI) on register bit RB; k and t as above.
+// A scaled form (FSV_HADA .. FSV_ROTI2) on register bit RB; k and t as above.
 template <int RB, int KIND>
 __device__ __forceinline__ void fsv_scaled_pairs(f32x16& ar, f32x16& ai, float k, float t) {
     fsv_for16([&](auto I_) {
